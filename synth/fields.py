@@ -1,0 +1,158 @@
+"""Seeded gauge fields and pseudofermion sources.
+
+Conventions (shared by every consumer, so they are fixed here once):
+
+* A lattice is ``L = (Lx, Ly, Lz, Lt)``; every extent is even.  Time is the
+  fourth direction.
+* Host gauge layout (canonical): ``complex128[Lt][Lz][Ly][Lx][mu][row][col]``
+  with ``mu = 0..3`` for x, y, z, t, i.e. the site index is lexicographic with
+  x running fastest.
+* Even-site colour vectors are ``complex128[nrhs][3][V/2]``: colour-major,
+  and within a colour the even sites in "eo" order, where
+  ``eo = lex >> 1`` and ``lex = x + Lx*(y + Ly*(z + Lz*t))``.
+
+Link generator (the paper's momentum distribution, Sec. 2.1): each link is
+``U = exp(i*eps*H)`` with ``H = sum_a omega^a T^a``, ``T^a = lambda^a/2`` the
+Gell-Mann generators and ``omega^a ~ N(0, 1)``; the exponential is taken by an
+eigen-decomposition of ``H`` and the result is reunitarised in FP64 (first two
+rows Gram-Schmidt orthonormalised, third row the complex conjugate of their
+cross product), which makes ``det U = 1`` to rounding.  Random numbers are
+drawn from ``numpy.random.Generator(PCG64(seed))`` in the order
+site (lexicographic, x fastest) -> mu -> a = 1..8.
+
+Source generator (the heat-bath distribution ``exp(-R^dagger R)`` of the Phi
+algorithm, Sec. 2.1): real and imaginary parts ``N(0, 1/2)``, drawn per even
+site (eo order) -> colour -> (re, im); right-hand side ``k`` uses seed
+``seed + k``.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+# The five workloads: lattice, link roughness eps, quark mass m, number of
+# right-hand sides, number of poles, exponent p of x^p, solver tolerance and
+# arithmetic mode.  The rational interval is [m^2, 16 + m^2] for all of them
+# (the spectrum of M^dagger M on even sites lies there because ||D|| <= 4).
+CONFIGS = {
+    1: dict(L=(4, 4, 4, 4), eps=0.5, m=0.1, nrhs=1, npole=8, powers=(-0.25,),
+            tol=1e-12, mode="fp64"),
+    2: dict(L=(16, 16, 16, 4), eps=0.5, m=0.02, nrhs=1, npole=15,
+            powers=(-0.25, 0.25), tol=1e-10, mode="fp64"),
+    3: dict(L=(32, 32, 32, 8), eps=0.7, m=0.01, nrhs=1, npole=15,
+            powers=(-0.25,), tol=1e-10, mode="mixed"),
+    4: dict(L=(32, 32, 32, 8), eps=0.7, m=0.01, nrhs=8, npole=15,
+            powers=(-0.25,), tol=1e-10, mode="mixed"),
+    5: dict(L=(48, 48, 48, 12), eps=0.8, m=0.005, nrhs=4, npole=20,
+            powers=(-0.25,), tol=1e-10, mode="mixed"),
+}
+
+
+def seed_gauge(cfg: int) -> int:
+    return 1000 + cfg
+
+
+def seed_source(cfg: int) -> int:
+    return 2000 + 100 * cfg
+
+
+def volume(L) -> int:
+    return int(L[0]) * int(L[1]) * int(L[2]) * int(L[3])
+
+
+def even_volume(L) -> int:
+    return volume(L) // 2
+
+
+def _check_dims(L):
+    if len(L) != 4 or any(int(l) < 2 or int(l) % 2 for l in L):
+        raise ValueError(f"lattice extents must be four even numbers >= 2, got {L}")
+
+
+def _gell_mann_generators() -> np.ndarray:
+    """T^a = lambda^a / 2, a = 1..8, as complex128[8][3][3]."""
+    lam = np.zeros((8, 3, 3), dtype=np.complex128)
+    lam[0][0, 1] = lam[0][1, 0] = 1
+    lam[1][0, 1] = -1j
+    lam[1][1, 0] = 1j
+    lam[2][0, 0], lam[2][1, 1] = 1, -1
+    lam[3][0, 2] = lam[3][2, 0] = 1
+    lam[4][0, 2] = -1j
+    lam[4][2, 0] = 1j
+    lam[5][1, 2] = lam[5][2, 1] = 1
+    lam[6][1, 2] = -1j
+    lam[6][2, 1] = 1j
+    lam[7][0, 0] = lam[7][1, 1] = 1 / np.sqrt(3)
+    lam[7][2, 2] = -2 / np.sqrt(3)
+    return lam / 2
+
+
+def _reunitarize(u: np.ndarray) -> np.ndarray:
+    """Gram-Schmidt on rows 0 and 1, row 2 = conj(row0 x row1)."""
+    r0 = u[..., 0, :]
+    r0 = r0 / np.linalg.norm(r0, axis=-1, keepdims=True)
+    r1 = u[..., 1, :]
+    r1 = r1 - np.sum(np.conj(r0) * r1, axis=-1, keepdims=True) * r0
+    r1 = r1 / np.linalg.norm(r1, axis=-1, keepdims=True)
+    r2 = np.conj(np.cross(r0, r1))
+    return np.stack([r0, r1, r2], axis=-2)
+
+
+def _exp_i_eps_h(omega: np.ndarray, eps: float) -> np.ndarray:
+    """exp(i*eps*H) for H = sum_a omega^a T^a, batched over leading axes."""
+    T = _gell_mann_generators()
+    H = np.einsum("...a,aij->...ij", omega, T)
+    w, V = np.linalg.eigh(H)
+    ph = np.exp(1j * eps * w)
+    U = np.einsum("...ik,...k,...jk->...ij", V, ph, np.conj(V))
+    return _reunitarize(U)
+
+
+def random_su3(shape, rng: np.random.Generator, eps: float) -> np.ndarray:
+    """SU(3) matrices exp(i*eps*H) with Gaussian algebra components."""
+    omega = rng.standard_normal(tuple(shape) + (8,))
+    return _exp_i_eps_h(omega, eps)
+
+
+def gauge_field(L, eps: float, seed: int, chunk: int = 1 << 18) -> np.ndarray:
+    """Seeded gauge field, complex128[Lt][Lz][Ly][Lx][4][3][3]."""
+    _check_dims(L)
+    Lx, Ly, Lz, Lt = (int(l) for l in L)
+    V = Lx * Ly * Lz * Lt
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = np.empty((V, 4, 3, 3), dtype=np.complex128)
+    # draw in chunks of sites; the generator is consumed in the same order
+    # as one draw of shape (V, 4, 8)
+    for s0 in range(0, V, chunk):
+        s1 = min(V, s0 + chunk)
+        omega = rng.standard_normal((s1 - s0, 4, 8))
+        out[s0:s1] = _exp_i_eps_h(omega, eps)
+    return out.reshape(Lt, Lz, Ly, Lx, 4, 3, 3)
+
+
+def unit_gauge(L) -> np.ndarray:
+    _check_dims(L)
+    Lx, Ly, Lz, Lt = (int(l) for l in L)
+    U = np.zeros((Lt, Lz, Ly, Lx, 4, 3, 3), dtype=np.complex128)
+    U[..., 0, 0] = U[..., 1, 1] = U[..., 2, 2] = 1
+    return U
+
+
+def source(L, seed: int, nrhs: int = 1) -> np.ndarray:
+    """Gaussian even-site sources, complex128[nrhs][3][V/2]."""
+    _check_dims(L)
+    Vh = even_volume(L)
+    out = np.empty((nrhs, 3, Vh), dtype=np.complex128)
+    for k in range(nrhs):
+        rng = np.random.Generator(np.random.PCG64(seed + k))
+        g = rng.standard_normal((Vh, 3, 2)) * np.sqrt(0.5)
+        out[k] = (g[..., 0] + 1j * g[..., 1]).T
+    return out
+
+
+def config_inputs(cfg: int):
+    """(U, b, params) for one of the five named workloads."""
+    c = CONFIGS[cfg]
+    U = gauge_field(c["L"], c["eps"], seed_gauge(cfg))
+    b = source(c["L"], seed_source(cfg), c["nrhs"])
+    return U, b, c
