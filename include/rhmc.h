@@ -1,0 +1,177 @@
+/*
+ * rhmc.h -- C ABI of the MI355X staggered-fermion solver library (librhmc.so).
+ *
+ * The library computes the hot path of two-flavour staggered RHMC as stated in
+ * arXiv:1106.5673 ("QCD simulations with staggered fermions on GPUs"):
+ *
+ *   - the staggered hopping term D of Eq. (stag) with the phases
+ *     eta_mu(n) = (-1)^(n_x + ... + n_{mu-1}) (Sec. 2), split into its
+ *     even/odd blocks D_eo (odd -> even) and D_oe (even -> odd);
+ *   - A = M^dagger M restricted to even sites, A = m^2 - D_eo D_oe
+ *     (even/odd preconditioning, Sec. 2.1; M^dagger M of Eq. pseudofermions);
+ *   - the shifted systems (A + sigma_i) x_i = b of Eq. (shifted), all solved
+ *     from one Krylov space with a zero start (Sec. 4.3);
+ *   - r(A) b = alpha0 b + sum_i alpha_i (A + beta_i)^-1 b, the rational
+ *     approximation of the rooted power in Eq. (system_r) (Sec. 2.1).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Lattice  L = {Lx, Ly, Lz, Lt}, every extent even and >= 2; directions
+ *          mu = 0..3 are x, y, z, t.  Site (x,y,z,t) has lexicographic index
+ *          lex = x + Lx*(y + Ly*(z + Lz*t)), parity (x+y+z+t) mod 2 (0 = even)
+ *          and, within its parity, index eo = lex / 2.  V = Lx*Ly*Lz*Lt,
+ *          Vh = V/2.  Space is periodic; a hop across the time boundary is
+ *          multiplied by t_bc (-1: antiperiodic).
+ * Gauge    host complex128 [Lt][Lz][Ly][Lx][mu][row][col], (re, im)
+ *          interleaved, each link in SU(3) (det = 1; the 12-real compressed
+ *          copy reconstructs row 3 as conj(row1 x row2), Sec. 4.2).
+ * Vectors  device colour vectors of one parity, [nrhs][3][Vh] complex, i.e.
+ *          element (r, c, eo) at offset (r*3 + c)*Vh + eo; complex128
+ *          (double2) for RHMC_PREC_FP64, complex64 (float2) for RHMC_PREC_FP32.
+ *          Solver inputs and outputs are always complex128.
+ * Streams  every call is enqueued on the caller's hipStream_t (0 = default
+ *          stream).  rhmc_dslash_eo and rhmc_apply_mdagm are asynchronous;
+ *          rhmc_multishift_cg and rhmc_rational_apply return after the
+ *          solution and the statistics are complete.
+ * Memory   the caller owns every vector and host array passed in; the library
+ *          owns lattice and gauge objects, the packed links and a solver
+ *          workspace cached inside the gauge object (allocated on first use
+ *          for a given shape, freed by rhmc_gauge_destroy).
+ * Errors   every call returns rhmc_status; on failure rhmc_last_error() gives
+ *          a thread-local message.  Nothing aborts or throws across the ABI.
+ */
+#ifndef RHMC_H
+#define RHMC_H
+
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RHMC_OK = 0,
+    RHMC_ERR_INVALID_ARG = -1,   /* bad sizes, null pointers, odd extents, ... */
+    RHMC_ERR_NONFINITE = -2,     /* a source or result holds NaN or Inf */
+    RHMC_ERR_NOT_CONVERGED = -3, /* maxiter reached; outputs hold the last iterates */
+    RHMC_ERR_HIP = -4,           /* a HIP runtime call failed */
+    RHMC_ERR_OOM = -5,           /* device allocation failed */
+    RHMC_ERR_UNSUPPORTED = -6    /* valid request this build does not implement */
+} rhmc_status;
+
+typedef enum { RHMC_PREC_FP64 = 0, RHMC_PREC_FP32 = 1 } rhmc_prec;
+
+/* Link storage requested from rhmc_gauge_create (bit flags). */
+#define RHMC_LINKS_FP64_18 1u /* 18 doubles per link: FP64 operator */
+#define RHMC_LINKS_FP32_12 2u /* first two rows in FP32, third rebuilt: FP32 operator */
+
+typedef enum {
+    RHMC_MODE_FP64 = 0,  /* every operator application and vector in FP64 */
+    RHMC_MODE_MIXED = 1  /* FP32 operator and vectors, FP64 reliable updates */
+} rhmc_mode;
+
+typedef struct rhmc_lattice rhmc_lattice;
+typedef struct rhmc_gauge rhmc_gauge;
+
+typedef struct {
+    double tol;             /* per-shift relative residual ||b-(A+s)x||/||b|| (default 1e-10) */
+    int32_t maxiter;        /* Krylov iterations of the shared solve (default 100000) */
+    int32_t mode;           /* rhmc_mode */
+    int32_t reliable_every; /* MIXED: iterations between FP64 residual replacements (default 50) */
+    int32_t refine;         /* nonzero: shifts whose FP64 true residual exceeds tol get a
+                               warm-started CG on their own system (default 1) */
+    int32_t block;          /* iterations between updates of the shifted solutions (1..16,
+                               default 10; MIXED rounds reliable_every to a multiple) */
+    int32_t use_graph;      /* nonzero: replay each block of iterations as a hipGraph (default 1) */
+    int32_t poll_every;     /* blocks launched between convergence polls (0 = automatic) */
+    int32_t tune;           /* nonzero: time the Dslash launch shapes once and keep the best */
+} rhmc_solver_params;
+
+typedef struct {
+    /* caller-owned arrays of nrhs*nshift entries, index r*nshift + i; each may be NULL */
+    int32_t* iterations;     /* iteration at which shift i of rhs r met tol */
+    double* true_residual;   /* final ||b - (A+sigma)x|| / ||b|| in FP64 */
+    int32_t* refine_iterations;
+    /* scalars filled by the library */
+    int32_t total_iterations;   /* iterations of the shared Krylov solve */
+    int32_t reliable_updates;
+    int32_t refine_rounds;
+    double time_ms;             /* host wall time of the call */
+    double max_true_residual;
+} rhmc_solver_stats;
+
+typedef struct {
+    double alpha0;
+    int32_t npole;
+    const double* alpha; /* host [npole] */
+    const double* beta;  /* host [npole], each > 0 (or >= 0 with m > 0) */
+} rhmc_rational;
+
+/* Fills the documented defaults. */
+void rhmc_solver_params_default(rhmc_solver_params* p);
+
+/* Lattice geometry (Sec. 2): L = {Lx, Ly, Lz, Lt}, each even and >= 2, V <= 2^28.
+ * t_bc is +1 or -1.  *out must be released with rhmc_lattice_destroy. */
+rhmc_status rhmc_lattice_create(const int32_t L[4], int32_t t_bc, rhmc_lattice** out);
+void rhmc_lattice_destroy(rhmc_lattice* lat);
+
+/* Neighbour table as the device kernels compute it: for every site of the given
+ * parity, in eo order, the eo index of n+mu (columns 0..3) and n-mu (4..7).
+ * out: host int32 [Vh][8].  sign (nullable): host int32 [Vh][8], the factor
+ * eta_mu(n) * (boundary sign) that multiplies each hop.  Runs a kernel; blocks. */
+rhmc_status rhmc_debug_neighbors(const rhmc_lattice* lat, int32_t parity, int32_t* out,
+                                 int32_t* sign);
+
+/* Upload and pack one gauge field (Sec. 4.2 storage: structure of arrays so that
+ * consecutive sites read consecutive memory).  links: host array described
+ * above, 4*V*9 complex128.  flags: any of RHMC_LINKS_*; 0 means both.
+ * The links are copied; the host array may be freed on return. */
+rhmc_status rhmc_gauge_create(const rhmc_lattice* lat, const double* links, uint32_t flags,
+                              hipStream_t stream, rhmc_gauge** out);
+void rhmc_gauge_destroy(rhmc_gauge* g);
+
+/* One application of the hopping term of Eq. (stag) between parities:
+ * out_parity 0: out_even = D_eo in_odd;  1: out_odd = D_oe in_even.
+ * prec FP64 uses the 18-real links and complex128 vectors, FP32 the 12-real
+ * links and complex64 vectors.  in and out: device [nrhs][3][Vh], must not
+ * overlap.  1 <= nrhs <= 64. */
+rhmc_status rhmc_dslash_eo(const rhmc_gauge* g, int32_t out_parity, rhmc_prec prec, int32_t nrhs,
+                           const void* in, void* out, hipStream_t stream);
+
+/* out = A in = m^2 in - D_eo D_oe in on even sites (Sec. 2.1).  Uses an odd-site
+ * temporary from the gauge object's workspace.  Same layouts as rhmc_dslash_eo. */
+rhmc_status rhmc_apply_mdagm(const rhmc_gauge* g, double m, rhmc_prec prec, int32_t nrhs,
+                             const void* in, void* out, hipStream_t stream);
+
+/* Multi-shift CG (Sec. 4.3, Eq. shifted): x[r][i] = (A + shifts[i])^-1 b[r] for
+ * every right-hand side r < nrhs and shift i < nshift, from the Krylov space of
+ * the smallest shift with a zero starting guess.
+ *   shifts: host [nshift], finite, >= 0, and > 0 if m == 0.  1 <= nshift <= 32.
+ *   b:      device complex128 [nrhs][3][Vh];  x: device complex128 [nrhs][nshift][3][Vh].
+ *   params: NULL for defaults.  stats: nullable.
+ * Returns RHMC_ERR_NOT_CONVERGED (with x and stats holding the last state) when
+ * some shift's FP64 true residual still exceeds tol. */
+rhmc_status rhmc_multishift_cg(const rhmc_gauge* g, double m, int32_t nshift,
+                               const double* shifts, int32_t nrhs, const void* b, void* x,
+                               const rhmc_solver_params* params, rhmc_solver_stats* stats,
+                               hipStream_t stream);
+
+/* y[r] = alpha0 b[r] + sum_i alpha[i] (A + beta[i])^-1 b[r]  (Sec. 2.1, Eq. system_r).
+ * b, y: device complex128 [nrhs][3][Vh] (may not overlap).  The shifted solutions
+ * live in the gauge object's workspace.  stats as for rhmc_multishift_cg with
+ * nshift = npole. */
+rhmc_status rhmc_rational_apply(const rhmc_gauge* g, double m, const rhmc_rational* rat,
+                                int32_t nrhs, const void* b, void* y,
+                                const rhmc_solver_params* params, rhmc_solver_stats* stats,
+                                hipStream_t stream);
+
+const char* rhmc_status_string(rhmc_status s);
+const char* rhmc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RHMC_H */

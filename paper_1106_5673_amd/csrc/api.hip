@@ -1,0 +1,324 @@
+// C ABI of librhmc (include/rhmc.h): argument validation, object lifetime and
+// dispatch to the kernels and the solver driver.  No exception crosses the ABI.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "solver.h"
+
+namespace rhmc {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+static rhmc_status invalid(const std::string& msg) {
+    set_error(msg);
+    return RHMC_ERR_INVALID_ARG;
+}
+
+static rhmc_status use_device(int dev) {
+    RHMC_HIP_TRY(hipSetDevice(dev));
+    return RHMC_OK;
+}
+
+// Odd-parity temporary of the gauge object, grown on demand.
+static rhmc_status tmp_odd(rhmc_gauge* g, size_t bytes, void** out) {
+    if (g->tmp_odd_bytes < bytes) {
+        hipFree(g->tmp_odd);
+        g->tmp_odd = nullptr;
+        g->tmp_odd_bytes = 0;
+        RHMC_HIP_TRY(hipMalloc(&g->tmp_odd, bytes));
+        g->tmp_odd_bytes = bytes;
+    }
+    *out = g->tmp_odd;
+    return RHMC_OK;
+}
+
+static rhmc_status scratch_partials(rhmc_gauge* g, double** out) {
+    // per-rhs partial sums of a kModeA launch that nobody reads
+    static thread_local std::vector<std::pair<int, double*>> cache;
+    for (auto& c : cache)
+        if (c.first == g->device) {
+            *out = c.second;
+            return RHMC_OK;
+        }
+    double* p = nullptr;
+    const size_t nblk = (size_t)g->lat.Vh / kBlock + 2;
+    RHMC_HIP_TRY(hipMalloc(&p, sizeof(double) * kMaxSys * nblk * 2));
+    cache.emplace_back(g->device, p);
+    *out = p;
+    return RHMC_OK;
+}
+
+template <typename VT>
+static rhmc_status hop(rhmc_gauge* g, int out_par, rhmc_prec prec, int nrhs, const void* in,
+                       void* out, int mode, const void* self, double c, hipStream_t s) {
+    const size_t n = (size_t)3 * g->lat.Vh;
+    const int nlinks = (int)(4 * g->lat.V);
+    double* partial = nullptr;
+    if (mode == kModeA) RHMC_TRY(scratch_partials(g, &partial));
+    for (int r0 = 0; r0 < nrhs; r0 += kMaxSys) {
+        const int cnt = nrhs - r0 < kMaxSys ? nrhs - r0 : kMaxSys;
+        DslashArgs<VT> a{};
+        a.g = g->lat.geom;
+        a.out_par = out_par;
+        a.nrhs = cnt;
+        a.partial = partial;
+        for (int k = 0; k < cnt; ++k) {
+            a.in[k] = reinterpret_cast<const VT*>(in) + (size_t)(r0 + k) * n;
+            a.out[k] = reinterpret_cast<VT*>(out) + (size_t)(r0 + k) * n;
+            if (self) a.self[k] = reinterpret_cast<const VT*>(self) + (size_t)(r0 + k) * n;
+            a.c[k] = c;
+        }
+        if constexpr (std::is_same<VT, double2>::value) {
+            RHMC_HIP_TRY(launch_dslash64(g->u64, nlinks, a, mode, s));
+        } else {
+            RHMC_HIP_TRY(launch_dslash32(g->u32, nlinks, a, mode, s));
+        }
+    }
+    (void)prec;
+    return RHMC_OK;
+}
+
+static rhmc_status check_prec(const rhmc_gauge* g, rhmc_prec prec) {
+    if (prec == RHMC_PREC_FP64 && !g->u64) return invalid("gauge object has no FP64 links");
+    if (prec == RHMC_PREC_FP32 && !g->u32) return invalid("gauge object has no FP32-12 links");
+    if (prec != RHMC_PREC_FP64 && prec != RHMC_PREC_FP32) return invalid("unknown precision");
+    return RHMC_OK;
+}
+
+static rhmc_status check_params(const rhmc_solver_params* p, const rhmc_gauge* g,
+                                rhmc_solver_params* out) {
+    rhmc_solver_params_default(out);
+    if (p) *out = *p;
+    if (!(out->tol > 0) || !std::isfinite(out->tol)) return invalid("tol must be positive");
+    if (out->maxiter < 1) return invalid("maxiter must be >= 1");
+    if (out->mode != RHMC_MODE_FP64 && out->mode != RHMC_MODE_MIXED) return invalid("unknown mode");
+    if (out->block < 1 || out->block > kMaxBlockLen) return invalid("block must be in 1..16");
+    if (out->reliable_every < 1) return invalid("reliable_every must be >= 1");
+    if (!g->u64) return invalid("solvers need the FP64 links (true residuals are FP64)");
+    if (out->mode == RHMC_MODE_MIXED && !g->u32) return invalid("MIXED mode needs the FP32-12 links");
+    return RHMC_OK;
+}
+
+}  // namespace rhmc
+
+using namespace rhmc;
+
+extern "C" {
+
+void rhmc_solver_params_default(rhmc_solver_params* p) {
+    if (!p) return;
+    p->tol = 1e-10;
+    p->maxiter = 100000;
+    p->mode = RHMC_MODE_FP64;
+    p->reliable_every = 50;
+    p->refine = 1;
+    p->block = 10;
+    p->use_graph = 1;
+    p->poll_every = 0;
+    p->tune = 0;
+}
+
+rhmc_status rhmc_lattice_create(const int32_t L[4], int32_t t_bc, rhmc_lattice** out) {
+    if (!L || !out) return invalid("null argument");
+    *out = nullptr;
+    int64_t V = 1;
+    for (int i = 0; i < 4; ++i) {
+        if (L[i] < 2 || (L[i] & 1)) return invalid("every lattice extent must be even and >= 2");
+        V *= L[i];
+    }
+    if (V > (int64_t(1) << 28)) return invalid("lattice volume above 2^28 sites");
+    if (t_bc != 1 && t_bc != -1) return invalid("t_bc must be +1 or -1");
+    rhmc_lattice* lat = new (std::nothrow) rhmc_lattice();
+    if (!lat) return RHMC_ERR_OOM;
+    std::memcpy(lat->L, L, sizeof(lat->L));
+    lat->t_bc = t_bc;
+    lat->V = V;
+    lat->Vh = V / 2;
+    Geom& g = lat->geom;
+    g.Lx = L[0];
+    g.Ly = L[1];
+    g.Lz = L[2];
+    g.Lt = L[3];
+    g.hx = L[0] / 2;
+    g.Vh = (int)(V / 2);
+    g.sy = g.hx;
+    g.sz = g.hx * L[1];
+    g.st = g.hx * L[1] * L[2];
+    g.tbc = t_bc;
+    *out = lat;
+    return RHMC_OK;
+}
+
+void rhmc_lattice_destroy(rhmc_lattice* lat) { delete lat; }
+
+rhmc_status rhmc_debug_neighbors(const rhmc_lattice* lat, int32_t parity, int32_t* out,
+                                 int32_t* sign) {
+    if (!lat || !out) return invalid("null argument");
+    if (parity != 0 && parity != 1) return invalid("parity must be 0 or 1");
+    const size_t cnt = (size_t)lat->Vh * 8;
+    int *d_nb = nullptr, *d_sg = nullptr;
+    RHMC_HIP_TRY(hipMalloc(&d_nb, cnt * sizeof(int)));
+    hipError_t e = hipMalloc(&d_sg, cnt * sizeof(int));
+    if (e == hipSuccess) e = launch_neighbors(lat->geom, parity, d_nb, d_sg, 0);
+    if (e == hipSuccess) e = hipMemcpy(out, d_nb, cnt * sizeof(int), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && sign) e = hipMemcpy(sign, d_sg, cnt * sizeof(int), hipMemcpyDeviceToHost);
+    hipFree(d_nb);
+    hipFree(d_sg);
+    RHMC_HIP_TRY(e);
+    return RHMC_OK;
+}
+
+rhmc_status rhmc_gauge_create(const rhmc_lattice* lat, const double* links, uint32_t flags,
+                              hipStream_t stream, rhmc_gauge** out) {
+    if (!lat || !links || !out) return invalid("null argument");
+    *out = nullptr;
+    if (flags == 0) flags = RHMC_LINKS_FP64_18 | RHMC_LINKS_FP32_12;
+    if (flags & ~(RHMC_LINKS_FP64_18 | RHMC_LINKS_FP32_12)) return invalid("unknown link flags");
+    rhmc_gauge* g = new (std::nothrow) rhmc_gauge();
+    if (!g) return RHMC_ERR_OOM;
+    g->lat = *lat;
+    hipError_t e = hipGetDevice(&g->device);
+    const size_t nlinks = (size_t)4 * lat->V;
+    double2* canon = nullptr;
+    if (e == hipSuccess && (flags & RHMC_LINKS_FP64_18))
+        e = hipMalloc(&g->u64, nlinks * 9 * sizeof(double2));
+    if (e == hipSuccess && (flags & RHMC_LINKS_FP32_12))
+        e = hipMalloc(&g->u32, nlinks * 3 * sizeof(float4));
+    if (e == hipSuccess) e = hipMalloc(&canon, nlinks * 9 * sizeof(double2));
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(canon, links, nlinks * 9 * sizeof(double2), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = launch_pack_links(g, canon, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    hipFree(canon);
+    if (e != hipSuccess) {
+        set_error(std::string("rhmc_gauge_create: ") + hipGetErrorString(e));
+        rhmc_gauge_destroy(g);
+        return e == hipErrorOutOfMemory ? RHMC_ERR_OOM : RHMC_ERR_HIP;
+    }
+    *out = g;
+    return RHMC_OK;
+}
+
+void rhmc_gauge_destroy(rhmc_gauge* g) {
+    if (!g) return;
+    hipSetDevice(g->device);
+    workspace_destroy(g->ws);
+    hipFree(g->u64);
+    hipFree(g->u32);
+    hipFree(g->tmp_odd);
+    delete g;
+}
+
+rhmc_status rhmc_dslash_eo(const rhmc_gauge* gc, int32_t out_parity, rhmc_prec prec, int32_t nrhs,
+                           const void* in, void* out, hipStream_t stream) {
+    rhmc_gauge* g = const_cast<rhmc_gauge*>(gc);
+    if (!g || !in || !out) return invalid("null argument");
+    if (out_parity != 0 && out_parity != 1) return invalid("out_parity must be 0 or 1");
+    if (nrhs < 1 || nrhs > 64) return invalid("nrhs must be in 1..64");
+    if (in == out) return invalid("in and out must not overlap");
+    RHMC_TRY(check_prec(g, prec));
+    RHMC_TRY(use_device(g->device));
+    if (prec == RHMC_PREC_FP64)
+        return hop<double2>(g, out_parity, prec, nrhs, in, out, kModeD, nullptr, 0.0, stream);
+    return hop<float2>(g, out_parity, prec, nrhs, in, out, kModeD, nullptr, 0.0, stream);
+}
+
+rhmc_status rhmc_apply_mdagm(const rhmc_gauge* gc, double m, rhmc_prec prec, int32_t nrhs,
+                             const void* in, void* out, hipStream_t stream) {
+    rhmc_gauge* g = const_cast<rhmc_gauge*>(gc);
+    if (!g || !in || !out) return invalid("null argument");
+    if (nrhs < 1 || nrhs > 64) return invalid("nrhs must be in 1..64");
+    if (in == out) return invalid("in and out must not overlap");
+    if (!std::isfinite(m)) return invalid("m must be finite");
+    RHMC_TRY(check_prec(g, prec));
+    RHMC_TRY(use_device(g->device));
+    const size_t n = (size_t)3 * g->lat.Vh;
+    const size_t vb = prec == RHMC_PREC_FP64 ? sizeof(double2) : sizeof(float2);
+    void* t = nullptr;
+    RHMC_TRY(tmp_odd(g, vb * n * nrhs, &t));
+    if (prec == RHMC_PREC_FP64) {
+        RHMC_TRY(hop<double2>(g, 1, prec, nrhs, in, t, kModeD, nullptr, 0.0, stream));
+        return hop<double2>(g, 0, prec, nrhs, t, out, kModeA, in, m * m, stream);
+    }
+    RHMC_TRY(hop<float2>(g, 1, prec, nrhs, in, t, kModeD, nullptr, 0.0, stream));
+    return hop<float2>(g, 0, prec, nrhs, t, out, kModeA, in, m * m, stream);
+}
+
+static rhmc_status check_shifts(double m, int nshift, const double* shifts) {
+    if (nshift < 1 || nshift > kMaxShift) return invalid("nshift must be in 1..32");
+    if (!shifts) return invalid("null shifts");
+    for (int i = 0; i < nshift; ++i) {
+        if (!std::isfinite(shifts[i]) || shifts[i] < 0) return invalid("shifts must be finite and >= 0");
+        if (m * m + shifts[i] <= 0) return invalid("m^2 + shift must be > 0 (A + shift positive definite)");
+    }
+    return RHMC_OK;
+}
+
+rhmc_status rhmc_multishift_cg(const rhmc_gauge* gc, double m, int32_t nshift,
+                               const double* shifts, int32_t nrhs, const void* b, void* x,
+                               const rhmc_solver_params* params, rhmc_solver_stats* stats,
+                               hipStream_t stream) {
+    rhmc_gauge* g = const_cast<rhmc_gauge*>(gc);
+    if (!g || !b || !x) return invalid("null argument");
+    if (nrhs < 1 || nrhs > 64) return invalid("nrhs must be in 1..64");
+    if (!std::isfinite(m)) return invalid("m must be finite");
+    RHMC_TRY(check_shifts(m, nshift, shifts));
+    rhmc_solver_params prm;
+    RHMC_TRY(check_params(params, g, &prm));
+    RHMC_TRY(use_device(g->device));
+    const size_t n = (size_t)3 * g->lat.Vh;
+    return multishift(g, m, nshift, shifts, nrhs, reinterpret_cast<const double2*>(b),
+                      reinterpret_cast<double2*>(x), (size_t)nshift * n, n, prm, stats, stream);
+}
+
+rhmc_status rhmc_rational_apply(const rhmc_gauge* gc, double m, const rhmc_rational* rat,
+                                int32_t nrhs, const void* b, void* y,
+                                const rhmc_solver_params* params, rhmc_solver_stats* stats,
+                                hipStream_t stream) {
+    rhmc_gauge* g = const_cast<rhmc_gauge*>(gc);
+    if (!g || !rat || !b || !y) return invalid("null argument");
+    if (b == y) return invalid("b and y must not overlap");
+    if (nrhs < 1 || nrhs > 64) return invalid("nrhs must be in 1..64");
+    if (!std::isfinite(m) || !std::isfinite(rat->alpha0)) return invalid("non-finite coefficient");
+    if (rat->npole < 1 || !rat->alpha) return invalid("rational needs npole >= 1 and alpha");
+    for (int i = 0; i < rat->npole; ++i)
+        if (!std::isfinite(rat->alpha[i])) return invalid("non-finite coefficient");
+    RHMC_TRY(check_shifts(m, rat->npole, rat->beta));
+    rhmc_solver_params prm;
+    RHMC_TRY(check_params(params, g, &prm));
+    RHMC_TRY(use_device(g->device));
+    if (stats) {
+        stats->total_iterations = 0;
+        stats->reliable_updates = 0;
+        stats->refine_rounds = 0;
+        stats->time_ms = 0;
+        stats->max_true_residual = 0;
+    }
+    return rational(g, m, rat, nrhs, reinterpret_cast<const double2*>(b),
+                    reinterpret_cast<double2*>(y), prm, stats, stream);
+}
+
+const char* rhmc_status_string(rhmc_status s) {
+    switch (s) {
+        case RHMC_OK: return "ok";
+        case RHMC_ERR_INVALID_ARG: return "invalid argument";
+        case RHMC_ERR_NONFINITE: return "non-finite value";
+        case RHMC_ERR_NOT_CONVERGED: return "not converged";
+        case RHMC_ERR_HIP: return "HIP runtime error";
+        case RHMC_ERR_OOM: return "out of device memory";
+        case RHMC_ERR_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char* rhmc_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,59 @@
+// Launch arguments of the BLAS-1 kernels (blas.hip).
+#pragma once
+
+#include "common.h"
+
+namespace rhmc {
+
+// Generic per-system vector arguments; n = complex numbers per vector (3*Vh).
+template <typename VT>
+struct VecArgs {
+    void* state;   // SolverState
+    size_t n;
+    const double2* b64[kMaxSys];
+    VT* x[kMaxSys];
+    VT* y[kMaxSys];
+    VT* z[kMaxSys];
+    double* partial;
+    unsigned* counter;
+};
+
+// Deferred update of the shifted solutions at a block boundary.
+template <typename VT>
+struct FlushArgs {
+    void* state;
+    size_t n;
+    int nshift;
+    VT* ring[kMaxBlockLen + 1][kMaxSys];  // stored base residuals r(k0+l)
+    VT* P;                                // shifted directions [nsys][nshift][n]
+    double2* X;                           // shifted solutions
+    size_t x_sys, x_shift;                // element strides of X between systems / shifts
+    unsigned* counter;
+};
+
+struct CombineArgs {
+    size_t n;
+    int nterm;
+    double alpha0;
+    double alpha[kMaxShift];
+    const double2* b[kMaxSys];
+    const double2* x[kMaxSys];  // first of nterm vectors, x_stride elements apart
+    size_t x_stride;
+    double2* y[kMaxSys];
+};
+
+struct AddArgs {
+    size_t n;
+    const double2* x[kMaxSys];
+    double2* y[kMaxSys];
+};
+
+template <typename VT> hipError_t launch_start(const VecArgs<VT>& a, int nsys, hipStream_t s);
+template <typename VT> hipError_t launch_rupdate(const VecArgs<VT>& a, int nsys, hipStream_t s);
+template <typename VT> hipError_t launch_pupdate(const VecArgs<VT>& a, int nsys, hipStream_t s);
+template <typename VT>
+hipError_t launch_flush(const FlushArgs<VT>& a, int nsys, int qmax, hipStream_t s);
+hipError_t launch_combine(const CombineArgs& a, int nsys, hipStream_t s);
+hipError_t launch_add(const AddArgs& a, int nsys, hipStream_t s);
+
+}  // namespace rhmc

@@ -1,0 +1,315 @@
+// Staggered hopping term (Eq. stag, Sec. 2) between the two parities, and the
+// link packing that feeds it (storage layout of Sec. 4.2).
+//
+// One lane owns one output site and every right-hand side of the launch, so
+// each link is read once per application however many vectors are batched.
+// Links are structure-of-arrays over the link index k = (2*mu + parity)*Vh + eo,
+// so the 64 lanes of a wave read 64 consecutive links per load; neighbour
+// vectors are colour-major [3][Vh] arrays, read by consecutive sites.
+#include "common.h"
+#include "state.h"
+
+namespace rhmc {
+
+// ------------------------------------------------------------------ pack
+__global__ __launch_bounds__(kBlock) void k_pack_links(const double2* __restrict__ canon, Geom g,
+                                                        double2* __restrict__ u64,
+                                                        float4* __restrict__ u32, int nlinks) {
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;  // lex * 4 + mu
+    const int V = 2 * g.Vh;
+    if (id >= 4 * V) return;
+    const int lex = id >> 2, mu = id & 3;
+    int r = lex / g.Lx;
+    const int x = lex - r * g.Lx;
+    const int y = r % g.Ly;
+    r /= g.Ly;
+    const int z = r % g.Lz;
+    const int t = r / g.Lz;
+    const int par = (x + y + z + t) & 1;
+    const int k = (2 * mu + par) * g.Vh + (lex >> 1);
+    const double2* src = canon + (size_t)id * 9;
+    double2 e[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) e[i] = src[i];
+    if (u64) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) u64[(size_t)i * nlinks + k] = e[i];
+    }
+    if (u32) {
+        // rows 1-2 rounded to nearest FP32; row 3 is rebuilt in the kernel
+        u32[(size_t)0 * nlinks + k] = make_float4((float)e[0].x, (float)e[0].y, (float)e[1].x, (float)e[1].y);
+        u32[(size_t)1 * nlinks + k] = make_float4((float)e[2].x, (float)e[2].y, (float)e[3].x, (float)e[3].y);
+        u32[(size_t)2 * nlinks + k] = make_float4((float)e[4].x, (float)e[4].y, (float)e[5].x, (float)e[5].y);
+    }
+}
+
+hipError_t launch_pack_links(const rhmc_gauge* g, const double2* canon, hipStream_t s) {
+    const int V = (int)g->lat.V;
+    const int nlinks = 4 * V;
+    const int grid = (4 * V + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_pack_links, dim3(grid), dim3(kBlock), 0, s, canon, g->lat.geom, g->u64,
+                       g->u32, nlinks);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ neighbours
+__global__ __launch_bounds__(kBlock) void k_neighbors(Geom g, int par, int* nb, int* sign) {
+    const int eo = blockIdx.x * blockDim.x + threadIdx.x;
+    if (eo >= g.Vh) return;
+    int x, y, z, t;
+    site_coords(g, eo, par, x, y, z, t);
+    const Hops h = make_hops(g, eo, x, y, z, t);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        nb[(size_t)eo * 8 + k] = h.nb[k];
+        if (sign) sign[(size_t)eo * 8 + k] = (int)(2.0f * h.coef[k]) * (k < 4 ? 1 : -1);
+    }
+}
+
+hipError_t launch_neighbors(const Geom& g, int par, int* nb, int* sign, hipStream_t s) {
+    hipLaunchKernelGGL(k_neighbors, dim3((g.Vh + kBlock - 1) / kBlock), dim3(kBlock), 0, s, g, par,
+                       nb, sign);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ links
+template <typename RT>
+struct Link {
+    RT re[3][3], im[3][3];
+};
+
+__device__ __forceinline__ void load_link(const double2* __restrict__ u, int nlinks, int k,
+                                          Link<double>& L) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const double2 v = u[(size_t)(3 * i + j) * nlinks + k];
+            L.re[i][j] = v.x;
+            L.im[i][j] = v.y;
+        }
+}
+
+// 12-real link: rows 1-2 stored, row 3 = conj(row1 x row2) (valid for det U = 1).
+__device__ __forceinline__ void load_link(const float4* __restrict__ u, int nlinks, int k,
+                                          Link<float>& L) {
+    const float4 a = u[k];
+    const float4 b = u[(size_t)nlinks + k];
+    const float4 c = u[(size_t)2 * nlinks + k];
+    L.re[0][0] = a.x; L.im[0][0] = a.y; L.re[0][1] = a.z; L.im[0][1] = a.w;
+    L.re[0][2] = b.x; L.im[0][2] = b.y; L.re[1][0] = b.z; L.im[1][0] = b.w;
+    L.re[1][1] = c.x; L.im[1][1] = c.y; L.re[1][2] = c.z; L.im[1][2] = c.w;
+    // (row1 x row2)_j = row1_{j+1} row2_{j+2} - row1_{j+2} row2_{j+1}; row3 = its conjugate
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const int j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+        const float pr = L.re[0][j1] * L.re[1][j2] - L.im[0][j1] * L.im[1][j2]
+                       - (L.re[0][j2] * L.re[1][j1] - L.im[0][j2] * L.im[1][j1]);
+        const float pi = L.re[0][j1] * L.im[1][j2] + L.im[0][j1] * L.re[1][j2]
+                       - (L.re[0][j2] * L.im[1][j1] + L.im[0][j2] * L.re[1][j1]);
+        L.re[2][j] = pr;
+        L.im[2][j] = -pi;
+    }
+}
+
+template <typename VT> struct RealOf;
+template <> struct RealOf<double2> { using T = double; };
+template <> struct RealOf<float2> { using T = float; };
+
+// ------------------------------------------------------------------ hopping kernel
+template <typename VT, typename LT, int NR, int MODE>
+__global__ __launch_bounds__(kBlock) void k_dslash(const LT* __restrict__ links, int nlinks,
+                                                    DslashArgs<VT> a) {
+    using RT = typename RealOf<VT>::T;
+    if (a.all_done && *a.all_done) return;
+    const int nblk = gridDim.x;
+    const int blk = xcd_remap(blockIdx.x, nblk);
+    const int Vh = a.g.Vh;
+    const int eo = blk * kBlock + threadIdx.x;
+
+    bool act[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+        act[r] = (r < a.nrhs) && !(a.skip && a.skip[r * a.skip_stride]);
+
+    double dot[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) dot[r] = 0.0;
+
+    if (eo < Vh) {
+        int x, y, z, t;
+        site_coords(a.g, eo, a.out_par, x, y, z, t);
+        const Hops h = make_hops(a.g, eo, x, y, z, t);
+        RT ar[NR][3], ai[NR][3];
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) ar[r][c] = ai[r][c] = RT(0);
+
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) {
+            // forward hop: + coef * U_mu(n) psi(n+mu)
+            {
+                Link<RT> U;
+                load_link(links, nlinks, (2 * mu + a.out_par) * Vh + eo, U);
+                const int nb = h.nb[mu];
+                const RT s = (RT)h.coef[mu];
+#pragma unroll
+                for (int r = 0; r < NR; ++r) {
+                    if (!act[r]) continue;
+                    const VT* in = a.in[r];
+                    const VT v0 = in[nb], v1 = in[Vh + nb], v2 = in[2 * Vh + nb];
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        const RT tr = U.re[i][0] * v0.x - U.im[i][0] * v0.y + U.re[i][1] * v1.x -
+                                      U.im[i][1] * v1.y + U.re[i][2] * v2.x - U.im[i][2] * v2.y;
+                        const RT ti = U.re[i][0] * v0.y + U.im[i][0] * v0.x + U.re[i][1] * v1.y +
+                                      U.im[i][1] * v1.x + U.re[i][2] * v2.y + U.im[i][2] * v2.x;
+                        ar[r][i] += s * tr;
+                        ai[r][i] += s * ti;
+                    }
+                }
+            }
+            // backward hop: + coef * U_mu(n-mu)^dagger psi(n-mu)   (coef carries the minus)
+            {
+                const int nb = h.nb[4 + mu];
+                Link<RT> U;
+                load_link(links, nlinks, (2 * mu + 1 - a.out_par) * Vh + nb, U);
+                const RT s = (RT)h.coef[4 + mu];
+#pragma unroll
+                for (int r = 0; r < NR; ++r) {
+                    if (!act[r]) continue;
+                    const VT* in = a.in[r];
+                    const VT v0 = in[nb], v1 = in[Vh + nb], v2 = in[2 * Vh + nb];
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        // (U^dagger v)_i = sum_j conj(U_ji) v_j
+                        const RT tr = U.re[0][i] * v0.x + U.im[0][i] * v0.y + U.re[1][i] * v1.x +
+                                      U.im[1][i] * v1.y + U.re[2][i] * v2.x + U.im[2][i] * v2.y;
+                        const RT ti = U.re[0][i] * v0.y - U.im[0][i] * v0.x + U.re[1][i] * v1.y -
+                                      U.im[1][i] * v1.x + U.re[2][i] * v2.y - U.im[2][i] * v2.x;
+                        ar[r][i] += s * tr;
+                        ai[r][i] += s * ti;
+                    }
+                }
+            }
+        }
+
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            if (!act[r]) continue;
+            if (MODE == kModeD) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    VT o;
+                    o.x = ar[r][c];
+                    o.y = ai[r][c];
+                    a.out[r][c * Vh + eo] = o;
+                }
+            } else if (MODE == kModeA) {
+                const RT cr = (RT)a.c[r];
+                double d = 0.0;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const VT p = a.self[r][c * Vh + eo];
+                    VT o;
+                    o.x = cr * p.x - ar[r][c];
+                    o.y = cr * p.y - ai[r][c];
+                    a.out[r][c * Vh + eo] = o;
+                    d += (double)p.x * (double)o.x + (double)p.y * (double)o.y;
+                }
+                dot[r] = d;
+            } else {  // kModeResid (FP64 operator)
+                const double cr = a.c[r];
+                double d = 0.0;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const VT xv = a.self[r][c * Vh + eo];
+                    const double2 bv = a.rhs[r][c * Vh + eo];
+                    double2 o;
+                    o.x = bv.x - cr * (double)xv.x + (double)ar[r][c];
+                    o.y = bv.y - cr * (double)xv.y + (double)ai[r][c];
+                    if (a.out[r]) {
+                        VT w;
+                        w.x = o.x;
+                        w.y = o.y;
+                        a.out[r][c * Vh + eo] = w;
+                    }
+                    if (a.out32[r]) a.out32[r][c * Vh + eo] = make_float2((float)o.x, (float)o.y);
+                    d += o.x * o.x + o.y * o.y;
+                }
+                dot[r] = d;
+            }
+        }
+    }
+
+    if (MODE != kModeD) {
+        // deterministic block reduction -> one partial per rhs and block
+        __shared__ double sm[NR][kBlock / 64];
+        const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            double v = dot[r];
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            if (lane == 0) sm[r][wid] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < NR && threadIdx.x < a.nrhs) {
+            double s = 0.0;
+#pragma unroll
+            for (int w = 0; w < kBlock / 64; ++w) s += sm[threadIdx.x][w];
+            a.partial[(size_t)threadIdx.x * nblk + blk] = s;
+            __threadfence();
+        }
+        if (a.finalize) {
+            __shared__ int last;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                __threadfence();
+                const unsigned prev = atomicAdd(a.counter, 1u);
+                last = (prev == (unsigned)(nblk - 1));
+            }
+            __syncthreads();
+            if (last) {
+                __threadfence();
+                solver_finalize(a.finalize, a.fin_state, a.partial, nblk, a.nrhs, a.out_sums);
+                if (threadIdx.x == 0) *a.counter = 0u;
+            }
+        }
+    }
+}
+
+int dslash_grid(int Vh) { return (Vh + kBlock - 1) / kBlock; }
+
+template <typename VT, typename LT, int MODE>
+static hipError_t dispatch(const LT* links, int nlinks, const DslashArgs<VT>& a, hipStream_t s) {
+    const dim3 grid(dslash_grid(a.g.Vh)), block(kBlock);
+    if (a.nrhs <= 1)
+        hipLaunchKernelGGL((k_dslash<VT, LT, 1, MODE>), grid, block, 0, s, links, nlinks, a);
+    else if (a.nrhs <= 2)
+        hipLaunchKernelGGL((k_dslash<VT, LT, 2, MODE>), grid, block, 0, s, links, nlinks, a);
+    else if (a.nrhs <= 4)
+        hipLaunchKernelGGL((k_dslash<VT, LT, 4, MODE>), grid, block, 0, s, links, nlinks, a);
+    else
+        hipLaunchKernelGGL((k_dslash<VT, LT, 8, MODE>), grid, block, 0, s, links, nlinks, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_dslash64(const double2* u64, int nlinks, const DslashArgs<double2>& a, int mode,
+                           hipStream_t s) {
+    switch (mode) {
+        case kModeD: return dispatch<double2, double2, kModeD>(u64, nlinks, a, s);
+        case kModeA: return dispatch<double2, double2, kModeA>(u64, nlinks, a, s);
+        default: return dispatch<double2, double2, kModeResid>(u64, nlinks, a, s);
+    }
+}
+
+hipError_t launch_dslash32(const float4* u32, int nlinks, const DslashArgs<float2>& a, int mode,
+                           hipStream_t s) {
+    switch (mode) {
+        case kModeD: return dispatch<float2, float4, kModeD>(u32, nlinks, a, s);
+        default: return dispatch<float2, float4, kModeA>(u32, nlinks, a, s);
+    }
+}
+
+}  // namespace rhmc

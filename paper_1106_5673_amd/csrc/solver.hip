@@ -1,0 +1,695 @@
+// Multi-shift CG driver (Sec. 4.3, Eq. shifted) for A = m^2 - D_eo D_oe.
+//
+// One CG iteration is four kernels on the caller's stream:
+//   t  = D_oe p                                   (hopping, FP64 or FP32-12)
+//   Ap = (m^2 + sigma_0) p - D_eo t, sum <p,Ap>   -> alpha, zeta_i, alpha_i
+//   r' = r - alpha Ap, sum <r',r'>                -> beta, beta_i, convergence
+//   p  = r' + beta p
+// The scalar recurrences run in FP64 in the last workgroup of the reducing
+// kernels, so the host only polls one flag.  The shifted solutions x_i and
+// directions p_i are updated once per block of K iterations from the stored
+// base residuals (state.h); a block is captured once as a hipGraph and
+// replayed.  MIXED mode iterates in FP32 with 12-real links and every
+// `reliable_every` iterations replaces r by b - (A + sigma_0) x_0 computed in
+// FP64.  At the end every shift's true residual is recomputed in FP64, and a
+// shift above tolerance gets a warm-started CG on its own system.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <type_traits>
+#include <vector>
+
+#include "blas.h"
+#include "solver.h"
+#include "state.h"
+
+namespace rhmc {
+
+struct GraphKey {
+    int nsys = 0, nshift = 0, K = 0, mode = -1, reliable = 0;
+    const void* b[kMaxSys] = {};
+    const void* x = nullptr;
+    size_t x_sys = 0, x_shift = 0;
+    double c[kMaxSys] = {};
+    int base[kMaxSys] = {};
+    bool operator==(const GraphKey& o) const { return std::memcmp(this, &o, sizeof(*this)) == 0; }
+};
+
+struct CachedGraph {
+    GraphKey key;
+    hipGraphExec_t exec = nullptr;
+};
+
+struct Workspace {
+    int device = 0;
+    size_t n = 0;          // complex numbers per vector (3*Vh)
+    int cap_sys = 0, cap_shift = 0, cap_K = 0;
+    size_t vec_bytes = 0;  // bytes of one vector at the widest precision used (FP64)
+    // iteration vectors, stored at FP64 width so both modes share the buffers
+    void* ring = nullptr;  // [K+1][nsys] vectors
+    void* p = nullptr;     // [nsys]
+    void* Ap = nullptr;    // [nsys]
+    void* t = nullptr;     // [nsys] odd parity
+    void* P = nullptr;     // [nsys][nshift]
+    double2* t64 = nullptr;    // [kMaxSys] odd parity, FP64
+    double2* rb = nullptr;     // [kMaxSys] refinement right-hand sides
+    double2* rx = nullptr;     // [kMaxSys] refinement corrections
+    double2* xr = nullptr;     // rational apply: [nsys][nshift] shifted solutions
+    size_t xr_count = 0;
+    double* partial = nullptr;
+    unsigned* counters = nullptr;  // [8]
+    double* sums = nullptr;        // [kMaxSys]
+    SolverState* st = nullptr;     // device
+    SolverState* hst = nullptr;    // pinned host mirror
+    int* flags_host = nullptr;     // pinned [2]
+    double* sums_host = nullptr;   // pinned [kMaxSys]
+    hipStream_t cap = nullptr;     // capture stream
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    CachedGraph graphs[4];
+    int graph_next = 0;
+};
+
+static void free_graphs(Workspace* w) {
+    for (auto& g : w->graphs) {
+        if (g.exec) hipGraphExecDestroy(g.exec);
+        g.exec = nullptr;
+        g.key = GraphKey();
+    }
+}
+
+void workspace_destroy(Workspace* w) {
+    if (!w) return;
+    free_graphs(w);
+    hipFree(w->ring);
+    hipFree(w->p);
+    hipFree(w->Ap);
+    hipFree(w->t);
+    hipFree(w->P);
+    hipFree(w->t64);
+    hipFree(w->rb);
+    hipFree(w->rx);
+    hipFree(w->xr);
+    hipFree(w->partial);
+    hipFree(w->counters);
+    hipFree(w->sums);
+    hipFree(w->st);
+    hipHostFree(w->hst);
+    hipHostFree(w->flags_host);
+    hipHostFree(w->sums_host);
+    if (w->cap) hipStreamDestroy(w->cap);
+    for (auto& e : w->ev)
+        if (e) hipEventDestroy(e);
+    delete w;
+}
+
+static rhmc_status alloc(void** p, size_t bytes) {
+    RHMC_HIP_TRY(hipMalloc(p, bytes));
+    return RHMC_OK;
+}
+
+// Ensure capacity for nsys systems x nshift shifts with blocks of K.
+static rhmc_status ensure_workspace(rhmc_gauge* g, int nsys, int nshift, int K) {
+    Workspace* w = g->ws;
+    const size_t n = (size_t)3 * g->lat.Vh;
+    if (w && w->cap_sys >= nsys && w->cap_shift >= nshift && w->cap_K >= K) return RHMC_OK;
+    int cs = nsys, csh = nshift, cK = K;
+    if (w) {
+        cs = std::max(cs, w->cap_sys);
+        csh = std::max(csh, w->cap_shift);
+        cK = std::max(cK, w->cap_K);
+        workspace_destroy(w);
+        g->ws = nullptr;
+    }
+    w = new Workspace();
+    g->ws = w;
+    w->device = g->device;
+    w->n = n;
+    w->cap_sys = cs;
+    w->cap_shift = csh;
+    w->cap_K = cK;
+    w->vec_bytes = n * sizeof(double2);
+    const size_t vb = w->vec_bytes;
+    RHMC_TRY(alloc(&w->ring, vb * (cK + 1) * cs));
+    RHMC_TRY(alloc(&w->p, vb * cs));
+    RHMC_TRY(alloc(&w->Ap, vb * cs));
+    RHMC_TRY(alloc(&w->t, vb * cs));
+    RHMC_TRY(alloc(&w->P, vb * cs * csh));
+    RHMC_TRY(alloc((void**)&w->t64, vb * kMaxSys));
+    RHMC_TRY(alloc((void**)&w->rb, vb * kMaxSys));
+    RHMC_TRY(alloc((void**)&w->rx, vb * kMaxSys));
+    const size_t nblk = n / 2 / kBlock + 2;
+    RHMC_TRY(alloc((void**)&w->partial, sizeof(double) * 2 * kMaxSys * nblk));
+    RHMC_TRY(alloc((void**)&w->counters, sizeof(unsigned) * 8));
+    RHMC_HIP_TRY(hipMemset(w->counters, 0, sizeof(unsigned) * 8));
+    RHMC_TRY(alloc((void**)&w->sums, sizeof(double) * kMaxSys));
+    RHMC_TRY(alloc((void**)&w->st, sizeof(SolverState)));
+    RHMC_HIP_TRY(hipHostMalloc((void**)&w->hst, sizeof(SolverState), hipHostMallocDefault));
+    RHMC_HIP_TRY(hipHostMalloc((void**)&w->flags_host, sizeof(int) * 2, hipHostMallocDefault));
+    RHMC_HIP_TRY(hipHostMalloc((void**)&w->sums_host, sizeof(double) * kMaxSys, hipHostMallocDefault));
+    RHMC_HIP_TRY(hipStreamCreateWithFlags(&w->cap, hipStreamNonBlocking));
+    RHMC_HIP_TRY(hipEventCreateWithFlags(&w->ev[0], hipEventDisableTiming));
+    RHMC_HIP_TRY(hipEventCreateWithFlags(&w->ev[1], hipEventDisableTiming));
+    return RHMC_OK;
+}
+
+rhmc_status ensure_rational_buffer(rhmc_gauge* g, size_t nvec, double2** out) {
+    Workspace* w = g->ws;
+    if (w->xr_count < nvec) {
+        hipFree(w->xr);
+        w->xr = nullptr;
+        w->xr_count = 0;
+        RHMC_HIP_TRY(hipMalloc((void**)&w->xr, w->vec_bytes * nvec));
+        w->xr_count = nvec;
+        free_graphs(w);   // graphs may reference the old buffer
+    }
+    *out = w->xr;
+    return RHMC_OK;
+}
+
+// ------------------------------------------------------------------ problem
+struct Problem {
+    int nsys, nshift;
+    double m2;
+    double sigma0[kMaxSys];
+    double off[kMaxSys][kMaxShift];
+    int base[kMaxSys];
+    double tol[kMaxSys];          // relative tolerance per system
+    const double2* b[kMaxSys];    // FP64 sources
+    double2* X;                   // FP64 solutions
+    size_t x_sys, x_shift;        // element strides
+    int mode, K, reliable_blocks, maxiter;
+    bool use_graph;
+    int poll_every;
+};
+
+template <typename VT>
+static VT* vec(void* base, size_t n, size_t idx) {
+    return reinterpret_cast<VT*>(base) + idx * n;
+}
+
+// Enqueue one block of K iterations (+ flush, + optional reliable update).
+template <typename VT>
+static rhmc_status enqueue_block(const rhmc_gauge* g, Workspace* w, const Problem& pb,
+                                 bool reliable, hipStream_t s) {
+    const size_t n = w->n;
+    const int ns = pb.nsys;
+    const int nlinks = (int)(4 * g->lat.V);
+    const bool f32 = std::is_same<VT, float2>::value;
+
+    DslashArgs<VT> d{};
+    d.g = g->lat.geom;
+    d.nrhs = ns;
+    d.skip = &w->st->sys[0].done;
+    d.skip_stride = (int)(sizeof(SysScalars) / sizeof(int));
+    d.all_done = &w->st->all_done;
+    d.partial = w->partial;
+    d.counter = w->counters + 0;
+    d.fin_state = w->st;
+    DslashArgs<VT> a = d;
+    d.out_par = 1;
+    d.finalize = kFinNone;
+    a.out_par = 0;
+    a.finalize = kFinAlpha;
+    a.counter = w->counters + 1;
+    for (int j = 0; j < ns; ++j) {
+        d.in[j] = vec<VT>(w->p, n, j);
+        d.out[j] = vec<VT>(w->t, n, j);
+        a.in[j] = vec<VT>(w->t, n, j);
+        a.self[j] = vec<VT>(w->p, n, j);
+        a.out[j] = vec<VT>(w->Ap, n, j);
+        a.c[j] = pb.m2 + pb.sigma0[j];
+    }
+    for (int q = 0; q < pb.K; ++q) {
+        if constexpr (std::is_same<VT, float2>::value) {
+            RHMC_HIP_TRY(launch_dslash32(g->u32, nlinks, d, kModeD, s));
+            RHMC_HIP_TRY(launch_dslash32(g->u32, nlinks, a, kModeA, s));
+        } else {
+            RHMC_HIP_TRY(launch_dslash64(g->u64, nlinks, d, kModeD, s));
+            RHMC_HIP_TRY(launch_dslash64(g->u64, nlinks, a, kModeA, s));
+        }
+        VecArgs<VT> r{};
+        r.state = w->st;
+        r.n = n;
+        r.partial = w->partial;
+        r.counter = w->counters + 2;
+        for (int j = 0; j < ns; ++j) {
+            r.x[j] = vec<VT>(w->ring, n, (size_t)q * ns + j);
+            r.y[j] = vec<VT>(w->Ap, n, j);
+            r.z[j] = vec<VT>(w->ring, n, (size_t)(q + 1) * ns + j);
+        }
+        RHMC_HIP_TRY(launch_rupdate<VT>(r, ns, s));
+        VecArgs<VT> p{};
+        p.state = w->st;
+        p.n = n;
+        for (int j = 0; j < ns; ++j) {
+            p.x[j] = vec<VT>(w->ring, n, (size_t)(q + 1) * ns + j);
+            p.y[j] = vec<VT>(w->p, n, j);
+        }
+        RHMC_HIP_TRY(launch_pupdate<VT>(p, ns, s));
+    }
+    FlushArgs<VT> f{};
+    f.state = w->st;
+    f.n = n;
+    f.nshift = pb.nshift;
+    for (int l = 0; l <= pb.K; ++l)
+        for (int j = 0; j < ns; ++j) f.ring[l][j] = vec<VT>(w->ring, n, (size_t)l * ns + j);
+    f.P = reinterpret_cast<VT*>(w->P);
+    f.X = pb.X;
+    f.x_sys = pb.x_sys;
+    f.x_shift = pb.x_shift;
+    f.counter = w->counters + 3;
+    RHMC_HIP_TRY(launch_flush<VT>(f, ns, pb.K, s));
+
+    if (reliable) {
+        // r = b - (m^2 + sigma_0) x_0 + D_eo D_oe x_0 in FP64, stored into r(k0)
+        DslashArgs<double2> d64{};
+        d64.g = g->lat.geom;
+        d64.nrhs = ns;
+        d64.skip = d.skip;
+        d64.skip_stride = d.skip_stride;
+        d64.all_done = d.all_done;
+        d64.out_par = 1;
+        DslashArgs<double2> r64 = d64;
+        r64.out_par = 0;
+        r64.partial = w->partial;
+        r64.counter = w->counters + 4;
+        r64.finalize = kFinReliable;
+        r64.fin_state = w->st;
+        for (int j = 0; j < ns; ++j) {
+            const double2* x0 = pb.X + j * pb.x_sys + pb.base[j] * pb.x_shift;
+            d64.in[j] = x0;
+            d64.out[j] = w->t64 + (size_t)j * n;
+            r64.in[j] = w->t64 + (size_t)j * n;
+            r64.self[j] = x0;
+            r64.rhs[j] = pb.b[j];
+            r64.c[j] = pb.m2 + pb.sigma0[j];
+            r64.out[j] = nullptr;
+            if (f32) r64.out32[j] = reinterpret_cast<float2*>(vec<VT>(w->ring, n, j));
+        }
+        if (!f32)
+            for (int j = 0; j < ns; ++j) r64.out[j] = reinterpret_cast<double2*>(vec<VT>(w->ring, n, j));
+        RHMC_HIP_TRY(launch_dslash64(g->u64, nlinks, d64, kModeD, s));
+        RHMC_HIP_TRY(launch_dslash64(g->u64, nlinks, r64, kModeResid, s));
+    }
+    return RHMC_OK;
+}
+
+template <typename VT>
+static rhmc_status get_graph(rhmc_gauge* g, Workspace* w, const Problem& pb, bool reliable,
+                             hipGraphExec_t* out) {
+    GraphKey k;
+    std::memset(static_cast<void*>(&k), 0, sizeof(k));
+    k.nsys = pb.nsys;
+    k.nshift = pb.nshift;
+    k.K = pb.K;
+    k.mode = pb.mode;
+    k.reliable = reliable;
+    for (int j = 0; j < pb.nsys; ++j) {
+        k.b[j] = pb.b[j];
+        k.c[j] = pb.m2 + pb.sigma0[j];
+        k.base[j] = pb.base[j];
+    }
+    k.x = pb.X;
+    k.x_sys = pb.x_sys;
+    k.x_shift = pb.x_shift;
+    for (auto& cg : w->graphs)
+        if (cg.exec && cg.key == k) {
+            *out = cg.exec;
+            return RHMC_OK;
+        }
+    CachedGraph& slot = w->graphs[w->graph_next];
+    w->graph_next = (w->graph_next + 1) % 4;
+    if (slot.exec) hipGraphExecDestroy(slot.exec);
+    slot.exec = nullptr;
+    hipGraph_t graph = nullptr;
+    RHMC_HIP_TRY(hipStreamBeginCapture(w->cap, hipStreamCaptureModeThreadLocal));
+    rhmc_status st = enqueue_block<VT>(g, w, pb, reliable, w->cap);
+    hipError_t e = hipStreamEndCapture(w->cap, &graph);
+    if (st != RHMC_OK) {
+        if (graph) hipGraphDestroy(graph);
+        return st;
+    }
+    RHMC_HIP_TRY(e);
+    e = hipGraphInstantiate(&slot.exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    RHMC_HIP_TRY(e);
+    slot.key = k;
+    *out = slot.exec;
+    return RHMC_OK;
+}
+
+// Core shared Krylov solve; X receives every shifted solution.
+template <typename VT>
+static rhmc_status run_krylov(rhmc_gauge* g, const Problem& pb, hipStream_t s, int* iters_out,
+                              int* reliable_out) {
+    RHMC_TRY(ensure_workspace(g, pb.nsys, pb.nshift, pb.K));
+    Workspace* w = g->ws;
+    const size_t n = w->n;
+    SolverState* h = w->hst;
+    std::memset(h, 0, sizeof(SolverState));
+    h->nsys = pb.nsys;
+    h->nshift = pb.nshift;
+    h->first_block = 1;
+    h->maxiter = pb.maxiter;
+    for (int j = 0; j < pb.nsys; ++j) {
+        h->sys[j].tolb = pb.tol[j];
+        h->sys[j].base = pb.base[j];
+        for (int i = 0; i < pb.nshift; ++i) {
+            ShiftScalars& q = h->sh[j][i];
+            q.off = pb.off[j][i];
+            q.zeta = q.zeta_prev = q.zeta_next = 1.0;
+            q.c = 1.0;
+            q.active = q.block_active = 1;
+        }
+    }
+    RHMC_HIP_TRY(hipMemcpyAsync(w->st, h, sizeof(SolverState), hipMemcpyHostToDevice, s));
+    VecArgs<VT> st{};
+    st.state = w->st;
+    st.n = n;
+    st.partial = w->partial;
+    st.counter = w->counters + 5;
+    for (int j = 0; j < pb.nsys; ++j) {
+        st.b64[j] = pb.b[j];
+        st.x[j] = vec<VT>(w->ring, n, j);
+        st.y[j] = vec<VT>(w->p, n, j);
+    }
+    RHMC_HIP_TRY(launch_start<VT>(st, pb.nsys, s));
+    RHMC_HIP_TRY(hipMemcpyAsync(h, w->st, sizeof(SolverState), hipMemcpyDeviceToHost, s));
+    RHMC_HIP_TRY(hipStreamSynchronize(s));
+    for (int j = 0; j < pb.nsys; ++j) {
+        const double bn = h->sys[j].bnorm;
+        if (!std::isfinite(bn)) {
+            set_error("source holds NaN or Inf");
+            return RHMC_ERR_NONFINITE;
+        }
+        if (bn == 0.0)
+            for (int i = 0; i < pb.nshift; ++i)
+                RHMC_HIP_TRY(hipMemsetAsync(pb.X + j * pb.x_sys + i * pb.x_shift, 0,
+                                            n * sizeof(double2), s));
+    }
+
+    hipGraphExec_t gb = nullptr, gr = nullptr;
+    if (pb.use_graph) {
+        RHMC_TRY(get_graph<VT>(g, w, pb, false, &gb));
+        if (pb.mode == RHMC_MODE_MIXED) RHMC_TRY(get_graph<VT>(g, w, pb, true, &gr));
+    }
+    const int max_blocks = (pb.maxiter + pb.K - 1) / pb.K + 1;
+    int launched = 0;
+    bool done = h->all_done != 0;
+    int pending = -1;  // block index whose flag copy is in flight
+    while (!done && launched < max_blocks) {
+        const bool rel = pb.mode == RHMC_MODE_MIXED && ((launched + 1) % pb.reliable_blocks == 0);
+        if (pb.use_graph) {
+            RHMC_HIP_TRY(hipGraphLaunch(rel ? gr : gb, s));
+        } else {
+            RHMC_TRY(enqueue_block<VT>(g, w, pb, rel, s));
+        }
+        ++launched;
+        if (launched % pb.poll_every == 0 || launched == max_blocks) {
+            const int slot = (launched / pb.poll_every) & 1;
+            RHMC_HIP_TRY(hipMemcpyAsync(&w->flags_host[slot], &w->st->all_done, sizeof(int),
+                                        hipMemcpyDeviceToHost, s));
+            RHMC_HIP_TRY(hipEventRecord(w->ev[slot], s));
+            if (pending >= 0) {
+                RHMC_HIP_TRY(hipEventSynchronize(w->ev[pending]));
+                done = w->flags_host[pending] != 0;
+            }
+            pending = slot;
+        }
+    }
+    RHMC_HIP_TRY(hipMemcpyAsync(h, w->st, sizeof(SolverState), hipMemcpyDeviceToHost, s));
+    RHMC_HIP_TRY(hipStreamSynchronize(s));
+    *iters_out = h->iter;
+    *reliable_out = h->reliable_count;
+    return RHMC_OK;
+}
+
+// FP64 true residuals ||b_j - (A + sigma_ji) x_ji||^2 for a list of (j, i);
+// optionally stores the residual vectors (at most kMaxSys per call).
+static rhmc_status true_residuals(rhmc_gauge* g, const Problem& pb, const std::vector<int>& list,
+                                  double* out2, double2* store, hipStream_t s) {
+    Workspace* w = g->ws;
+    const size_t n = w->n;
+    const int nlinks = (int)(4 * g->lat.V);
+    for (size_t c0 = 0; c0 < list.size(); c0 += kMaxSys) {
+        const int cnt = (int)std::min<size_t>(kMaxSys, list.size() - c0);
+        DslashArgs<double2> d{};
+        d.g = g->lat.geom;
+        d.nrhs = cnt;
+        d.out_par = 1;
+        DslashArgs<double2> r = d;
+        r.out_par = 0;
+        r.partial = w->partial;
+        r.counter = w->counters + 6;
+        r.finalize = kFinNorms;
+        r.out_sums = w->sums;
+        for (int k = 0; k < cnt; ++k) {
+            const int p = list[c0 + k];
+            const int j = p / pb.nshift, i = p % pb.nshift;
+            const double2* x = pb.X + j * pb.x_sys + i * pb.x_shift;
+            d.in[k] = x;
+            d.out[k] = w->t64 + (size_t)k * n;
+            r.in[k] = w->t64 + (size_t)k * n;
+            r.self[k] = x;
+            r.rhs[k] = pb.b[j];
+            r.c[k] = pb.m2 + pb.sigma0[j] + pb.off[j][i];
+            r.out[k] = store ? store + (size_t)k * n : nullptr;
+        }
+        RHMC_HIP_TRY(launch_dslash64(g->u64, nlinks, d, kModeD, s));
+        RHMC_HIP_TRY(launch_dslash64(g->u64, nlinks, r, kModeResid, s));
+        RHMC_HIP_TRY(hipMemcpyAsync(w->sums_host, w->sums, sizeof(double) * cnt,
+                                    hipMemcpyDeviceToHost, s));
+        RHMC_HIP_TRY(hipStreamSynchronize(s));
+        for (int k = 0; k < cnt; ++k) out2[c0 + k] = w->sums_host[k];
+    }
+    return RHMC_OK;
+}
+
+static rhmc_status solve_impl(rhmc_gauge* g, Problem pb, const rhmc_solver_params& prm,
+                              rhmc_solver_stats* stats, hipStream_t s) {
+    const auto t0 = std::chrono::steady_clock::now();
+    int iters = 0, rel = 0;
+    if (pb.mode == RHMC_MODE_MIXED)
+        RHMC_TRY(run_krylov<float2>(g, pb, s, &iters, &rel));
+    else
+        RHMC_TRY(run_krylov<double2>(g, pb, s, &iters, &rel));
+    Workspace* w = g->ws;
+    const SolverState hs = *w->hst;
+    const int total = pb.nsys * pb.nshift;
+    std::vector<int> conv(total), refine_it(total, 0);
+    for (int j = 0; j < pb.nsys; ++j)
+        for (int i = 0; i < pb.nshift; ++i) {
+            const ShiftScalars& q = hs.sh[j][i];
+            conv[j * pb.nshift + i] = q.active ? hs.sys[j].iters : q.conv_iter;
+        }
+    double bnorm[kMaxSys];
+    for (int j = 0; j < pb.nsys; ++j) bnorm[j] = hs.sys[j].bnorm;
+
+    std::vector<int> all(total);
+    for (int p = 0; p < total; ++p) all[p] = p;
+    std::vector<double> res2(total);
+    RHMC_TRY(true_residuals(g, pb, all, res2.data(), nullptr, s));
+    std::vector<double> res(total);
+    auto relres = [&](int p) {
+        const int j = p / pb.nshift;
+        return bnorm[j] > 0 ? std::sqrt(res2[p]) / bnorm[j] : 0.0;
+    };
+    for (int p = 0; p < total; ++p) res[p] = relres(p);
+
+    int rounds = 0;
+    const double tol = prm.tol;
+    while (prm.refine && rounds < 4) {
+        std::vector<int> bad;
+        for (int p = 0; p < total; ++p)
+            if (!(res[p] <= tol)) bad.push_back(p);
+        if (bad.empty()) break;
+        ++rounds;
+        for (size_t c0 = 0; c0 < bad.size(); c0 += kMaxSys) {
+            const int cnt = (int)std::min<size_t>(kMaxSys, bad.size() - c0);
+            std::vector<int> chunk(bad.begin() + c0, bad.begin() + c0 + cnt);
+            std::vector<double> r2(cnt);
+            RHMC_TRY(true_residuals(g, pb, chunk, r2.data(), w->rb, s));
+            Problem rp = pb;
+            rp.nsys = cnt;
+            rp.nshift = 1;
+            rp.X = w->rx;
+            rp.x_sys = w->n;
+            rp.x_shift = 0;
+            for (int k = 0; k < cnt; ++k) {
+                const int p = chunk[k];
+                const int j = p / pb.nshift, i = p % pb.nshift;
+                rp.sigma0[k] = pb.sigma0[j] + pb.off[j][i];
+                rp.off[k][0] = 0.0;
+                rp.base[k] = 0;
+                rp.b[k] = w->rb + (size_t)k * w->n;
+                const double rn = std::sqrt(r2[k]);
+                rp.tol[k] = rn > 0 ? std::min(0.5, 0.5 * tol * bnorm[j] / rn) : 0.5;
+            }
+            int it2 = 0, rel2 = 0;
+            if (pb.mode == RHMC_MODE_MIXED)
+                RHMC_TRY(run_krylov<float2>(g, rp, s, &it2, &rel2));
+            else
+                RHMC_TRY(run_krylov<double2>(g, rp, s, &it2, &rel2));
+            rel += rel2;
+            AddArgs ad{};
+            ad.n = w->n;
+            for (int k = 0; k < cnt; ++k) {
+                const int p = chunk[k];
+                const int j = p / pb.nshift, i = p % pb.nshift;
+                ad.x[k] = w->rx + (size_t)k * w->n;
+                ad.y[k] = pb.X + j * pb.x_sys + i * pb.x_shift;
+                refine_it[p] += w->hst->sys[k].iters;
+            }
+            RHMC_HIP_TRY(launch_add(ad, cnt, s));
+        }
+        RHMC_TRY(true_residuals(g, pb, bad, res2.data(), nullptr, s));
+        for (size_t k = 0; k < bad.size(); ++k) {
+            const int p = bad[k];
+            const int j = p / pb.nshift;
+            res[p] = bnorm[j] > 0 ? std::sqrt(res2[k]) / bnorm[j] : 0.0;
+        }
+    }
+    RHMC_HIP_TRY(hipStreamSynchronize(s));
+    const auto t1 = std::chrono::steady_clock::now();
+
+    double worst = 0.0;
+    bool ok = true;
+    for (int p = 0; p < total; ++p) {
+        worst = std::max(worst, res[p]);
+        if (!(res[p] <= tol)) ok = false;
+    }
+    if (stats) {
+        for (int p = 0; p < total; ++p) {
+            if (stats->iterations) stats->iterations[p] = conv[p];
+            if (stats->true_residual) stats->true_residual[p] = res[p];
+            if (stats->refine_iterations) stats->refine_iterations[p] = refine_it[p];
+        }
+        stats->total_iterations = iters;
+        stats->reliable_updates = rel;
+        stats->refine_rounds = rounds;
+        stats->time_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+        stats->max_true_residual = worst;
+    }
+    for (int p = 0; p < total; ++p)
+        if (!std::isfinite(res[p])) {
+            set_error("solution is not finite");
+            return RHMC_ERR_NONFINITE;
+        }
+    if (!ok) {
+        set_error("some shift did not reach the requested tolerance");
+        return RHMC_ERR_NOT_CONVERGED;
+    }
+    return RHMC_OK;
+}
+
+rhmc_status multishift(rhmc_gauge* g, double m, int nshift, const double* shifts, int nrhs,
+                       const double2* b, double2* x, size_t x_sys, size_t x_shift,
+                       const rhmc_solver_params& prm, rhmc_solver_stats* stats, hipStream_t s) {
+    const size_t n = (size_t)3 * g->lat.Vh;
+    double smin = shifts[0];
+    int base = 0;
+    for (int i = 1; i < nshift; ++i)
+        if (shifts[i] < smin) {
+            smin = shifts[i];
+            base = i;
+        }
+    rhmc_solver_stats acc{};
+    const int K = std::max(1, std::min(kMaxBlockLen, prm.block));
+    // process the right-hand sides in groups of kMaxSys
+    for (int r0 = 0; r0 < nrhs; r0 += kMaxSys) {
+        const int cnt = std::min(kMaxSys, nrhs - r0);
+        Problem pb{};
+        pb.nsys = cnt;
+        pb.nshift = nshift;
+        pb.m2 = m * m;
+        for (int j = 0; j < cnt; ++j) {
+            pb.sigma0[j] = smin;
+            pb.base[j] = base;
+            pb.tol[j] = prm.tol;
+            pb.b[j] = b + (size_t)(r0 + j) * n;
+            for (int i = 0; i < nshift; ++i) pb.off[j][i] = shifts[i] - smin;
+        }
+        pb.X = x + (size_t)r0 * x_sys;
+        pb.x_sys = x_sys;
+        pb.x_shift = x_shift;
+        pb.mode = prm.mode;
+        pb.K = K;
+        pb.reliable_blocks = std::max(1, (prm.reliable_every + K - 1) / K);
+        pb.maxiter = prm.maxiter;
+        pb.use_graph = prm.use_graph != 0;
+        pb.poll_every = prm.poll_every > 0 ? prm.poll_every : 1;
+        rhmc_solver_stats st{};
+        if (stats) {
+            st.iterations = stats->iterations ? stats->iterations + (size_t)r0 * nshift : nullptr;
+            st.true_residual = stats->true_residual ? stats->true_residual + (size_t)r0 * nshift : nullptr;
+            st.refine_iterations =
+                stats->refine_iterations ? stats->refine_iterations + (size_t)r0 * nshift : nullptr;
+        }
+        const rhmc_status rs = solve_impl(g, pb, prm, &st, s);
+        acc.total_iterations = std::max(acc.total_iterations, st.total_iterations);
+        acc.reliable_updates += st.reliable_updates;
+        acc.refine_rounds = std::max(acc.refine_rounds, st.refine_rounds);
+        acc.time_ms += st.time_ms;
+        acc.max_true_residual = std::max(acc.max_true_residual, st.max_true_residual);
+        if (stats) {
+            stats->total_iterations = acc.total_iterations;
+            stats->reliable_updates = acc.reliable_updates;
+            stats->refine_rounds = acc.refine_rounds;
+            stats->time_ms = acc.time_ms;
+            stats->max_true_residual = acc.max_true_residual;
+        }
+        if (rs != RHMC_OK) return rs;
+    }
+    return RHMC_OK;
+}
+
+rhmc_status rational(rhmc_gauge* g, double m, const rhmc_rational* rat, int nrhs,
+                     const double2* b, double2* y, const rhmc_solver_params& prm,
+                     rhmc_solver_stats* stats, hipStream_t s) {
+    const size_t n = (size_t)3 * g->lat.Vh;
+    const int np = rat->npole;
+    const int K = std::max(1, std::min(kMaxBlockLen, prm.block));
+    RHMC_TRY(ensure_workspace(g, std::min(nrhs, kMaxSys), np, K));
+    double2* xr = nullptr;
+    RHMC_TRY(ensure_rational_buffer(g, (size_t)std::min(nrhs, kMaxSys) * np, &xr));
+    for (int r0 = 0; r0 < nrhs; r0 += kMaxSys) {
+        const int cnt = std::min(kMaxSys, nrhs - r0);
+        rhmc_solver_stats st{};
+        if (stats) {
+            st.iterations = stats->iterations ? stats->iterations + (size_t)r0 * np : nullptr;
+            st.true_residual = stats->true_residual ? stats->true_residual + (size_t)r0 * np : nullptr;
+            st.refine_iterations =
+                stats->refine_iterations ? stats->refine_iterations + (size_t)r0 * np : nullptr;
+        }
+        const rhmc_status rs = multishift(g, m, np, rat->beta, cnt, b + (size_t)r0 * n, xr,
+                                          (size_t)np * n, n, prm, &st, s);
+        if (stats) {
+            stats->total_iterations = std::max(stats->total_iterations, st.total_iterations);
+            stats->reliable_updates += st.reliable_updates;
+            stats->refine_rounds = std::max(stats->refine_rounds, st.refine_rounds);
+            stats->time_ms += st.time_ms;
+            stats->max_true_residual = std::max(stats->max_true_residual, st.max_true_residual);
+        }
+        if (rs != RHMC_OK && rs != RHMC_ERR_NOT_CONVERGED) return rs;
+        CombineArgs c{};
+        c.n = n;
+        c.nterm = np;
+        c.alpha0 = rat->alpha0;
+        for (int i = 0; i < np; ++i) c.alpha[i] = rat->alpha[i];
+        c.x_stride = n;
+        for (int j = 0; j < cnt; ++j) {
+            c.b[j] = b + (size_t)(r0 + j) * n;
+            c.x[j] = xr + (size_t)j * np * n;
+            c.y[j] = y + (size_t)(r0 + j) * n;
+        }
+        RHMC_HIP_TRY(launch_combine(c, cnt, s));
+        if (rs != RHMC_OK) return rs;
+    }
+    RHMC_HIP_TRY(hipStreamSynchronize(s));
+    return RHMC_OK;
+}
+
+}  // namespace rhmc

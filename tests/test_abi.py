@@ -1,0 +1,75 @@
+"""The C-ABI library loads on the CPU host and exports every declared symbol.
+
+No compute call is made here (there is no GPU); host-side validation paths
+that touch no device are exercised.
+"""
+
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "rhmc.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rhmc_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def rh():
+    from paper_1106_5673_amd import rhmc
+
+    if not os.path.exists(rhmc.LIB_PATH):
+        pytest.skip("librhmc.so not built")
+    rhmc.load()
+    return rhmc
+
+
+def test_every_declared_symbol_is_exported(rh):
+    lib = rh.load()
+    names = _declared()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(rh.EXPORTED) == names
+
+
+def test_status_strings(rh):
+    assert rh.rhmc_status_string(rh.RHMC_OK) == "ok"
+    assert rh.rhmc_status_string(rh.RHMC_ERR_NOT_CONVERGED) == "not converged"
+
+
+def test_params_defaults(rh):
+    p = rh.rhmc_solver_params_default()
+    assert p.tol == 1e-10 and p.reliable_every == 50 and p.block == 10 and p.use_graph == 1
+
+
+@pytest.mark.parametrize("L", [(4, 4, 3, 4), (1, 4, 4, 4), (0, 2, 2, 2)])
+def test_lattice_rejects_odd_extents(rh, L):
+    with pytest.raises(rh.RhmcError) as e:
+        rh.rhmc_lattice_create(L)
+    assert e.value.status == rh.RHMC_ERR_INVALID_ARG
+    assert "even" in rh.rhmc_last_error()
+
+
+def test_lattice_rejects_bad_boundary(rh):
+    with pytest.raises(rh.RhmcError):
+        rh.rhmc_lattice_create((4, 4, 4, 4), 0)
+
+
+def test_lattice_create_destroy(rh):
+    lat = rh.rhmc_lattice_create((4, 4, 4, 8), -1)
+    assert lat.Vh == 256
+
+
+def test_product_path_has_no_oracle_import():
+    """The binding and the build never reach the oracle (test infrastructure)."""
+    pkg = os.path.join(ROOT, "paper_1106_5673_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in txt and "from oracle" not in txt, f

@@ -1,0 +1,205 @@
+"""GPU parity of the hopping term, A = m^2 - D_eo D_oe and the neighbour tables.
+
+Everything goes through the C ABI (ctypes binding) and is compared with the
+FP64 CPU oracle on the same seeded inputs:
+  * neighbour indices and hop signs: bit-exact;
+  * point sources on unit links: bit-exact (single products of +-1/2);
+  * random SU(3) fields, FP64 path: max |gpu - oracle| <= 1e-13 * max |oracle|,
+    well inside the 1e-12 relative budget (FMA contraction and summation order
+    differ, each output is a sum of 24 products);
+  * FP32 path with 12-real links: |gpu - oracle| <= 32 * 2^-24 * scale per
+    element, scale = 1/2 sum over the 8 hops of |U| |psi| (rounding of links,
+    vectors, the third-row rebuild and 24 accumulations).
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import dirac, lattice
+
+pytestmark = pytest.mark.gpu
+
+LATTICES = [(4, 4, 4, 4), (2, 4, 6, 8), (6, 2, 4, 2), (8, 8, 8, 6), (16, 16, 16, 4)]
+
+
+@pytest.fixture(scope="module")
+def rh():
+    import torch
+
+    from paper_1106_5673_amd import rhmc
+
+    rhmc.load()
+    assert torch.cuda.is_available()
+    return rhmc
+
+
+def _dev():
+    import torch
+
+    return torch.device("cuda:0")
+
+
+def _to(x):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(x)).to(_dev())
+
+
+def _rand_vec(rng, nrhs, Vh):
+    return (rng.standard_normal((nrhs, 3, Vh)) + 1j * rng.standard_normal((nrhs, 3, Vh)))
+
+
+@pytest.mark.parametrize("L", LATTICES + [(2, 2, 2, 2)])
+@pytest.mark.parametrize("t_bc", [-1, 1])
+def test_neighbors_bit_exact(rh, L, t_bc):
+    lat = rh.rhmc_lattice_create(L, t_bc)
+    for par in (0, 1):
+        nb, sg = rh.rhmc_debug_neighbors(lat, par)
+        assert np.array_equal(nb, lattice.neighbor_table(L, par))
+        x, y, z, t = lattice.eo_coordinates(L, par)
+        bc = lattice.boundary_sign_table(L, par, t_bc)
+        eta = np.stack([np.ones_like(x), (-1) ** x, (-1) ** (x + y), (-1) ** (x + y + z)], axis=1)
+        expect = np.concatenate([eta, eta], axis=1) * bc
+        assert np.array_equal(sg, expect)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_point_sources_unit_links_bit_exact(rh, prec):
+    import torch
+
+    L = (4, 4, 4, 4)
+    U = synth.unit_gauge(L)
+    lat = rh.rhmc_lattice_create(L, -1)
+    g = rh.rhmc_gauge_create(lat, U)
+    Vh = lat.Vh
+    p = rh.RHMC_PREC_FP64 if prec == "fp64" else rh.RHMC_PREC_FP32
+    cdt = np.complex128 if prec == "fp64" else np.complex64
+    srcs = [(0, 0, 5), (1, 2, 77), (2, 1, 127), (0, 0, 0)]
+    for out_par in (0, 1):
+        v = np.zeros((len(srcs), 3, Vh), dtype=cdt)
+        for k, (c, _, eo) in enumerate(srcs):
+            v[k, c, eo] = 1.0
+        vin = _to(v)
+        vout = torch.empty_like(vin)
+        rh.rhmc_dslash_eo(g, out_par, p, len(srcs), vin, vout)
+        torch.cuda.synchronize()
+        ref = dirac.dslash(U, v.astype(np.complex128), out_par)
+        assert np.array_equal(vout.cpu().numpy().astype(np.complex128), ref)
+    g.close()
+
+
+def _abs_scale(U, v, out_par):
+    """1/2 sum over the 8 hops of |U| |psi| per output element (error scale)."""
+    L = dirac.lattice_of(U)
+    full = np.abs(lattice.embed(v, L, 1 - out_par))
+    A = np.abs(U)
+    out = np.zeros(full.shape)
+    for mu in range(4):
+        ax = lattice.AXIS[mu]
+        out += np.einsum("...ij,...j->...i", A[..., mu, :, :], np.roll(full, -1, axis=ax))
+        Ab = np.roll(A[..., mu, :, :], 1, axis=ax - 1)
+        out += np.einsum("...ji,...j->...i", Ab, np.roll(full, 1, axis=ax))
+    return 0.5 * lattice.restrict(out, L, out_par)
+
+
+@pytest.mark.parametrize("L", LATTICES)
+@pytest.mark.parametrize("nrhs", [1, 3])
+def test_dslash_random_fields(rh, L, nrhs):
+    import torch
+
+    t_bc = -1
+    U = synth.gauge_field(L, 0.7, 4000 + sum(L))
+    lat = rh.rhmc_lattice_create(L, t_bc)
+    g = rh.rhmc_gauge_create(lat, U)
+    rng = np.random.default_rng(11)
+    for out_par in (0, 1):
+        v = _rand_vec(rng, nrhs, lat.Vh)
+        ref = dirac.dslash(U, v, out_par, t_bc)
+        vin = _to(v)
+        vout = torch.empty_like(vin)
+        rh.rhmc_dslash_eo(g, out_par, rh.RHMC_PREC_FP64, nrhs, vin, vout)
+        torch.cuda.synchronize()
+        got = vout.cpu().numpy()
+        assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+        # FP32 with 12-real links
+        v32 = v.astype(np.complex64)
+        ref32 = dirac.dslash(U, v32.astype(np.complex128), out_par, t_bc)
+        vin = _to(v32)
+        vout = torch.empty_like(vin)
+        rh.rhmc_dslash_eo(g, out_par, rh.RHMC_PREC_FP32, nrhs, vin, vout)
+        torch.cuda.synchronize()
+        got32 = vout.cpu().numpy().astype(np.complex128)
+        scale = _abs_scale(U, v32.astype(np.complex128), out_par)
+        err = np.abs(got32 - ref32)
+        assert np.all(err.real <= 32 * 2.0 ** -24 * scale + 1e-30)
+    g.close()
+
+
+@pytest.mark.parametrize("nrhs", [2, 8, 11])
+def test_multi_rhs_matches_single(rh, nrhs):
+    """Batched right-hand sides give the same answer as one at a time."""
+    import torch
+
+    L = (8, 8, 8, 6)
+    U = synth.gauge_field(L, 0.7, 4100)
+    lat = rh.rhmc_lattice_create(L, -1)
+    g = rh.rhmc_gauge_create(lat, U)
+    rng = np.random.default_rng(12)
+    v = _rand_vec(rng, nrhs, lat.Vh)
+    for prec, cdt, tol in ((rh.RHMC_PREC_FP64, np.complex128, 0.0),
+                           (rh.RHMC_PREC_FP32, np.complex64, 0.0)):
+        vin = _to(v.astype(cdt))
+        vout = torch.empty_like(vin)
+        rh.rhmc_dslash_eo(g, 0, prec, nrhs, vin, vout)
+        one = torch.empty_like(vin[0:1])
+        torch.cuda.synchronize()
+        for r in range(nrhs):
+            rh.rhmc_dslash_eo(g, 0, prec, 1, vin[r:r + 1].contiguous(), one)
+            torch.cuda.synchronize()
+            d = (vout[r] - one[0]).abs().max().item()
+            s = one.abs().max().item()
+            assert d <= max(tol, 1e-15 if cdt == np.complex128 else 1e-6) * s
+    g.close()
+
+
+@pytest.mark.parametrize("L", [(4, 4, 4, 4), (16, 16, 16, 4)])
+def test_mdagm_matches_oracle(rh, L):
+    import torch
+
+    m = 0.02
+    U = synth.gauge_field(L, 0.5, 4200)
+    lat = rh.rhmc_lattice_create(L, -1)
+    g = rh.rhmc_gauge_create(lat, U)
+    rng = np.random.default_rng(13)
+    v = _rand_vec(rng, 2, lat.Vh)
+    ref = dirac.mdagm(U, m, v)
+    vin = _to(v)
+    vout = torch.empty_like(vin)
+    rh.rhmc_apply_mdagm(g, m, rh.RHMC_PREC_FP64, 2, vin, vout)
+    torch.cuda.synchronize()
+    got = vout.cpu().numpy()
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+    vin32 = _to(v.astype(np.complex64))
+    vout32 = torch.empty_like(vin32)
+    rh.rhmc_apply_mdagm(g, m, rh.RHMC_PREC_FP32, 2, vin32, vout32)
+    torch.cuda.synchronize()
+    got32 = vout32.cpu().numpy().astype(np.complex128)
+    assert np.linalg.norm(got32 - ref) <= 1e-5 * np.linalg.norm(ref)
+    g.close()
+
+
+def test_invalid_arguments(rh):
+    import torch
+
+    with pytest.raises(rh.RhmcError) as e:
+        rh.rhmc_lattice_create((4, 4, 3, 4))
+    assert e.value.status == rh.RHMC_ERR_INVALID_ARG
+    L = (4, 4, 4, 4)
+    lat = rh.rhmc_lattice_create(L)
+    g = rh.rhmc_gauge_create(lat, synth.unit_gauge(L), flags=rh.RHMC_LINKS_FP64_18)
+    v = torch.zeros((1, 3, lat.Vh), dtype=torch.complex64, device=_dev())
+    with pytest.raises(rh.RhmcError) as e:
+        rh.rhmc_dslash_eo(g, 0, rh.RHMC_PREC_FP32, 1, v, torch.empty_like(v))
+    assert e.value.status == rh.RHMC_ERR_INVALID_ARG
+    g.close()
