@@ -40,29 +40,12 @@ static rhmc_status tmp_odd(rhmc_gauge* g, size_t bytes, void** out) {
     return RHMC_OK;
 }
 
-static rhmc_status scratch_partials(rhmc_gauge* g, double** out) {
-    // per-rhs partial sums of a kModeA launch that nobody reads
-    static thread_local std::vector<std::pair<int, double*>> cache;
-    for (auto& c : cache)
-        if (c.first == g->device) {
-            *out = c.second;
-            return RHMC_OK;
-        }
-    double* p = nullptr;
-    const size_t nblk = (size_t)g->lat.Vh / kBlock + 2;
-    RHMC_HIP_TRY(hipMalloc(&p, sizeof(double) * kMaxSys * nblk * 2));
-    cache.emplace_back(g->device, p);
-    *out = p;
-    return RHMC_OK;
-}
-
 template <typename VT>
 static rhmc_status hop(rhmc_gauge* g, int out_par, rhmc_prec prec, int nrhs, const void* in,
                        void* out, int mode, const void* self, double c, hipStream_t s) {
     const size_t n = (size_t)3 * g->lat.Vh;
     const int nlinks = (int)(4 * g->lat.V);
-    double* partial = nullptr;
-    if (mode == kModeA) RHMC_TRY(scratch_partials(g, &partial));
+    double* partial = g->partial;   // kModeA partial sums nobody reads
     for (int r0 = 0; r0 < nrhs; r0 += kMaxSys) {
         const int cnt = nrhs - r0 < kMaxSys ? nrhs - r0 : kMaxSys;
         DslashArgs<VT> a{};
@@ -192,6 +175,8 @@ rhmc_status rhmc_gauge_create(const rhmc_lattice* lat, const double* links, uint
         e = hipMalloc(&g->u64, nlinks * 9 * sizeof(double2));
     if (e == hipSuccess && (flags & RHMC_LINKS_FP32_12))
         e = hipMalloc(&g->u32, nlinks * 3 * sizeof(float4));
+    if (e == hipSuccess)
+        e = hipMalloc(&g->partial, sizeof(double) * kMaxSys * (size_t)dslash_grid((int)lat->Vh));
     if (e == hipSuccess) e = hipMalloc(&canon, nlinks * 9 * sizeof(double2));
     if (e == hipSuccess)
         e = hipMemcpyAsync(canon, links, nlinks * 9 * sizeof(double2), hipMemcpyHostToDevice, stream);
@@ -214,6 +199,7 @@ void rhmc_gauge_destroy(rhmc_gauge* g) {
     hipFree(g->u64);
     hipFree(g->u32);
     hipFree(g->tmp_odd);
+    hipFree(g->partial);
     delete g;
 }
 

@@ -126,6 +126,7 @@ struct rhmc_gauge {
     float4* u32;   // FP32-12: [3][8*Vh], rows 1-2 as three float4 per link
     void* tmp_odd;           // odd-parity temporary for rhmc_apply_mdagm
     size_t tmp_odd_bytes;
+    double* partial;         // [kMaxSys][hopping grid] block sums of rhmc_apply_mdagm
     rhmc::Workspace* ws;     // solver workspace (lazily created)
 };
 

@@ -46,19 +46,18 @@ struct CachedGraph {
 struct Workspace {
     int device = 0;
     size_t n = 0;          // complex numbers per vector (3*Vh)
-    int cap_sys = 0, cap_shift = 0, cap_K = 0;
-    size_t vec_bytes = 0;  // bytes of one vector at the widest precision used (FP64)
-    // iteration vectors, stored at FP64 width so both modes share the buffers
-    void* ring = nullptr;  // [K+1][nsys] vectors
+    size_t vec_bytes = 0;  // bytes of one vector at FP64 width (both modes share buffers)
+    // iteration vectors; they grow with the problem shape, never shrink
+    void* ring = nullptr;  // [K+1][nsys] stored base residuals
     void* p = nullptr;     // [nsys]
     void* Ap = nullptr;    // [nsys]
     void* t = nullptr;     // [nsys] odd parity
-    void* P = nullptr;     // [nsys][nshift]
+    void* P = nullptr;     // [nsys][nshift] shifted directions
+    size_t ring_cap = 0, p_cap = 0, Ap_cap = 0, t_cap = 0, P_cap = 0;  // bytes
+    // fixed-size buffers, allocated once with the workspace
     double2* t64 = nullptr;    // [kMaxSys] odd parity, FP64
     double2* rb = nullptr;     // [kMaxSys] refinement right-hand sides
     double2* rx = nullptr;     // [kMaxSys] refinement corrections
-    double2* xr = nullptr;     // rational apply: [nsys][nshift] shifted solutions
-    size_t xr_count = 0;
     double* partial = nullptr;
     unsigned* counters = nullptr;  // [8]
     double* sums = nullptr;        // [kMaxSys]
@@ -68,6 +67,9 @@ struct Workspace {
     double* sums_host = nullptr;   // pinned [kMaxSys]
     hipStream_t cap = nullptr;     // capture stream
     hipEvent_t ev[2] = {nullptr, nullptr};
+    // rational apply: [nsys][npole] shifted solutions
+    double2* xr = nullptr;
+    size_t xr_cap = 0;
     CachedGraph graphs[4];
     int graph_next = 0;
 };
@@ -83,19 +85,10 @@ static void free_graphs(Workspace* w) {
 void workspace_destroy(Workspace* w) {
     if (!w) return;
     free_graphs(w);
-    hipFree(w->ring);
-    hipFree(w->p);
-    hipFree(w->Ap);
-    hipFree(w->t);
-    hipFree(w->P);
-    hipFree(w->t64);
-    hipFree(w->rb);
-    hipFree(w->rx);
-    hipFree(w->xr);
-    hipFree(w->partial);
-    hipFree(w->counters);
-    hipFree(w->sums);
-    hipFree(w->st);
+    for (void* p : {w->ring, w->p, w->Ap, w->t, w->P, (void*)w->t64, (void*)w->rb, (void*)w->rx,
+                    (void*)w->xr, (void*)w->partial, (void*)w->counters, (void*)w->sums,
+                    (void*)w->st})
+        hipFree(p);
     hipHostFree(w->hst);
     hipHostFree(w->flags_host);
     hipHostFree(w->sums_host);
@@ -110,61 +103,60 @@ static rhmc_status alloc(void** p, size_t bytes) {
     return RHMC_OK;
 }
 
-// Ensure capacity for nsys systems x nshift shifts with blocks of K.
-static rhmc_status ensure_workspace(rhmc_gauge* g, int nsys, int nshift, int K) {
-    Workspace* w = g->ws;
-    const size_t n = (size_t)3 * g->lat.Vh;
-    if (w && w->cap_sys >= nsys && w->cap_shift >= nshift && w->cap_K >= K) return RHMC_OK;
-    int cs = nsys, csh = nshift, cK = K;
-    if (w) {
-        cs = std::max(cs, w->cap_sys);
-        csh = std::max(csh, w->cap_shift);
-        cK = std::max(cK, w->cap_K);
-        workspace_destroy(w);
-        g->ws = nullptr;
-    }
-    w = new Workspace();
-    g->ws = w;
-    w->device = g->device;
-    w->n = n;
-    w->cap_sys = cs;
-    w->cap_shift = csh;
-    w->cap_K = cK;
-    w->vec_bytes = n * sizeof(double2);
-    const size_t vb = w->vec_bytes;
-    RHMC_TRY(alloc(&w->ring, vb * (cK + 1) * cs));
-    RHMC_TRY(alloc(&w->p, vb * cs));
-    RHMC_TRY(alloc(&w->Ap, vb * cs));
-    RHMC_TRY(alloc(&w->t, vb * cs));
-    RHMC_TRY(alloc(&w->P, vb * cs * csh));
-    RHMC_TRY(alloc((void**)&w->t64, vb * kMaxSys));
-    RHMC_TRY(alloc((void**)&w->rb, vb * kMaxSys));
-    RHMC_TRY(alloc((void**)&w->rx, vb * kMaxSys));
-    const size_t nblk = n / 2 / kBlock + 2;
-    RHMC_TRY(alloc((void**)&w->partial, sizeof(double) * 2 * kMaxSys * nblk));
-    RHMC_TRY(alloc((void**)&w->counters, sizeof(unsigned) * 8));
-    RHMC_HIP_TRY(hipMemset(w->counters, 0, sizeof(unsigned) * 8));
-    RHMC_TRY(alloc((void**)&w->sums, sizeof(double) * kMaxSys));
-    RHMC_TRY(alloc((void**)&w->st, sizeof(SolverState)));
-    RHMC_HIP_TRY(hipHostMalloc((void**)&w->hst, sizeof(SolverState), hipHostMallocDefault));
-    RHMC_HIP_TRY(hipHostMalloc((void**)&w->flags_host, sizeof(int) * 2, hipHostMallocDefault));
-    RHMC_HIP_TRY(hipHostMalloc((void**)&w->sums_host, sizeof(double) * kMaxSys, hipHostMallocDefault));
-    RHMC_HIP_TRY(hipStreamCreateWithFlags(&w->cap, hipStreamNonBlocking));
-    RHMC_HIP_TRY(hipEventCreateWithFlags(&w->ev[0], hipEventDisableTiming));
-    RHMC_HIP_TRY(hipEventCreateWithFlags(&w->ev[1], hipEventDisableTiming));
+// Grow one buffer to at least `need` bytes.  Captured graphs hold the old
+// address, so they are dropped; pointers held by a caller of this function
+// into *other* buffers stay valid.
+static rhmc_status grow(Workspace* w, void** buf, size_t* cap, size_t need) {
+    if (*cap >= need) return RHMC_OK;
+    free_graphs(w);
+    hipFree(*buf);
+    *buf = nullptr;
+    *cap = 0;
+    RHMC_TRY(alloc(buf, need));
+    *cap = need;
     return RHMC_OK;
 }
 
-rhmc_status ensure_rational_buffer(rhmc_gauge* g, size_t nvec, double2** out) {
+// Ensure room for nsys systems x nshift shifts with blocks of K.  The
+// workspace object and its fixed-size buffers are created once per gauge
+// object and never freed before rhmc_gauge_destroy.
+static rhmc_status ensure_workspace(rhmc_gauge* g, int nsys, int nshift, int K) {
     Workspace* w = g->ws;
-    if (w->xr_count < nvec) {
-        hipFree(w->xr);
-        w->xr = nullptr;
-        w->xr_count = 0;
-        RHMC_HIP_TRY(hipMalloc((void**)&w->xr, w->vec_bytes * nvec));
-        w->xr_count = nvec;
-        free_graphs(w);   // graphs may reference the old buffer
+    if (!w) {
+        w = new Workspace();
+        g->ws = w;
+        w->device = g->device;
+        w->n = (size_t)3 * g->lat.Vh;
+        w->vec_bytes = w->n * sizeof(double2);
+        const size_t vb = w->vec_bytes;
+        RHMC_TRY(alloc((void**)&w->t64, vb * kMaxSys));
+        RHMC_TRY(alloc((void**)&w->rb, vb * kMaxSys));
+        RHMC_TRY(alloc((void**)&w->rx, vb * kMaxSys));
+        const size_t nblk = w->n / 2 / kBlock + 2;
+        RHMC_TRY(alloc((void**)&w->partial, sizeof(double) * 2 * kMaxSys * nblk));
+        RHMC_TRY(alloc((void**)&w->counters, sizeof(unsigned) * 8));
+        RHMC_HIP_TRY(hipMemset(w->counters, 0, sizeof(unsigned) * 8));
+        RHMC_TRY(alloc((void**)&w->sums, sizeof(double) * kMaxSys));
+        RHMC_TRY(alloc((void**)&w->st, sizeof(SolverState)));
+        RHMC_HIP_TRY(hipHostMalloc((void**)&w->hst, sizeof(SolverState), hipHostMallocDefault));
+        RHMC_HIP_TRY(hipHostMalloc((void**)&w->flags_host, sizeof(int) * 2, hipHostMallocDefault));
+        RHMC_HIP_TRY(hipHostMalloc((void**)&w->sums_host, sizeof(double) * kMaxSys, hipHostMallocDefault));
+        RHMC_HIP_TRY(hipStreamCreateWithFlags(&w->cap, hipStreamNonBlocking));
+        RHMC_HIP_TRY(hipEventCreateWithFlags(&w->ev[0], hipEventDisableTiming));
+        RHMC_HIP_TRY(hipEventCreateWithFlags(&w->ev[1], hipEventDisableTiming));
     }
+    const size_t vb = w->vec_bytes;
+    RHMC_TRY(grow(w, &w->ring, &w->ring_cap, vb * (size_t)(K + 1) * nsys));
+    RHMC_TRY(grow(w, &w->p, &w->p_cap, vb * nsys));
+    RHMC_TRY(grow(w, &w->Ap, &w->Ap_cap, vb * nsys));
+    RHMC_TRY(grow(w, &w->t, &w->t_cap, vb * nsys));
+    RHMC_TRY(grow(w, &w->P, &w->P_cap, vb * (size_t)nsys * nshift));
+    return RHMC_OK;
+}
+
+static rhmc_status ensure_rational_buffer(rhmc_gauge* g, size_t nvec, double2** out) {
+    Workspace* w = g->ws;
+    RHMC_TRY(grow(w, (void**)&w->xr, &w->xr_cap, w->vec_bytes * nvec));
     *out = w->xr;
     return RHMC_OK;
 }
