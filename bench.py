@@ -1,0 +1,279 @@
+#!/usr/bin/env python
+"""Benchmark of the staggered RHMC hot path on one MI355X.
+
+Workload (default): 48^3 x 12 lattice, links exp(i*0.8*H), m = 0.005, four
+Gaussian pseudofermion sources, the 20-pole rational approximation of x^-1/4
+on [m^2, 16 + m^2], tolerance 1e-10 per shift.  One step is one call of
+rhmc_rational_apply in MIXED precision with all four right-hand sides batched:
+multi-shift CG (FP32 12-real hopping term, FP64 reductions and recurrences,
+FP64 reliable updates), FP64 true-residual check and refinement, FP64 combine.
+
+Printed JSON line:
+  value        effective GB/s of the FP32 12-real four-rhs hopping kernel (the
+               kernel the solve spends its time in), algorithmic bytes per
+               launch / average launch time from HIP events on its stream;
+  ms_per_step  wall time of one mixed + batched solve;
+  time_to_solution_s  the same solve in MIXED + batched and in plain FP64;
+  roofline     the hopping kernel against the 8 TB/s HBM peak;
+  cpu_baseline the FP64 numpy oracle timed on a bounded sample.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("Dslash GB/s (% HBM peak); multi-shift CG time to r≤10^-10, FP64 vs mixed+batched")
+HBM_PEAK_GBPS = 8000.0
+WORKLOADS = {
+    # name: (config index, description)
+    "c5": (5, "48^3x12, eps 0.8, m 0.005, 4 rhs x 20-pole x^-1/4, MIXED batched, tol 1e-10"),
+    "c4": (4, "32^3x8, eps 0.7, m 0.01, 8 rhs x 15-pole x^-1/4, MIXED batched, tol 1e-10"),
+    "c3": (3, "32^3x8, eps 0.7, m 0.01, 1 rhs x 15-pole x^-1/4, MIXED, tol 1e-10"),
+}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def dslash_bytes_per_site(prec: str, nrhs: int) -> int:
+    """Algorithmic bytes per output site of one hopping application: 8 links
+    read once, the input vector read once and the output written once."""
+    if prec == "fp32":
+        return 8 * 48 + nrhs * (24 + 24)
+    return 8 * 144 + nrhs * (48 + 48)
+
+
+def source_hash(path):
+    with open(path, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def traffic_from_profile(kernel_tag: str):
+    """HBM bytes per launch from a committed counter summary, if it was taken
+    on the current hopping-kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", f"{kernel_tag}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    cur = source_hash(os.path.join(ROOT, "paper_1106_5673_amd", "csrc", "dslash.hip"))
+    if rec.get("dslash_source_sha256_16") != cur:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(U, b, m, rat, gpu_iters):
+    """Time the FP64 oracle on a bounded sample of the same workload."""
+    import numpy as np
+
+    from oracle import dirac
+
+    Vh = b.shape[-1]
+    t0, c0 = time.perf_counter(), time.process_time()
+    dirac.dslash(U, b[:1], 1)
+    t_d = time.perf_counter() - t0
+    cpu_d = time.process_time() - c0
+    # one iteration of the oracle's multi-shift CG on one rhs, all shifts
+    from oracle import solvers
+
+    t1 = time.perf_counter()
+    solvers.multishift_cg(lambda v: dirac.mdagm(U, m, v), b[0], np.asarray(rat.beta),
+                          tol=1e-10, maxiter=1)
+    t_it = time.perf_counter() - t1
+    beta = np.asarray(rat.beta)
+    cpu_total = time.process_time() - c0
+    wall_total = time.perf_counter() - t0
+    gbps = dslash_bytes_per_site("fp64", 1) * Vh / t_d / 1e9
+    nrhs = b.shape[0]
+    return {
+        "value": gbps,
+        "unit": "GB/s",
+        "cores": max(1, round(cpu_total / wall_total)),
+        "kind": "oracle",
+        "sample": (f"one FP64 D_oe application on 1 rhs ({t_d:.2f} s, counted at "
+                   f"{dslash_bytes_per_site('fp64', 1)} B/site) and one multi-shift CG "
+                   f"iteration on 1 rhs with {beta.size} shifts ({t_it:.2f} s) of the same "
+                   f"lattice and field"),
+        "seconds_per_cg_iteration_per_rhs": t_it,
+        "time_to_solution_s_extrapolated": t_it * gpu_iters * nrhs,
+        "cpu_seconds": cpu_d,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c5", choices=sorted(WORKLOADS))
+    ap.add_argument("--dslash-reps", type=int, default=200)
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison solve")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only-dslash", action="store_true",
+                    help="only the hopping-kernel timing and a copy of known size (counter runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(see the sharding design); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+
+    import synth
+    from synth.make_rational import rational_for
+
+    cfg, desc = WORKLOADS[args.workload]
+    c = synth.CONFIGS[cfg]
+    L, m, nrhs = c["L"], c["m"], c["nrhs"]
+    t0 = time.perf_counter()
+    U = synth.gauge_field(L, c["eps"], synth.fields.seed_gauge(cfg))
+    b = synth.source(L, synth.fields.seed_source(cfg), nrhs)
+    rat = rational_for(cfg, -0.25)
+    log(f"inputs for {desc} ready in {time.perf_counter() - t0:.1f} s")
+
+    import torch
+
+    from paper_1106_5673_amd import rhmc
+
+    dev = torch.device("cuda:0")
+    lat = rhmc.rhmc_lattice_create(L, -1)
+    g = rhmc.rhmc_gauge_create(lat, U)
+    Vh = lat.Vh
+    bd = torch.from_numpy(b).to(dev)
+    y = torch.empty_like(bd)
+    torch.cuda.synchronize()
+    log("gauge packed on the device")
+
+    # ---------------------------------------------------------------- hopping kernel
+    def time_dslash(prec, k, reps):
+        dt = torch.complex64 if prec == "fp32" else torch.complex128
+        pr = rhmc.RHMC_PREC_FP32 if prec == "fp32" else rhmc.RHMC_PREC_FP64
+        vin = bd[:k].to(dt).contiguous()
+        vout = torch.empty_like(vin)
+        for _ in range(5):
+            rhmc.rhmc_dslash_eo(g, 1, pr, k, vin, vout)
+        s = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            rhmc.rhmc_dslash_eo(g, 1, pr, k, vin, vout)
+        e1.record(s)
+        e1.synchronize()
+        avg_s = e0.elapsed_time(e1) / 1e3 / reps
+        byts = dslash_bytes_per_site(prec, k) * Vh
+        return avg_s, byts
+
+    if args.only_dslash:
+        avg, byts = time_dslash("fp32", nrhs, args.dslash_reps)
+        log(f"fp32-12 x{nrhs}: {avg * 1e6:.1f} us, {byts / avg / 1e9:.0f} GB/s")
+        avg64, byts64 = time_dslash("fp64", 1, args.dslash_reps)
+        log(f"fp64-18 x1: {avg64 * 1e6:.1f} us, {byts64 / avg64 / 1e9:.0f} GB/s")
+        # a plain copy of known size for calibrating the HBM byte counters
+        src = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy of 256 MiB done")
+        return
+
+    prm_mixed = rhmc.solver_params(tol=c["tol"], mode=rhmc.RHMC_MODE_MIXED, tune=1)
+    prm_fp64 = rhmc.solver_params(tol=c["tol"], mode=rhmc.RHMC_MODE_FP64, tune=1)
+
+    def step(prm):
+        return rhmc.rhmc_rational_apply(g, m, rat.alpha0, rat.alpha, rat.beta, bd, y, prm)
+
+    for w in range(args.warmup):
+        st = step(prm_mixed)
+        log(f"warmup {w}: {st['time_ms']:.1f} ms, {st['total_iterations']} iterations, "
+            f"max true residual {st['max_true_residual']:.2e}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for k in range(args.steps):
+        stats.append(step(prm_mixed))
+        log(f"step {k}: {stats[-1]['time_ms']:.1f} ms")
+    torch.cuda.synchronize()
+    t_mixed = (time.perf_counter() - t0) / max(1, args.steps)
+    st = stats[-1] if stats else step(prm_mixed)
+
+    t_fp64 = None
+    st64 = None
+    if not args.no_fp64:
+        t1 = time.perf_counter()
+        st64 = step(prm_fp64)
+        torch.cuda.synchronize()
+        t_fp64 = time.perf_counter() - t1
+        log(f"fp64 solve: {t_fp64 * 1e3:.1f} ms, {st64['total_iterations']} iterations")
+
+    avg, byts = time_dslash("fp32", nrhs, args.dslash_reps)
+    achieved = byts / avg / 1e9
+    avg64, byts64 = time_dslash("fp64", 1, args.dslash_reps // 2)
+    log(f"hopping fp32-12 x{nrhs}: {avg * 1e6:.1f} us ({achieved:.0f} GB/s); "
+        f"fp64-18 x1: {avg64 * 1e6:.1f} us ({byts64 / avg64 / 1e9:.0f} GB/s)")
+    tag = f"dslash_fp32_{nrhs}rhs_{'x'.join(str(v) for v in L)}"
+    traffic = traffic_from_profile(tag)
+    g.close()
+
+    out = {
+        "metric": METRIC,
+        "value": round(achieved, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_mixed * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": desc,
+            "lattice": list(L),
+            "nrhs": nrhs,
+            "npole": len(rat.beta),
+            "mass": m,
+            "tol": c["tol"],
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBPS, 4),
+            "traffic": traffic,
+            "kernel": f"hopping FP32 12-real, {nrhs} rhs, {avg * 1e6:.2f} us per launch, "
+                      f"{byts / 1e6:.1f} MB algorithmic per launch",
+        },
+        "time_to_solution_s": {
+            "mixed_batched": round(t_mixed, 4),
+            "fp64": None if t_fp64 is None else round(t_fp64, 4),
+        },
+        "iterations": {"mixed_batched": st["total_iterations"],
+                       "fp64": None if st64 is None else st64["total_iterations"]},
+        "max_true_residual": {"mixed_batched": st["max_true_residual"],
+                              "fp64": None if st64 is None else st64["max_true_residual"]},
+        "reliable_updates": st["reliable_updates"],
+        "refine_rounds": st["refine_rounds"],
+        "refine_iterations": int(st["refine_iterations"].sum()),
+        "shifts_refined": int((st["refine_iterations"] > 0).sum()),
+        "dslash_fp64_1rhs_GBps": round(byts64 / avg64 / 1e9, 1),
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(U, b, m, rat, st["total_iterations"])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -59,6 +59,7 @@ static rhmc_status hop(rhmc_gauge* g, int out_par, rhmc_prec prec, int nrhs, con
             if (self) a.self[k] = reinterpret_cast<const VT*>(self) + (size_t)(r0 + k) * n;
             a.c[k] = c;
         }
+        set_variant(a, g);
         if constexpr (std::is_same<VT, double2>::value) {
             RHMC_HIP_TRY(launch_dslash64(g->u64, nlinks, a, mode, s));
         } else {
@@ -168,6 +169,7 @@ rhmc_status rhmc_gauge_create(const rhmc_lattice* lat, const double* links, uint
     rhmc_gauge* g = new (std::nothrow) rhmc_gauge();
     if (!g) return RHMC_ERR_OOM;
     g->lat = *lat;
+    default_hop_variants(g->hop_variant);
     hipError_t e = hipGetDevice(&g->device);
     const size_t nlinks = (size_t)4 * lat->V;
     double2* canon = nullptr;

@@ -15,7 +15,6 @@ struct VecArgs {
     VT* y[kMaxSys];
     VT* z[kMaxSys];
     double* partial;
-    unsigned* counter;
 };
 
 // Deferred update of the shifted solutions at a block boundary.
@@ -28,7 +27,6 @@ struct FlushArgs {
     VT* P;                                // shifted directions [nsys][nshift][n]
     double2* X;                           // shifted solutions
     size_t x_sys, x_shift;                // element strides of X between systems / shifts
-    unsigned* counter;
 };
 
 struct CombineArgs {
@@ -54,6 +52,11 @@ template <typename VT> hipError_t launch_pupdate(const VecArgs<VT>& a, int nsys,
 template <typename VT>
 hipError_t launch_flush(const FlushArgs<VT>& a, int nsys, int qmax, hipStream_t s);
 hipError_t launch_combine(const CombineArgs& a, int nsys, hipStream_t s);
+// blocks along x of a vector kernel over n complex numbers (the partial-sum count)
+int vec_blocks(size_t n);
+// one-block kernel finishing block sums and running a FinalizeKind (state.h)
+hipError_t launch_finalize(int kind, void* state, const double* partial, int nblk, int nrhs,
+                           double* out_sums, hipStream_t s);
 hipError_t launch_add(const AddArgs& a, int nsys, hipStream_t s);
 
 }  // namespace rhmc

@@ -33,11 +33,11 @@ template <> struct Pair<double2> {
     }
 };
 
-// Block-reduce up to two doubles, write partial[(r0)*nblk + bx] (and r1), then
-// run the finalize in the last block of the grid.
-__device__ __forceinline__ void reduce_and_finalize(double v0, double v1, int r0, int r1,
-                                                    double* partial, unsigned* counter,
-                                                    int finalize, void* state) {
+// Block-reduce up to two doubles and store them as partial[r*gridDim.x + bx]
+// (r0, r1 >= 0).  The sums are finished by a one-block finalize kernel: the
+// kernel boundary makes every partial visible, with no per-block fence.
+__device__ __forceinline__ void reduce_store(double v0, double v1, int r0, int r1,
+                                             double* partial) {
     __shared__ double sm[2][kBlock / 64];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     for (int off = 32; off > 0; off >>= 1) {
@@ -49,29 +49,25 @@ __device__ __forceinline__ void reduce_and_finalize(double v0, double v1, int r0
         sm[1][wid] = v1;
     }
     __syncthreads();
-    const int nblk = gridDim.x;
     if (threadIdx.x < 2) {
         const int r = threadIdx.x == 0 ? r0 : r1;
         if (r >= 0) {
             double s = 0.0;
             for (int w = 0; w < kBlock / 64; ++w) s += sm[threadIdx.x][w];
-            partial[(size_t)r * nblk + blockIdx.x] = s;
-            __threadfence();
+            partial[(size_t)r * gridDim.x + blockIdx.x] = s;
         }
     }
-    __shared__ int last;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned total = gridDim.x * gridDim.y;
-        last = (atomicAdd(counter, 1u) == total - 1);
-    }
-    __syncthreads();
-    if (last) {
-        __threadfence();
-        solver_finalize(finalize, state, partial, nblk, 0, nullptr);
-        if (threadIdx.x == 0) *counter = 0u;
-    }
+}
+
+// ------------------------------------------------------------------ finalize
+// One block: finish the block sums of the preceding kernel and run the FP64
+// scalar recurrences of the multi-shift CG (state.h).
+__global__ __launch_bounds__(kBlock) void k_finalize(int kind, void* state, const double* partial,
+                                                     int nblk, int nrhs, double* out_sums) {
+    if (kind != kFinNorms && kind != kFinInit &&
+        reinterpret_cast<const SolverState*>(state)->all_done)
+        return;
+    solver_finalize(kind, state, partial, nblk, nrhs, out_sums);
 }
 
 // ------------------------------------------------------------------ start
@@ -80,9 +76,9 @@ template <typename VT>
 __global__ __launch_bounds__(kBlock) void k_start(VecArgs<VT> a) {
     SolverState* st = reinterpret_cast<SolverState*>(a.state);
     const int j = blockIdx.y;
-    const size_t i = ((size_t)blockIdx.x * kBlock + threadIdx.x) * 2;
     double b2 = 0.0, r2 = 0.0;
-    if (i < a.n) {
+    for (size_t i = ((size_t)blockIdx.x * kBlock + threadIdx.x) * 2; i < a.n;
+         i += (size_t)gridDim.x * kBlock * 2) {
         Pair<double2> b;
         b.load(a.b64[j], i);
         Pair<VT> r;
@@ -95,7 +91,7 @@ __global__ __launch_bounds__(kBlock) void k_start(VecArgs<VT> a) {
         r.store(a.x[j], i);
         r.store(a.y[j], i);
     }
-    reduce_and_finalize(b2, r2, j, st->nsys + j, a.partial, a.counter, kFinInit, a.state);
+    reduce_store(b2, r2, j, st->nsys + j, a.partial);
 }
 
 // ------------------------------------------------------------------ r update
@@ -105,10 +101,11 @@ __global__ __launch_bounds__(kBlock) void k_rupdate(VecArgs<VT> a) {
     SolverState* st = reinterpret_cast<SolverState*>(a.state);
     if (st->all_done) return;
     const int j = blockIdx.y;
-    const size_t i = ((size_t)blockIdx.x * kBlock + threadIdx.x) * 2;
     double r2 = 0.0;
-    if (!st->sys[j].done && i < a.n) {
-        const double alpha = st->sys[j].alpha;
+    const bool live = !st->sys[j].done;
+    const double alpha = st->sys[j].alpha;
+    for (size_t i = ((size_t)blockIdx.x * kBlock + threadIdx.x) * 2; live && i < a.n;
+         i += (size_t)gridDim.x * kBlock * 2) {
         Pair<VT> r, ap;
         r.load(a.x[j], i);
         ap.load(a.y[j], i);
@@ -121,7 +118,7 @@ __global__ __launch_bounds__(kBlock) void k_rupdate(VecArgs<VT> a) {
         }
         r.store(a.z[j], i);
     }
-    reduce_and_finalize(r2, 0.0, j, -1, a.partial, a.counter, kFinBeta, a.state);
+    reduce_store(r2, 0.0, j, -1, a.partial);
 }
 
 // ------------------------------------------------------------------ p update
@@ -207,36 +204,28 @@ __device__ __forceinline__ void flush_site(const FlushArgs<VT>& a, const SolverS
 
 template <typename VT, int Q>
 __global__ __launch_bounds__(kBlock) void k_flush(FlushArgs<VT> a) {
-    SolverState* st = reinterpret_cast<SolverState*>(a.state);
+    const SolverState* st = reinterpret_cast<const SolverState*>(a.state);
     const int j = blockIdx.y;
     const size_t i = ((size_t)blockIdx.x * kBlock + threadIdx.x) * 2;
     if (st->sys[j].blk_steps > 0 && i < a.n) flush_site<VT, Q>(a, st, j, i);
-    // last block resets the block coefficients
-    __shared__ int last;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned total = gridDim.x * gridDim.y;
-        last = (atomicAdd(a.counter, 1u) == total - 1);
+}
+
+// After a flush: restart the block coefficients (one block).
+__global__ __launch_bounds__(kBlock) void k_flush_reset(void* state) {
+    SolverState* st = reinterpret_cast<SolverState*>(state);
+    const int nsys = st->nsys, nsh = st->nshift;
+    for (int p = threadIdx.x; p < nsys * nsh; p += blockDim.x) {
+        ShiftScalars& h = st->sh[p / nsh][p % nsh];
+        h.c = 1.0;
+        h.e = 0.0;
+        for (int l = 0; l <= kMaxBlockLen; ++l) h.d[l] = h.f[l] = 0.0;
+        h.block_active = h.active;
     }
     __syncthreads();
-    if (last) {
-        __threadfence();
-        const int nsys = st->nsys, nsh = st->nshift;
-        for (int p = threadIdx.x; p < nsys * nsh; p += blockDim.x) {
-            ShiftScalars& h = st->sh[p / nsh][p % nsh];
-            h.c = 1.0;
-            h.e = 0.0;
-            for (int l = 0; l <= kMaxBlockLen; ++l) h.d[l] = h.f[l] = 0.0;
-            h.block_active = h.active;
-        }
-        __syncthreads();
-        if (threadIdx.x < nsys) st->sys[threadIdx.x].blk_steps = 0;
-        if (threadIdx.x == 0) {
-            st->first_block = 0;
-            st->blk_it = 0;
-            *a.counter = 0u;
-        }
+    if (threadIdx.x < nsys) st->sys[threadIdx.x].blk_steps = 0;
+    if (threadIdx.x == 0) {
+        st->first_block = 0;
+        st->blk_it = 0;
     }
 }
 
@@ -284,14 +273,19 @@ static dim3 vec_grid(size_t n, int nsys) {
     return dim3((unsigned)((n / 2 + kBlock - 1) / kBlock), (unsigned)nsys);
 }
 
+// reducing kernels stride over the vector with at most kRedBlocks blocks per
+// system, which bounds the number of partial sums the finalize has to add
+constexpr int kRedBlocks = 1024;
+static dim3 red_grid(size_t n, int nsys) { return dim3((unsigned)vec_blocks(n), (unsigned)nsys); }
+
 template <typename VT>
 hipError_t launch_start(const VecArgs<VT>& a, int nsys, hipStream_t s) {
-    hipLaunchKernelGGL(k_start<VT>, vec_grid(a.n, nsys), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_start<VT>, red_grid(a.n, nsys), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 template <typename VT>
 hipError_t launch_rupdate(const VecArgs<VT>& a, int nsys, hipStream_t s) {
-    hipLaunchKernelGGL(k_rupdate<VT>, vec_grid(a.n, nsys), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_rupdate<VT>, red_grid(a.n, nsys), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 template <typename VT>
@@ -299,6 +293,18 @@ hipError_t launch_pupdate(const VecArgs<VT>& a, int nsys, hipStream_t s) {
     hipLaunchKernelGGL(k_pupdate<VT>, vec_grid(a.n, nsys), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
+int vec_blocks(size_t n) {
+    const size_t full = (n / 2 + kBlock - 1) / kBlock;
+    return (int)(full < (size_t)kRedBlocks ? full : (size_t)kRedBlocks);
+}
+
+hipError_t launch_finalize(int kind, void* state, const double* partial, int nblk, int nrhs,
+                           double* out_sums, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, kind, state, partial, nblk, nrhs,
+                       out_sums);
+    return hipGetLastError();
+}
+
 template <typename VT>
 hipError_t launch_flush(const FlushArgs<VT>& a, int nsys, int qmax, hipStream_t s) {
     const dim3 g = vec_grid(a.n, nsys), b(kBlock);
@@ -310,6 +316,9 @@ hipError_t launch_flush(const FlushArgs<VT>& a, int nsys, int qmax, hipStream_t 
         hipLaunchKernelGGL((k_flush<VT, 12>), g, b, 0, s, a);
     else
         hipLaunchKernelGGL((k_flush<VT, 16>), g, b, 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_flush_reset, dim3(1), dim3(kBlock), 0, s, a.state);
     return hipGetLastError();
 }
 hipError_t launch_combine(const CombineArgs& a, int nsys, hipStream_t s) {

@@ -64,6 +64,27 @@ __device__ __forceinline__ void site_coords(const Geom& g, int eo, int par, int&
     x = 2 * xh + ((par + y + z + t) & 1);
 }
 
+// Site visited by processing index p (0 <= p < Vh) of a hopping launch.
+// order 0 walks the eo index itself (x fastest, then y, z, t); order 1 walks
+// x, y, t, z, so that consecutive sites of one XCD's contiguous range share
+// z-planes and the reuse distance of the z and t neighbours stays small.
+__device__ __forceinline__ void process_site(const Geom& g, int p, int par, int order, int& eo,
+                                             int& x, int& y, int& z, int& t) {
+    if (order == 0) {
+        eo = p;
+        site_coords(g, eo, par, x, y, z, t);
+        return;
+    }
+    const int xh = p % g.hx;
+    int r = p / g.hx;
+    y = r % g.Ly;
+    r /= g.Ly;
+    t = r % g.Lt;
+    z = r / g.Lt;
+    eo = xh + g.hx * (y + g.Ly * (z + g.Lz * t));
+    x = 2 * xh + ((par + y + z + t) & 1);
+}
+
 // The eight neighbours (eo index, opposite parity) of site eo with coordinates
 // (x,y,z,t) and the real factor multiplying each hop of D (Eq. stag):
 //   forward  hop mu: +1/2 * eta_mu(n) * bc,  acts with U_mu(n)
@@ -128,6 +149,8 @@ struct rhmc_gauge {
     size_t tmp_odd_bytes;
     double* partial;         // [kMaxSys][hopping grid] block sums of rhmc_apply_mdagm
     rhmc::Workspace* ws;     // solver workspace (lazily created)
+    int hop_variant[2][4];   // launch variant per [RHMC_PREC_*][rhs class]
+    int hop_tuned[2][4];     // 1 once the autotuner has timed that case
 };
 
 namespace rhmc {
@@ -155,12 +178,20 @@ struct DslashArgs {
     const int* skip;              // if non-null: skip[r*skip_stride] != 0 -> rhs r finished
     int skip_stride;
     const int* all_done;          // if non-null and set: the launch does nothing
-    double* partial;              // [nrhs][nblocks]
-    unsigned* counter;            // last-block detection
-    int finalize;                 // FinalizeKind run by the last block
-    void* fin_state;              // SolverState updated by the finalize
-    double* out_sums;             // kFinNorms: per-rhs sums
+    double* partial;              // [nrhs][nblocks] block sums (kModeA, kModeResid)
+    int variant;                  // launch variant (HopVariant index)
 };
+
+// Launch variants of the hopping kernel, index = order | nt << 1 | pipe << 2:
+//   order  site processing order (process_site)
+//   nt     non-temporal (streaming) loads of the links, which are read once
+//          per application and need not displace neighbour vectors
+//   pipe   issue the loads of two hops as one batch instead of one
+constexpr int kHopVariants = 8;
+// right-hand-side classes of the kernel templates: 1, 2, 4, 8
+inline int nr_class(int nrhs) { return nrhs <= 1 ? 0 : nrhs <= 2 ? 1 : nrhs <= 4 ? 2 : 3; }
+// measured defaults on MI355X (48^3 x 12), [precision][rhs class]
+void default_hop_variants(int (&v)[2][4]);
 
 // Geometry of a hopping launch.
 int dslash_grid(int Vh);
@@ -171,5 +202,16 @@ hipError_t launch_dslash64(const double2* u64, int nlinks, const DslashArgs<doub
 hipError_t launch_dslash32(const float4* u32, int nlinks, const DslashArgs<float2>& a,
                            int mode, hipStream_t s);
 hipError_t launch_neighbors(const Geom& g, int par, int* nb, int* sign, hipStream_t s);
+
+// Pick the launch variant of the gauge object for this precision and nrhs.
+template <typename VT>
+inline void set_variant(DslashArgs<VT>& a, const rhmc_gauge* g) {
+    a.variant = g->hop_variant[sizeof(VT) == 8 ? RHMC_PREC_FP32 : RHMC_PREC_FP64][nr_class(a.nrhs)];
+}
+
+// Time every launch variant of one hopping application (out_parity 1, plain D)
+// on the given vectors and keep the fastest in the gauge object.
+rhmc_status tune_hop(rhmc_gauge* g, rhmc_prec prec, int nrhs, const void* in, void* out,
+                     hipStream_t s);
 
 }  // namespace rhmc

@@ -6,6 +6,8 @@
 // Links are structure-of-arrays over the link index k = (2*mu + parity)*Vh + eo,
 // so the 64 lanes of a wave read 64 consecutive links per load; neighbour
 // vectors are colour-major [3][Vh] arrays, read by consecutive sites.
+#include <cstdlib>
+
 #include "common.h"
 #include "state.h"
 
@@ -78,24 +80,49 @@ struct Link {
     RT re[3][3], im[3][3];
 };
 
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+template <bool NT>
+__device__ __forceinline__ double2 ldg(const double2* p) {
+    if constexpr (NT) {
+        const d2v v = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(p));
+        return make_double2(v.x, v.y);
+    } else {
+        return *p;
+    }
+}
+
+template <bool NT>
+__device__ __forceinline__ float4 ldg(const float4* p) {
+    if constexpr (NT) {
+        const f4v v = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(p));
+        return make_float4(v.x, v.y, v.z, v.w);
+    } else {
+        return *p;
+    }
+}
+
+template <bool NT>
 __device__ __forceinline__ void load_link(const double2* __restrict__ u, int nlinks, int k,
                                           Link<double>& L) {
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            const double2 v = u[(size_t)(3 * i + j) * nlinks + k];
+            const double2 v = ldg<NT>(u + (size_t)(3 * i + j) * nlinks + k);
             L.re[i][j] = v.x;
             L.im[i][j] = v.y;
         }
 }
 
 // 12-real link: rows 1-2 stored, row 3 = conj(row1 x row2) (valid for det U = 1).
+template <bool NT>
 __device__ __forceinline__ void load_link(const float4* __restrict__ u, int nlinks, int k,
                                           Link<float>& L) {
-    const float4 a = u[k];
-    const float4 b = u[(size_t)nlinks + k];
-    const float4 c = u[(size_t)2 * nlinks + k];
+    const float4 a = ldg<NT>(u + k);
+    const float4 b = ldg<NT>(u + (size_t)nlinks + k);
+    const float4 c = ldg<NT>(u + (size_t)2 * nlinks + k);
     L.re[0][0] = a.x; L.im[0][0] = a.y; L.re[0][1] = a.z; L.im[0][1] = a.w;
     L.re[0][2] = b.x; L.im[0][2] = b.y; L.re[1][0] = b.z; L.im[1][0] = b.w;
     L.re[1][1] = c.x; L.im[1][1] = c.y; L.re[1][2] = c.z; L.im[1][2] = c.w;
@@ -117,7 +144,7 @@ template <> struct RealOf<double2> { using T = double; };
 template <> struct RealOf<float2> { using T = float; };
 
 // ------------------------------------------------------------------ hopping kernel
-template <typename VT, typename LT, int NR, int MODE>
+template <typename VT, typename LT, int NR, int MODE, bool NT, bool PIPE>
 __global__ __launch_bounds__(kBlock) void k_dslash(const LT* __restrict__ links, int nlinks,
                                                     DslashArgs<VT> a) {
     using RT = typename RealOf<VT>::T;
@@ -125,20 +152,27 @@ __global__ __launch_bounds__(kBlock) void k_dslash(const LT* __restrict__ links,
     const int nblk = gridDim.x;
     const int blk = xcd_remap(blockIdx.x, nblk);
     const int Vh = a.g.Vh;
-    const int eo = blk * kBlock + threadIdx.x;
+    const int p = blk * kBlock + threadIdx.x;
 
+    // Every lane loads all NR vectors of a hop with no branch in between, so
+    // the compiler can keep every load of a hop in flight at once; slots of
+    // finished or absent right-hand sides read rhs 0 (valid, cached) and only
+    // their stores are suppressed.
     bool act[NR];
+    const VT* inp[NR];
 #pragma unroll
-    for (int r = 0; r < NR; ++r)
+    for (int r = 0; r < NR; ++r) {
         act[r] = (r < a.nrhs) && !(a.skip && a.skip[r * a.skip_stride]);
+        inp[r] = (r < a.nrhs) ? a.in[r] : a.in[0];
+    }
 
     double dot[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) dot[r] = 0.0;
 
-    if (eo < Vh) {
-        int x, y, z, t;
-        site_coords(a.g, eo, a.out_par, x, y, z, t);
+    if (p < Vh) {
+        int eo, x, y, z, t;
+        process_site(a.g, p, a.out_par, a.variant & 1, eo, x, y, z, t);
         const Hops h = make_hops(a.g, eo, x, y, z, t);
         RT ar[NR][3], ai[NR][3];
 #pragma unroll
@@ -146,52 +180,60 @@ __global__ __launch_bounds__(kBlock) void k_dslash(const LT* __restrict__ links,
 #pragma unroll
             for (int c = 0; c < 3; ++c) ar[r][c] = ai[r][c] = RT(0);
 
+        int nbh = h.nb[0];
 #pragma unroll
-        for (int mu = 0; mu < 4; ++mu) {
-            // forward hop: + coef * U_mu(n) psi(n+mu)
-            {
-                Link<RT> U;
-                load_link(links, nlinks, (2 * mu + a.out_par) * Vh + eo, U);
-                const int nb = h.nb[mu];
-                const RT s = (RT)h.coef[mu];
+        for (int hop = 0; hop < 8; ++hop) {
+            const int mu = hop & 3;
+            const bool fwd = hop < 4;
+            const int nb = nbh;
+            // forward: U_mu(n) at this site; backward: U_mu(n-mu) at the neighbour
+            const int k = fwd ? (2 * mu + a.out_par) * Vh + eo : (2 * mu + 1 - a.out_par) * Vh + nb;
+            Link<RT> U;
+            load_link<NT>(links, nlinks, k, U);
+            VT v[NR][3];
 #pragma unroll
-                for (int r = 0; r < NR; ++r) {
-                    if (!act[r]) continue;
-                    const VT* in = a.in[r];
-                    const VT v0 = in[nb], v1 = in[Vh + nb], v2 = in[2 * Vh + nb];
+            for (int r = 0; r < NR; ++r) {
+                v[r][0] = inp[r][nb];
+                v[r][1] = inp[r][Vh + nb];
+                v[r][2] = inp[r][2 * Vh + nb];
+            }
+            const RT s = (RT)h.coef[hop];
 #pragma unroll
-                    for (int i = 0; i < 3; ++i) {
-                        const RT tr = U.re[i][0] * v0.x - U.im[i][0] * v0.y + U.re[i][1] * v1.x -
-                                      U.im[i][1] * v1.y + U.re[i][2] * v2.x - U.im[i][2] * v2.y;
-                        const RT ti = U.re[i][0] * v0.y + U.im[i][0] * v0.x + U.re[i][1] * v1.y +
-                                      U.im[i][1] * v1.x + U.re[i][2] * v2.y + U.im[i][2] * v2.x;
-                        ar[r][i] += s * tr;
-                        ai[r][i] += s * ti;
+            for (int r = 0; r < NR; ++r) {
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    RT tr, ti;
+                    if (fwd) {  // (U v)_i = sum_j U_ij v_j
+                        tr = U.re[i][0] * v[r][0].x - U.im[i][0] * v[r][0].y + U.re[i][1] * v[r][1].x -
+                             U.im[i][1] * v[r][1].y + U.re[i][2] * v[r][2].x - U.im[i][2] * v[r][2].y;
+                        ti = U.re[i][0] * v[r][0].y + U.im[i][0] * v[r][0].x + U.re[i][1] * v[r][1].y +
+                             U.im[i][1] * v[r][1].x + U.re[i][2] * v[r][2].y + U.im[i][2] * v[r][2].x;
+                    } else {    // (U^dagger v)_i = sum_j conj(U_ji) v_j
+                        tr = U.re[0][i] * v[r][0].x + U.im[0][i] * v[r][0].y + U.re[1][i] * v[r][1].x +
+                             U.im[1][i] * v[r][1].y + U.re[2][i] * v[r][2].x + U.im[2][i] * v[r][2].y;
+                        ti = U.re[0][i] * v[r][0].y - U.im[0][i] * v[r][0].x + U.re[1][i] * v[r][1].y -
+                             U.im[1][i] * v[r][1].x + U.re[2][i] * v[r][2].y - U.im[2][i] * v[r][2].x;
                     }
+                    ar[r][i] += s * tr;
+                    ai[r][i] += s * ti;
                 }
             }
-            // backward hop: + coef * U_mu(n-mu)^dagger psi(n-mu)   (coef carries the minus)
-            {
-                const int nb = h.nb[4 + mu];
-                Link<RT> U;
-                load_link(links, nlinks, (2 * mu + 1 - a.out_par) * Vh + nb, U);
-                const RT s = (RT)h.coef[4 + mu];
+            if (hop + 1 < 8) {
+                // Empty volatile asms (no instruction) pin this hop's sums and
+                // make the next hop's index depend on them: each wave then
+                // issues the loads of one hop as a batch and finishes its
+                // arithmetic before the next batch, instead of the scheduler
+                // hoisting all eight hops' loads and keeping them live (one
+                // wave per SIMD).  Latency is hidden by the other resident waves.
+                // PIPE: pin every second hop, so two hops' loads form one batch
+                if (!PIPE || (hop & 1)) {
 #pragma unroll
-                for (int r = 0; r < NR; ++r) {
-                    if (!act[r]) continue;
-                    const VT* in = a.in[r];
-                    const VT v0 = in[nb], v1 = in[Vh + nb], v2 = in[2 * Vh + nb];
+                    for (int r = 0; r < NR; ++r)
 #pragma unroll
-                    for (int i = 0; i < 3; ++i) {
-                        // (U^dagger v)_i = sum_j conj(U_ji) v_j
-                        const RT tr = U.re[0][i] * v0.x + U.im[0][i] * v0.y + U.re[1][i] * v1.x +
-                                      U.im[1][i] * v1.y + U.re[2][i] * v2.x + U.im[2][i] * v2.y;
-                        const RT ti = U.re[0][i] * v0.y - U.im[0][i] * v0.x + U.re[1][i] * v1.y -
-                                      U.im[1][i] * v1.x + U.re[2][i] * v2.y - U.im[2][i] * v2.x;
-                        ar[r][i] += s * tr;
-                        ai[r][i] += s * ti;
-                    }
+                        for (int i = 0; i < 3; ++i) asm volatile("" : "+v"(ar[r][i]), "+v"(ai[r][i]));
                 }
+                nbh = h.nb[hop + 1];
+                asm volatile("" : "+v"(nbh));
             }
         }
 
@@ -255,44 +297,56 @@ __global__ __launch_bounds__(kBlock) void k_dslash(const LT* __restrict__ links,
         }
         __syncthreads();
         if (threadIdx.x < NR && threadIdx.x < a.nrhs) {
-            double s = 0.0;
+            double t = 0.0;
 #pragma unroll
-            for (int w = 0; w < kBlock / 64; ++w) s += sm[threadIdx.x][w];
-            a.partial[(size_t)threadIdx.x * nblk + blk] = s;
-            __threadfence();
-        }
-        if (a.finalize) {
-            __shared__ int last;
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                __threadfence();
-                const unsigned prev = atomicAdd(a.counter, 1u);
-                last = (prev == (unsigned)(nblk - 1));
-            }
-            __syncthreads();
-            if (last) {
-                __threadfence();
-                solver_finalize(a.finalize, a.fin_state, a.partial, nblk, a.nrhs, a.out_sums);
-                if (threadIdx.x == 0) *a.counter = 0u;
-            }
+            for (int w = 0; w < kBlock / 64; ++w) t += sm[threadIdx.x][w];
+            a.partial[(size_t)threadIdx.x * nblk + blk] = t;
         }
     }
 }
 
 int dslash_grid(int Vh) { return (Vh + kBlock - 1) / kBlock; }
 
-template <typename VT, typename LT, int MODE>
-static hipError_t dispatch(const LT* links, int nlinks, const DslashArgs<VT>& a, hipStream_t s) {
+void default_hop_variants(int (&v)[2][4]) {
+    // index = order | nt << 1 | pipe << 2
+    const int fp64[4] = {3, 3, 6, 6};
+    const int fp32[4] = {5, 7, 7, 6};
+    for (int k = 0; k < 4; ++k) {
+        v[RHMC_PREC_FP64][k] = fp64[k];
+        v[RHMC_PREC_FP32][k] = fp32[k];
+    }
+    if (const char* e = std::getenv("RHMC_HOP_VARIANT")) {
+        const int f = std::atoi(e) & (kHopVariants - 1);
+        for (auto& row : v)
+            for (int& x : row) x = f;
+    }
+}
+
+template <typename VT, typename LT, int MODE, bool NT, bool PIPE>
+static hipError_t dispatch_nt(const LT* links, int nlinks, const DslashArgs<VT>& a, hipStream_t s) {
     const dim3 grid(dslash_grid(a.g.Vh)), block(kBlock);
     if (a.nrhs <= 1)
-        hipLaunchKernelGGL((k_dslash<VT, LT, 1, MODE>), grid, block, 0, s, links, nlinks, a);
+        hipLaunchKernelGGL((k_dslash<VT, LT, 1, MODE, NT, PIPE>), grid, block, 0, s, links, nlinks, a);
     else if (a.nrhs <= 2)
-        hipLaunchKernelGGL((k_dslash<VT, LT, 2, MODE>), grid, block, 0, s, links, nlinks, a);
+        hipLaunchKernelGGL((k_dslash<VT, LT, 2, MODE, NT, PIPE>), grid, block, 0, s, links, nlinks, a);
     else if (a.nrhs <= 4)
-        hipLaunchKernelGGL((k_dslash<VT, LT, 4, MODE>), grid, block, 0, s, links, nlinks, a);
+        hipLaunchKernelGGL((k_dslash<VT, LT, 4, MODE, NT, PIPE>), grid, block, 0, s, links, nlinks, a);
     else
-        hipLaunchKernelGGL((k_dslash<VT, LT, 8, MODE>), grid, block, 0, s, links, nlinks, a);
+        hipLaunchKernelGGL((k_dslash<VT, LT, 8, MODE, NT, PIPE>), grid, block, 0, s, links, nlinks, a);
     return hipGetLastError();
+}
+
+template <typename VT, typename LT, int MODE>
+static hipError_t dispatch(const LT* links, int nlinks, const DslashArgs<VT>& a0, hipStream_t s) {
+    DslashArgs<VT> a = a0;
+    const int v = a.variant & (kHopVariants - 1);
+    const bool nt = (v >> 1) & 1, pipe = (v >> 2) & 1;
+    if (pipe) {
+        if (nt) return dispatch_nt<VT, LT, MODE, true, true>(links, nlinks, a, s);
+        return dispatch_nt<VT, LT, MODE, false, true>(links, nlinks, a, s);
+    }
+    if (nt) return dispatch_nt<VT, LT, MODE, true, false>(links, nlinks, a, s);
+    return dispatch_nt<VT, LT, MODE, false, false>(links, nlinks, a, s);
 }
 
 hipError_t launch_dslash64(const double2* u64, int nlinks, const DslashArgs<double2>& a, int mode,
@@ -302,6 +356,67 @@ hipError_t launch_dslash64(const double2* u64, int nlinks, const DslashArgs<doub
         case kModeA: return dispatch<double2, double2, kModeA>(u64, nlinks, a, s);
         default: return dispatch<double2, double2, kModeResid>(u64, nlinks, a, s);
     }
+}
+
+rhmc_status tune_hop(rhmc_gauge* g, rhmc_prec prec, int nrhs, const void* in, void* out,
+                     hipStream_t s) {
+    const int cls = nr_class(nrhs);
+    const int nlinks = (int)(4 * g->lat.V);
+    const size_t n = (size_t)3 * g->lat.Vh;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    RHMC_HIP_TRY(hipEventCreate(&e0));
+    RHMC_HIP_TRY(hipEventCreate(&e1));
+    float best = 1e30f;
+    int best_v = g->hop_variant[prec][cls];
+    for (int v = 0; v < kHopVariants; ++v) {
+        hipError_t err = hipSuccess;
+        auto launch = [&]() {
+            if (prec == RHMC_PREC_FP64) {
+                DslashArgs<double2> a{};
+                a.g = g->lat.geom;
+                a.out_par = 1;
+                a.nrhs = nrhs;
+                a.variant = v;
+                for (int r = 0; r < nrhs; ++r) {
+                    a.in[r] = reinterpret_cast<const double2*>(in) + r * n;
+                    a.out[r] = reinterpret_cast<double2*>(out) + r * n;
+                }
+                err = launch_dslash64(g->u64, nlinks, a, kModeD, s);
+            } else {
+                DslashArgs<float2> a{};
+                a.g = g->lat.geom;
+                a.out_par = 1;
+                a.nrhs = nrhs;
+                a.variant = v;
+                for (int r = 0; r < nrhs; ++r) {
+                    a.in[r] = reinterpret_cast<const float2*>(in) + r * n;
+                    a.out[r] = reinterpret_cast<float2*>(out) + r * n;
+                }
+                err = launch_dslash32(g->u32, nlinks, a, kModeD, s);
+            }
+        };
+        for (int w = 0; w < 2 && err == hipSuccess; ++w) launch();
+        if (err == hipSuccess) err = hipEventRecord(e0, s);
+        for (int w = 0; w < 5 && err == hipSuccess; ++w) launch();
+        if (err == hipSuccess) err = hipEventRecord(e1, s);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        if (err != hipSuccess) {
+            hipEventDestroy(e0);
+            hipEventDestroy(e1);
+            RHMC_HIP_TRY(err);
+        }
+        if (ms < best) {
+            best = ms;
+            best_v = v;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    g->hop_variant[prec][cls] = best_v;
+    g->hop_tuned[prec][cls] = 1;
+    return RHMC_OK;
 }
 
 hipError_t launch_dslash32(const float4* u32, int nlinks, const DslashArgs<float2>& a, int mode,

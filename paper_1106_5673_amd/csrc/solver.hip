@@ -35,6 +35,7 @@ struct GraphKey {
     size_t x_sys = 0, x_shift = 0;
     double c[kMaxSys] = {};
     int base[kMaxSys] = {};
+    int variants[2][4] = {};
     bool operator==(const GraphKey& o) const { return std::memcmp(this, &o, sizeof(*this)) == 0; }
 };
 
@@ -59,7 +60,6 @@ struct Workspace {
     double2* rb = nullptr;     // [kMaxSys] refinement right-hand sides
     double2* rx = nullptr;     // [kMaxSys] refinement corrections
     double* partial = nullptr;
-    unsigned* counters = nullptr;  // [8]
     double* sums = nullptr;        // [kMaxSys]
     SolverState* st = nullptr;     // device
     SolverState* hst = nullptr;    // pinned host mirror
@@ -86,7 +86,7 @@ void workspace_destroy(Workspace* w) {
     if (!w) return;
     free_graphs(w);
     for (void* p : {w->ring, w->p, w->Ap, w->t, w->P, (void*)w->t64, (void*)w->rb, (void*)w->rx,
-                    (void*)w->xr, (void*)w->partial, (void*)w->counters, (void*)w->sums,
+                    (void*)w->xr, (void*)w->partial, (void*)w->sums,
                     (void*)w->st})
         hipFree(p);
     hipHostFree(w->hst);
@@ -134,8 +134,6 @@ static rhmc_status ensure_workspace(rhmc_gauge* g, int nsys, int nshift, int K) 
         RHMC_TRY(alloc((void**)&w->rx, vb * kMaxSys));
         const size_t nblk = w->n / 2 / kBlock + 2;
         RHMC_TRY(alloc((void**)&w->partial, sizeof(double) * 2 * kMaxSys * nblk));
-        RHMC_TRY(alloc((void**)&w->counters, sizeof(unsigned) * 8));
-        RHMC_HIP_TRY(hipMemset(w->counters, 0, sizeof(unsigned) * 8));
         RHMC_TRY(alloc((void**)&w->sums, sizeof(double) * kMaxSys));
         RHMC_TRY(alloc((void**)&w->st, sizeof(SolverState)));
         RHMC_HIP_TRY(hipHostMalloc((void**)&w->hst, sizeof(SolverState), hipHostMallocDefault));
@@ -174,6 +172,7 @@ struct Problem {
     size_t x_sys, x_shift;        // element strides
     int mode, K, reliable_blocks, maxiter;
     bool use_graph;
+    bool tune;
     int poll_every;
 };
 
@@ -198,14 +197,11 @@ static rhmc_status enqueue_block(const rhmc_gauge* g, Workspace* w, const Proble
     d.skip_stride = (int)(sizeof(SysScalars) / sizeof(int));
     d.all_done = &w->st->all_done;
     d.partial = w->partial;
-    d.counter = w->counters + 0;
-    d.fin_state = w->st;
     DslashArgs<VT> a = d;
     d.out_par = 1;
-    d.finalize = kFinNone;
     a.out_par = 0;
-    a.finalize = kFinAlpha;
-    a.counter = w->counters + 1;
+    const int dgrid = dslash_grid(g->lat.geom.Vh);
+    const int vgrid = vec_blocks(n);
     for (int j = 0; j < ns; ++j) {
         d.in[j] = vec<VT>(w->p, n, j);
         d.out[j] = vec<VT>(w->t, n, j);
@@ -214,6 +210,8 @@ static rhmc_status enqueue_block(const rhmc_gauge* g, Workspace* w, const Proble
         a.out[j] = vec<VT>(w->Ap, n, j);
         a.c[j] = pb.m2 + pb.sigma0[j];
     }
+    set_variant(d, g);
+    set_variant(a, g);
     for (int q = 0; q < pb.K; ++q) {
         if constexpr (std::is_same<VT, float2>::value) {
             RHMC_HIP_TRY(launch_dslash32(g->u32, nlinks, d, kModeD, s));
@@ -222,17 +220,18 @@ static rhmc_status enqueue_block(const rhmc_gauge* g, Workspace* w, const Proble
             RHMC_HIP_TRY(launch_dslash64(g->u64, nlinks, d, kModeD, s));
             RHMC_HIP_TRY(launch_dslash64(g->u64, nlinks, a, kModeA, s));
         }
+        RHMC_HIP_TRY(launch_finalize(kFinAlpha, w->st, w->partial, dgrid, ns, nullptr, s));
         VecArgs<VT> r{};
         r.state = w->st;
         r.n = n;
         r.partial = w->partial;
-        r.counter = w->counters + 2;
         for (int j = 0; j < ns; ++j) {
             r.x[j] = vec<VT>(w->ring, n, (size_t)q * ns + j);
             r.y[j] = vec<VT>(w->Ap, n, j);
             r.z[j] = vec<VT>(w->ring, n, (size_t)(q + 1) * ns + j);
         }
         RHMC_HIP_TRY(launch_rupdate<VT>(r, ns, s));
+        RHMC_HIP_TRY(launch_finalize(kFinBeta, w->st, w->partial, vgrid, ns, nullptr, s));
         VecArgs<VT> p{};
         p.state = w->st;
         p.n = n;
@@ -252,7 +251,6 @@ static rhmc_status enqueue_block(const rhmc_gauge* g, Workspace* w, const Proble
     f.X = pb.X;
     f.x_sys = pb.x_sys;
     f.x_shift = pb.x_shift;
-    f.counter = w->counters + 3;
     RHMC_HIP_TRY(launch_flush<VT>(f, ns, pb.K, s));
 
     if (reliable) {
@@ -267,9 +265,6 @@ static rhmc_status enqueue_block(const rhmc_gauge* g, Workspace* w, const Proble
         DslashArgs<double2> r64 = d64;
         r64.out_par = 0;
         r64.partial = w->partial;
-        r64.counter = w->counters + 4;
-        r64.finalize = kFinReliable;
-        r64.fin_state = w->st;
         for (int j = 0; j < ns; ++j) {
             const double2* x0 = pb.X + j * pb.x_sys + pb.base[j] * pb.x_shift;
             d64.in[j] = x0;
@@ -283,8 +278,11 @@ static rhmc_status enqueue_block(const rhmc_gauge* g, Workspace* w, const Proble
         }
         if (!f32)
             for (int j = 0; j < ns; ++j) r64.out[j] = reinterpret_cast<double2*>(vec<VT>(w->ring, n, j));
+        set_variant(d64, g);
+        set_variant(r64, g);
         RHMC_HIP_TRY(launch_dslash64(g->u64, nlinks, d64, kModeD, s));
         RHMC_HIP_TRY(launch_dslash64(g->u64, nlinks, r64, kModeResid, s));
+        RHMC_HIP_TRY(launch_finalize(kFinReliable, w->st, w->partial, dgrid, ns, nullptr, s));
     }
     return RHMC_OK;
 }
@@ -304,6 +302,7 @@ static rhmc_status get_graph(rhmc_gauge* g, Workspace* w, const Problem& pb, boo
         k.c[j] = pb.m2 + pb.sigma0[j];
         k.base[j] = pb.base[j];
     }
+    std::memcpy(k.variants, g->hop_variant, sizeof(k.variants));
     k.x = pb.X;
     k.x_sys = pb.x_sys;
     k.x_shift = pb.x_shift;
@@ -362,13 +361,13 @@ static rhmc_status run_krylov(rhmc_gauge* g, const Problem& pb, hipStream_t s, i
     st.state = w->st;
     st.n = n;
     st.partial = w->partial;
-    st.counter = w->counters + 5;
     for (int j = 0; j < pb.nsys; ++j) {
         st.b64[j] = pb.b[j];
         st.x[j] = vec<VT>(w->ring, n, j);
         st.y[j] = vec<VT>(w->p, n, j);
     }
     RHMC_HIP_TRY(launch_start<VT>(st, pb.nsys, s));
+    RHMC_HIP_TRY(launch_finalize(kFinInit, w->st, w->partial, vec_blocks(n), pb.nsys, nullptr, s));
     RHMC_HIP_TRY(hipMemcpyAsync(h, w->st, sizeof(SolverState), hipMemcpyDeviceToHost, s));
     RHMC_HIP_TRY(hipStreamSynchronize(s));
     for (int j = 0; j < pb.nsys; ++j) {
@@ -383,6 +382,11 @@ static rhmc_status run_krylov(rhmc_gauge* g, const Problem& pb, hipStream_t s, i
                                             n * sizeof(double2), s));
     }
 
+    if (pb.tune) {
+        const rhmc_prec pr = std::is_same<VT, float2>::value ? RHMC_PREC_FP32 : RHMC_PREC_FP64;
+        if (!g->hop_tuned[pr][nr_class(pb.nsys)])
+            RHMC_TRY(tune_hop(g, pr, pb.nsys, w->p, w->t, s));
+    }
     hipGraphExec_t gb = nullptr, gr = nullptr;
     if (pb.use_graph) {
         RHMC_TRY(get_graph<VT>(g, w, pb, false, &gb));
@@ -435,9 +439,6 @@ static rhmc_status true_residuals(rhmc_gauge* g, const Problem& pb, const std::v
         DslashArgs<double2> r = d;
         r.out_par = 0;
         r.partial = w->partial;
-        r.counter = w->counters + 6;
-        r.finalize = kFinNorms;
-        r.out_sums = w->sums;
         for (int k = 0; k < cnt; ++k) {
             const int p = list[c0 + k];
             const int j = p / pb.nshift, i = p % pb.nshift;
@@ -450,8 +451,12 @@ static rhmc_status true_residuals(rhmc_gauge* g, const Problem& pb, const std::v
             r.c[k] = pb.m2 + pb.sigma0[j] + pb.off[j][i];
             r.out[k] = store ? store + (size_t)k * n : nullptr;
         }
+        set_variant(d, g);
+        set_variant(r, g);
         RHMC_HIP_TRY(launch_dslash64(g->u64, nlinks, d, kModeD, s));
         RHMC_HIP_TRY(launch_dslash64(g->u64, nlinks, r, kModeResid, s));
+        RHMC_HIP_TRY(launch_finalize(kFinNorms, nullptr, w->partial, dslash_grid(g->lat.geom.Vh), cnt,
+                                     w->sums, s));
         RHMC_HIP_TRY(hipMemcpyAsync(w->sums_host, w->sums, sizeof(double) * cnt,
                                     hipMemcpyDeviceToHost, s));
         RHMC_HIP_TRY(hipStreamSynchronize(s));
@@ -499,6 +504,11 @@ static rhmc_status solve_impl(rhmc_gauge* g, Problem pb, const rhmc_solver_param
             if (!(res[p] <= tol)) bad.push_back(p);
         if (bad.empty()) break;
         ++rounds;
+        // batch systems of similar shift: they need similar iteration counts
+        std::stable_sort(bad.begin(), bad.end(), [&](int p, int q) {
+            return pb.sigma0[p / pb.nshift] + pb.off[p / pb.nshift][p % pb.nshift] <
+                   pb.sigma0[q / pb.nshift] + pb.off[q / pb.nshift][q % pb.nshift];
+        });
         for (size_t c0 = 0; c0 < bad.size(); c0 += kMaxSys) {
             const int cnt = (int)std::min<size_t>(kMaxSys, bad.size() - c0);
             std::vector<int> chunk(bad.begin() + c0, bad.begin() + c0 + cnt);
@@ -612,6 +622,7 @@ rhmc_status multishift(rhmc_gauge* g, double m, int nshift, const double* shifts
         pb.reliable_blocks = std::max(1, (prm.reliable_every + K - 1) / K);
         pb.maxiter = prm.maxiter;
         pb.use_graph = prm.use_graph != 0;
+        pb.tune = prm.tune != 0;
         pb.poll_every = prm.poll_every > 0 ? prm.poll_every : 1;
         rhmc_solver_stats st{};
         if (stats) {

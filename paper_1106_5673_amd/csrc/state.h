@@ -145,15 +145,16 @@ __device__ inline void solver_finalize(int kind, void* vstate, const double* par
         __syncthreads();
         for (int p = tid; p < nsys * nsh; p += blockDim.x) {
             const int j = p / nsh, i = p % nsh;
-            const SysScalars& s = st->sys[j];
-            ShiftScalars& h = st->sh[j][i];
-            if (s.done || !h.active) continue;
+            const SysScalars s = st->sys[j];
+            ShiftScalars* hp = &st->sh[j][i];
+            if (s.done || !hp->active) continue;
+            const double zeta = hp->zeta, zeta_prev = hp->zeta_prev, off = hp->off;
             const double a = s.alpha;
-            const double zn = h.zeta * h.zeta_prev * s.alpha_prev /
-                              (h.zeta_prev * s.alpha_prev * (1.0 + a * h.off) +
-                               a * s.beta_prev * (h.zeta_prev - h.zeta));
-            h.zeta_next = zn;
-            h.a = a * zn / h.zeta;
+            const double zn = zeta * zeta_prev * s.alpha_prev /
+                              (zeta_prev * s.alpha_prev * (1.0 + a * off) +
+                               a * s.beta_prev * (zeta_prev - zeta));
+            hp->zeta_next = zn;
+            hp->a = a * zn / zeta;
         }
         return;
     }
@@ -170,19 +171,28 @@ __device__ inline void solver_finalize(int kind, void* vstate, const double* par
     const int q_all = st->blk_it;
     for (int p = tid; p < nsys * nsh; p += blockDim.x) {
         const int j = p / nsh, i = p % nsh;
-        const SysScalars& s = st->sys[j];
-        ShiftScalars& h = st->sh[j][i];
-        if (s.done || !h.active) continue;
+        const SysScalars s = st->sys[j];
+        ShiftScalars* hp = &st->sh[j][i];
+        if (s.done || !hp->active) continue;
+        // one bulk copy into registers, update, one bulk copy back
+        ShiftScalars h = *hp;
         const int q = s.blk_steps;   // this step's index inside the block (0-based)
         const double ratio = h.zeta_next / h.zeta;
         const double bi = beta_s[j] * ratio * ratio;
         // x_i(k+1) = x_i(k) + a_i p_i(k);  p_i(k) = c P + sum_{l<=q} d[l] r(k0+l)
         h.e += h.a * h.c;
-        for (int l = 1; l <= q; ++l) h.f[l] += h.a * h.d[l];
         // p_i(k+1) = zeta_i(k+1) r(k+1) + b_i p_i(k)
         h.c *= bi;
-        for (int l = 1; l <= q; ++l) h.d[l] *= bi;
-        h.d[q + 1] = h.zeta_next;
+        // (fully unrolled with compile-time indices so h stays in registers)
+#pragma unroll
+        for (int l = 1; l <= kMaxBlockLen; ++l) {
+            if (l <= q) {
+                h.f[l] += h.a * h.d[l];
+                h.d[l] *= bi;
+            } else if (l == q + 1) {
+                h.d[l] = h.zeta_next;
+            }
+        }
         h.zeta_prev = h.zeta;
         h.zeta = h.zeta_next;
         const double res = fabs(h.zeta) * sqrt(sums[j]);
@@ -190,6 +200,7 @@ __device__ inline void solver_finalize(int kind, void* vstate, const double* par
             h.active = 0;
             h.conv_iter = s.iters + 1;
         }
+        *hp = h;
     }
     __syncthreads();
     for (int p = tid; p < nsys * nsh; p += blockDim.x) {

@@ -101,11 +101,26 @@ def _reunitarize(u: np.ndarray) -> np.ndarray:
 def _exp_i_eps_h(omega: np.ndarray, eps: float) -> np.ndarray:
     """exp(i*eps*H) for H = sum_a omega^a T^a, batched over leading axes."""
     T = _gell_mann_generators()
-    H = np.einsum("...a,aij->...ij", omega, T)
+    lead = omega.shape[:-1]
+    H = (omega.reshape(-1, 8) @ T.reshape(8, 9)).reshape(lead + (3, 3))
     w, V = np.linalg.eigh(H)
-    ph = np.exp(1j * eps * w)
-    U = np.einsum("...ik,...k,...jk->...ij", V, ph, np.conj(V))
+    U = (V * np.exp(1j * eps * w)[..., None, :]) @ np.conj(np.swapaxes(V, -1, -2))
     return _reunitarize(U)
+
+
+def _exp_chunk(args):
+    omega, eps = args
+    return _exp_i_eps_h(omega, eps)
+
+
+def _gpu_initialised() -> bool:
+    import sys
+
+    torch = sys.modules.get("torch")
+    try:
+        return bool(torch is not None and torch.cuda.is_initialized())
+    except Exception:
+        return True
 
 
 def random_su3(shape, rng: np.random.Generator, eps: float) -> np.ndarray:
@@ -114,19 +129,36 @@ def random_su3(shape, rng: np.random.Generator, eps: float) -> np.ndarray:
     return _exp_i_eps_h(omega, eps)
 
 
-def gauge_field(L, eps: float, seed: int, chunk: int = 1 << 18) -> np.ndarray:
-    """Seeded gauge field, complex128[Lt][Lz][Ly][Lx][4][3][3]."""
+def gauge_field(L, eps: float, seed: int, chunk: int = 1 << 16, workers=None) -> np.ndarray:
+    """Seeded gauge field, complex128[Lt][Lz][Ly][Lx][4][3][3].
+
+    All random numbers are drawn first, in the documented order; the
+    exponentials are then evaluated chunk by chunk, in worker processes when
+    the lattice is large (the result does not depend on the number of
+    workers).  Worker processes are forked only while no GPU context exists.
+    """
     _check_dims(L)
     Lx, Ly, Lz, Lt = (int(l) for l in L)
     V = Lx * Ly * Lz * Lt
     rng = np.random.Generator(np.random.PCG64(seed))
+    omega = rng.standard_normal((V, 4, 8))
     out = np.empty((V, 4, 3, 3), dtype=np.complex128)
-    # draw in chunks of sites; the generator is consumed in the same order
-    # as one draw of shape (V, 4, 8)
-    for s0 in range(0, V, chunk):
-        s1 = min(V, s0 + chunk)
-        omega = rng.standard_normal((s1 - s0, 4, 8))
-        out[s0:s1] = _exp_i_eps_h(omega, eps)
+    starts = list(range(0, V, chunk))
+    if workers is None:
+        import os
+
+        workers = 1 if (V < 4 * chunk or _gpu_initialised()) else min(16, os.cpu_count() or 1)
+    if workers > 1:
+        import concurrent.futures as cf
+        import multiprocessing as mp
+
+        with cf.ProcessPoolExecutor(workers, mp_context=mp.get_context("fork")) as ex:
+            parts = ex.map(_exp_chunk, ((omega[s0:s0 + chunk], eps) for s0 in starts))
+            for s0, part in zip(starts, parts):
+                out[s0:s0 + part.shape[0]] = part
+    else:
+        for s0 in starts:
+            out[s0:s0 + chunk] = _exp_i_eps_h(omega[s0:s0 + chunk], eps)
     return out.reshape(Lt, Lz, Ly, Lx, 4, 3, 3)
 
 
