@@ -82,8 +82,8 @@ typedef struct {
     int32_t reliable_every; /* MIXED: iterations between FP64 residual replacements (default 50) */
     int32_t refine;         /* nonzero: shifts whose FP64 true residual exceeds tol get a
                                warm-started CG on their own system (default 1) */
-    int32_t block;          /* iterations between updates of the shifted solutions (1..16,
-                               default 10; MIXED rounds reliable_every to a multiple) */
+    int32_t block;          /* iterations between updates of the shifted solutions (1..32,
+                               default 25; MIXED rounds reliable_every up to a multiple) */
     int32_t use_graph;      /* nonzero: replay each block of iterations as a hipGraph (default 1) */
     int32_t poll_every;     /* blocks launched between convergence polls (0 = automatic) */
     int32_t tune;           /* nonzero: time the Dslash launch shapes once and keep the best */
@@ -166,6 +166,25 @@ rhmc_status rhmc_rational_apply(const rhmc_gauge* g, double m, const rhmc_ration
                                 int32_t nrhs, const void* b, void* y,
                                 const rhmc_solver_params* params, rhmc_solver_stats* stats,
                                 hipStream_t stream);
+
+/* Autotuner of the hopping kernel (the batching form's launch shapes): times
+ * every launch variant (site processing order, non-temporal link loads, loads
+ * of one or two hops per batch) of one application D_oe on the given vectors
+ * and keeps the fastest for this precision and rhs count in the gauge object;
+ * later calls of every entry point use it.  in: device [nrhs][3][Vh] even
+ * sites; out: device [nrhs][3][Vh], overwritten.  Blocks until timed.
+ * rhmc_multishift_cg and rhmc_rational_apply do the same when params->tune is set. */
+rhmc_status rhmc_tune_dslash(rhmc_gauge* g, rhmc_prec prec, int32_t nrhs, const void* in,
+                             void* out, hipStream_t stream);
+
+/* The launch variant the hopping kernel currently uses for this precision and
+ * rhs count (the measured default, or the autotuner's choice), for reports:
+ * variant (host int32) = order | nt << 2 | pipe << 3, with order the site
+ * processing order 0..3 (0 even-odd index, 1 x,y,t,z, 2 and 3 z-tiles of 4 and
+ * 2 planes with t inside a tile), nt non-temporal link loads and pipe the
+ * loads of two hops issued as one batch. */
+rhmc_status rhmc_dslash_variant(const rhmc_gauge* g, rhmc_prec prec, int32_t nrhs,
+                                int32_t* variant);
 
 const char* rhmc_status_string(rhmc_status s);
 const char* rhmc_last_error(void);

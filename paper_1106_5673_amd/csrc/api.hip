@@ -84,7 +84,7 @@ static rhmc_status check_params(const rhmc_solver_params* p, const rhmc_gauge* g
     if (!(out->tol > 0) || !std::isfinite(out->tol)) return invalid("tol must be positive");
     if (out->maxiter < 1) return invalid("maxiter must be >= 1");
     if (out->mode != RHMC_MODE_FP64 && out->mode != RHMC_MODE_MIXED) return invalid("unknown mode");
-    if (out->block < 1 || out->block > kMaxBlockLen) return invalid("block must be in 1..16");
+    if (out->block < 1 || out->block > kMaxBlockLen) return invalid("block must be in 1..32");
     if (out->reliable_every < 1) return invalid("reliable_every must be >= 1");
     if (!g->u64) return invalid("solvers need the FP64 links (true residuals are FP64)");
     if (out->mode == RHMC_MODE_MIXED && !g->u32) return invalid("MIXED mode needs the FP32-12 links");
@@ -104,7 +104,7 @@ void rhmc_solver_params_default(rhmc_solver_params* p) {
     p->mode = RHMC_MODE_FP64;
     p->reliable_every = 50;
     p->refine = 1;
-    p->block = 10;
+    p->block = 25;
     p->use_graph = 1;
     p->poll_every = 0;
     p->tune = 0;
@@ -292,6 +292,25 @@ rhmc_status rhmc_rational_apply(const rhmc_gauge* gc, double m, const rhmc_ratio
     }
     return rational(g, m, rat, nrhs, reinterpret_cast<const double2*>(b),
                     reinterpret_cast<double2*>(y), prm, stats, stream);
+}
+
+rhmc_status rhmc_tune_dslash(rhmc_gauge* g, rhmc_prec prec, int32_t nrhs, const void* in,
+                             void* out, hipStream_t stream) {
+    if (!g || !in || !out) return invalid("null argument");
+    if (nrhs < 1 || nrhs > kMaxSys) return invalid("nrhs must be in 1..8");
+    if (in == out) return invalid("in and out must not overlap");
+    RHMC_TRY(check_prec(g, prec));
+    RHMC_TRY(use_device(g->device));
+    return tune_hop(g, prec, nrhs, in, out, stream);
+}
+
+rhmc_status rhmc_dslash_variant(const rhmc_gauge* g, rhmc_prec prec, int32_t nrhs,
+                                int32_t* variant) {
+    if (!g || !variant) return invalid("null argument");
+    if (nrhs < 1 || nrhs > 64) return invalid("nrhs must be in 1..64");
+    RHMC_TRY(check_prec(g, prec));
+    *variant = g->hop_variant[prec][nr_class(nrhs < kMaxSys ? nrhs : kMaxSys)];
+    return RHMC_OK;
 }
 
 const char* rhmc_status_string(rhmc_status s) {

@@ -14,19 +14,25 @@ struct VecArgs {
     VT* x[kMaxSys];
     VT* y[kMaxSys];
     VT* z[kMaxSys];
-    double* partial;
+    double* partial;        // this kernel's block sums ([nsys][nblk]); read by k_pupdate
+    int nblk;               // blocks per system of the kernel that wrote `partial`
+    const double* part2;    // block sums of the A kernel (<p, A p>)
+    int nblk2;
+    int q;                  // step index inside the current block
 };
 
 // Deferred update of the shifted solutions at a block boundary.
 template <typename VT>
 struct FlushArgs {
     void* state;
+    const void* coef;       // BlockCoef [kMaxSys][kMaxShift]
     size_t n;
     int nshift;
-    VT* ring[kMaxBlockLen + 1][kMaxSys];  // stored base residuals r(k0+l)
-    VT* P;                                // shifted directions [nsys][nshift][n]
-    double2* X;                           // shifted solutions
-    size_t x_sys, x_shift;                // element strides of X between systems / shifts
+    int nsys;
+    VT* ring;               // stored base residuals: r(k0+l) of system j at ring + (l*nsys + j)*n
+    VT* P;                  // shifted directions [nsys][nshift][n]
+    double2* X;             // shifted solutions
+    size_t x_sys, x_shift;  // element strides of X between systems / shifts
 };
 
 struct CombineArgs {

@@ -100,129 +100,204 @@ template <typename VT>
 __global__ __launch_bounds__(kBlock) void k_rupdate(VecArgs<VT> a) {
     SolverState* st = reinterpret_cast<SolverState*>(a.state);
     if (st->all_done) return;
+    __shared__ double smem[16];
     const int j = blockIdx.y;
-    double r2 = 0.0;
     const bool live = !st->sys[j].done;
-    const double alpha = st->sys[j].alpha;
-    for (size_t i = ((size_t)blockIdx.x * kBlock + threadIdx.x) * 2; live && i < a.n;
-         i += (size_t)gridDim.x * kBlock * 2) {
-        Pair<VT> r, ap;
-        r.load(a.x[j], i);
-        ap.load(a.y[j], i);
-        for (int k = 0; k < 2; ++k) {
-            const double nr = (double)r.re[k] - alpha * (double)ap.re[k];
-            const double ni = (double)r.im[k] - alpha * (double)ap.im[k];
-            r.re[k] = nr;
-            r.im[k] = ni;
-            r2 += (double)r.re[k] * r.re[k] + (double)r.im[k] * r.im[k];
+    double r2 = 0.0;
+    if (live) {
+        // alpha = rr / <p, A p>; every block adds the A-kernel partials itself,
+        // in the same fixed order, so all blocks use the same alpha bits
+        const double pap = block_sum_partials(a.part2, j, a.nblk2, smem);
+        const double alpha = st->sys[j].rr[a.q & 1] / pap;
+        for (size_t i = ((size_t)blockIdx.x * kBlock + threadIdx.x) * 2; i < a.n;
+             i += (size_t)gridDim.x * kBlock * 2) {
+            Pair<VT> r, ap;
+            r.load(a.x[j], i);
+            ap.load(a.y[j], i);
+            for (int k = 0; k < 2; ++k) {
+                const double nr = (double)r.re[k] - alpha * (double)ap.re[k];
+                const double ni = (double)r.im[k] - alpha * (double)ap.im[k];
+                r.re[k] = nr;
+                r.im[k] = ni;
+                r2 += (double)r.re[k] * r.re[k] + (double)r.im[k] * r.im[k];
+            }
+            r.store(a.z[j], i);
         }
-        r.store(a.z[j], i);
     }
     reduce_store(r2, 0.0, j, -1, a.partial);
 }
 
 // ------------------------------------------------------------------ p update
-// p(k+1) = r(k+1) + beta p(k)
+// p(k+1) = r(k+1) + beta p(k); block (0, 0) also runs the FP64 recurrences
+// of this step (iteration_update), which the other blocks do not read.
 template <typename VT>
 __global__ __launch_bounds__(kBlock) void k_pupdate(VecArgs<VT> a) {
-    const SolverState* st = reinterpret_cast<const SolverState*>(a.state);
-    if (st->all_done) return;
+    SolverState* st = reinterpret_cast<SolverState*>(a.state);
+    __shared__ double smem[16];
+    __shared__ int flags[2];
     const int j = blockIdx.y;
-    if (st->sys[j].done) return;
-    const size_t i = ((size_t)blockIdx.x * kBlock + threadIdx.x) * 2;
-    if (i >= a.n) return;
-    const double beta = st->sys[j].beta_prev;
-    Pair<VT> r, p;
-    r.load(a.x[j], i);
-    p.load(a.y[j], i);
-    for (int k = 0; k < 2; ++k) {
-        p.re[k] = (double)r.re[k] + beta * (double)p.re[k];
-        p.im[k] = (double)r.im[k] + beta * (double)p.im[k];
+    // Block (0, 0) writes done / all_done during this kernel: every other block
+    // reads them once, through shared memory, so its threads agree on the
+    // branches around the barriers below.
+    if (threadIdx.x == 0) {
+        flags[0] = st->all_done;
+        flags[1] = st->sys[j].done;
     }
-    p.store(a.y[j], i);
+    __syncthreads();
+    if (flags[0]) return;
+    if (!flags[1]) {
+        const double rrn = block_sum_partials(a.partial, j, a.nblk, smem);
+        const double beta = rrn / st->sys[j].rr[a.q & 1];
+        for (size_t i = ((size_t)blockIdx.x * kBlock + threadIdx.x) * 2; i < a.n;
+             i += (size_t)gridDim.x * kBlock * 2) {
+            Pair<VT> r, p;
+            r.load(a.x[j], i);
+            p.load(a.y[j], i);
+            for (int k = 0; k < 2; ++k) {
+                p.re[k] = (double)r.re[k] + beta * (double)p.re[k];
+                p.im[k] = (double)r.im[k] + beta * (double)p.im[k];
+            }
+            p.store(a.y[j], i);
+        }
+    }
+    if (blockIdx.x == 0 && blockIdx.y == 0) {
+        __syncthreads();
+        iteration_update(st, a.part2, a.nblk2, a.partial, a.nblk, a.q);
+    }
 }
 
 // ------------------------------------------------------------------ flush
-// Apply the coefficients accumulated since the last block boundary:
-//   X_i <- X_i + e P_i + sum_l f[l] r_l,   P_i <- c P_i + sum_l d[l] r_l
-// for every shift active when the block started, then r_0 <- r_q and reset.
+// Block coefficients of every shift that took part in the block (one block,
+// one thread per (system, shift)); run before k_flush.
+__global__ __launch_bounds__(kBlock) void k_flush_coef(void* state) {
+    SolverState* st = reinterpret_cast<SolverState*>(state);
+    const int nsys = st->nsys, nsh = st->nshift;
+    for (int p = threadIdx.x; p < nsys * nsh; p += blockDim.x) {
+        const int j = p / nsh, i = p % nsh;
+        const ShiftScalars& h = st->sh[j][i];
+        if (h.block_active) flush_coefficients(st->coef[j * kMaxShift + i], h.nsteps);
+    }
+}
+
+template <typename VT> struct Comp;
+template <> struct Comp<float2> { using type = float; };
+template <> struct Comp<double2> { using type = double; };
+
+// One thread per complex element of one system's vectors: the q+1 stored base
+// residuals stay in registers while every shift's X and P stream through
+// once.  Shifts go in chunks of U: their loads are issued together, then each
+// residual is widened to FP64 once and applied to all U shifts.
 template <typename VT, int Q>
-__device__ __forceinline__ void flush_site(const FlushArgs<VT>& a, const SolverState* st, int j,
-                                           size_t i) {
-    const SysScalars& s = st->sys[j];
-    const int q = s.blk_steps;
-    Pair<VT> rl[Q + 1];
+__global__ __launch_bounds__(kBlock) void k_flush(FlushArgs<VT> a) {
+    using RT = typename Comp<VT>::type;
+    constexpr int U = (sizeof(VT) == 16 && Q > 16) ? 2 : 4;
+    const SolverState* st = reinterpret_cast<const SolverState*>(a.state);
+    const BlockCoef* coef = reinterpret_cast<const BlockCoef*>(a.coef);
+    const int j = blockIdx.y;
+    const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    const int q = st->sys[j].blk_steps;
+    if (q == 0 || i >= a.n) return;
+    RT rre[Q + 1], rim[Q + 1];
 #pragma unroll
     for (int l = 0; l <= Q; ++l)
-        if (l <= q) rl[l].load(a.ring[l][j], i);
-    const int first = st->first_block;
-    for (int sh = 0; sh < st->nshift; ++sh) {
-        const ShiftScalars& h = st->sh[j][sh];
-        if (!h.block_active) continue;
-        Pair<VT> P;
-        Pair<double2> X;
-        if (first) {
-            P = rl[0];
-            X.re[0] = X.re[1] = X.im[0] = X.im[1] = 0.0;
-        } else {
-            P.load(a.P + ((size_t)j * a.nshift + sh) * a.n, i);
-            X.load(a.X + j * a.x_sys + sh * a.x_shift, i);
+        if (l <= q) {
+            const VT v = a.ring[((size_t)l * a.nsys + j) * a.n + i];
+            rre[l] = v.x;
+            rim[l] = v.y;
         }
-        double xr[2], xi[2], pr[2], pi[2];
-        for (int k = 0; k < 2; ++k) {
-            xr[k] = X.re[k] + h.e * (double)P.re[k];
-            xi[k] = X.im[k] + h.e * (double)P.im[k];
-            pr[k] = h.c * (double)P.re[k];
-            pi[k] = h.c * (double)P.im[k];
+    const bool first = st->first_block != 0;
+    const int nsh = a.nshift;
+    for (int s0 = 0; s0 < nsh; s0 += U) {
+        // keep the widening of the residuals inside this chunk (not hoisted
+        // out of the shift loop, which would hold them all as FP64)
+#pragma unroll
+        for (int l = 0; l <= Q; ++l) asm volatile("" : "+v"(rre[l]), "+v"(rim[l]));
+        bool act[U];
+        int qi[U];
+        double xr[U], xi[U], pr[U], pi[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int sh = s0 + u;
+            act[u] = sh < nsh && st->sh[j][sh].block_active;
+            qi[u] = act[u] ? st->sh[j][sh].nsteps : 0;
+            xr[u] = xi[u] = pr[u] = pi[u] = 0.0;
+            if (act[u]) {
+                double p0r, p0i;
+                if (first) {
+                    p0r = (double)rre[0];
+                    p0i = (double)rim[0];
+                } else {
+                    const double2 x = a.X[j * a.x_sys + sh * a.x_shift + i];
+                    const VT p = a.P[((size_t)j * nsh + sh) * a.n + i];
+                    xr[u] = x.x;
+                    xi[u] = x.y;
+                    p0r = (double)p.x;
+                    p0i = (double)p.y;
+                }
+                const BlockCoef& bc = coef[j * kMaxShift + sh];
+                xr[u] += bc.e * p0r;
+                xi[u] += bc.e * p0i;
+                pr[u] = bc.c * p0r;
+                pi[u] = bc.c * p0i;
+            }
         }
 #pragma unroll
         for (int l = 1; l <= Q; ++l) {
-            if (l > q) break;
-            const double f = h.f[l], d = h.d[l];
-            for (int k = 0; k < 2; ++k) {
-                xr[k] += f * (double)rl[l].re[k];
-                xi[k] += f * (double)rl[l].im[k];
-                pr[k] += d * (double)rl[l].re[k];
-                pi[k] += d * (double)rl[l].im[k];
+            if (l <= q) {
+                const double rr = (double)rre[l], ri = (double)rim[l];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    if (l <= qi[u]) {
+                        const BlockCoef& bc = coef[j * kMaxShift + s0 + u];
+                        const double f = bc.f[l], d = bc.d[l];
+                        xr[u] += f * rr;
+                        xi[u] += f * ri;
+                        pr[u] += d * rr;
+                        pi[u] += d * ri;
+                    }
+                }
             }
         }
-        for (int k = 0; k < 2; ++k) {
-            X.re[k] = xr[k];
-            X.im[k] = xi[k];
-        }
-        X.store(a.X + j * a.x_sys + sh * a.x_shift, i);
-        if (h.active) {
-            for (int k = 0; k < 2; ++k) {
-                P.re[k] = pr[k];
-                P.im[k] = pi[k];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (!act[u]) continue;
+            const int sh = s0 + u;
+            a.X[j * a.x_sys + sh * a.x_shift + i] = make_double2(xr[u], xi[u]);
+            if (st->sh[j][sh].active) {
+                VT pv;
+                pv.x = (RT)pr[u];
+                pv.y = (RT)pi[u];
+                a.P[((size_t)j * nsh + sh) * a.n + i] = pv;
             }
-            P.store(a.P + ((size_t)j * a.nshift + sh) * a.n, i);
         }
     }
-    if (q > 0) rl[q > Q ? Q : q].store(a.ring[0][j], i);
+    // the last stored residual is r(k0) of the next block
+#pragma unroll
+    for (int l = 1; l <= Q; ++l)
+        if (l == q) {
+            VT v;
+            v.x = rre[l];
+            v.y = rim[l];
+            a.ring[(size_t)j * a.n + i] = v;
+        }
 }
 
-template <typename VT, int Q>
-__global__ __launch_bounds__(kBlock) void k_flush(FlushArgs<VT> a) {
-    const SolverState* st = reinterpret_cast<const SolverState*>(a.state);
-    const int j = blockIdx.y;
-    const size_t i = ((size_t)blockIdx.x * kBlock + threadIdx.x) * 2;
-    if (st->sys[j].blk_steps > 0 && i < a.n) flush_site<VT, Q>(a, st, j, i);
-}
-
-// After a flush: restart the block coefficients (one block).
+// After a flush: restart the block bookkeeping (one block).
 __global__ __launch_bounds__(kBlock) void k_flush_reset(void* state) {
     SolverState* st = reinterpret_cast<SolverState*>(state);
     const int nsys = st->nsys, nsh = st->nshift;
     for (int p = threadIdx.x; p < nsys * nsh; p += blockDim.x) {
         ShiftScalars& h = st->sh[p / nsh][p % nsh];
-        h.c = 1.0;
-        h.e = 0.0;
-        for (int l = 0; l <= kMaxBlockLen; ++l) h.d[l] = h.f[l] = 0.0;
+        h.nsteps = 0;
         h.block_active = h.active;
     }
     __syncthreads();
-    if (threadIdx.x < nsys) st->sys[threadIdx.x].blk_steps = 0;
+    if (threadIdx.x < nsys) {
+        SysScalars& s = st->sys[threadIdx.x];
+        if (st->blk_it & 1) s.rr[0] = s.rr[1];   // the next block starts at step 0
+        s.blk_steps = 0;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
         st->first_block = 0;
         st->blk_it = 0;
@@ -275,7 +350,7 @@ static dim3 vec_grid(size_t n, int nsys) {
 
 // reducing kernels stride over the vector with at most kRedBlocks blocks per
 // system, which bounds the number of partial sums the finalize has to add
-constexpr int kRedBlocks = 1024;
+constexpr int kRedBlocks = 512;
 static dim3 red_grid(size_t n, int nsys) { return dim3((unsigned)vec_blocks(n), (unsigned)nsys); }
 
 template <typename VT>
@@ -290,7 +365,7 @@ hipError_t launch_rupdate(const VecArgs<VT>& a, int nsys, hipStream_t s) {
 }
 template <typename VT>
 hipError_t launch_pupdate(const VecArgs<VT>& a, int nsys, hipStream_t s) {
-    hipLaunchKernelGGL(k_pupdate<VT>, vec_grid(a.n, nsys), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_pupdate<VT>, red_grid(a.n, nsys), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 int vec_blocks(size_t n) {
@@ -307,17 +382,16 @@ hipError_t launch_finalize(int kind, void* state, const double* partial, int nbl
 
 template <typename VT>
 hipError_t launch_flush(const FlushArgs<VT>& a, int nsys, int qmax, hipStream_t s) {
-    const dim3 g = vec_grid(a.n, nsys), b(kBlock);
+    hipLaunchKernelGGL(k_flush_coef, dim3(1), dim3(kBlock), 0, s, a.state);
+    const dim3 g((unsigned)((a.n + kBlock - 1) / kBlock), (unsigned)nsys), b(kBlock);
     if (qmax <= 4)
         hipLaunchKernelGGL((k_flush<VT, 4>), g, b, 0, s, a);
     else if (qmax <= 8)
         hipLaunchKernelGGL((k_flush<VT, 8>), g, b, 0, s, a);
-    else if (qmax <= 12)
-        hipLaunchKernelGGL((k_flush<VT, 12>), g, b, 0, s, a);
-    else
+    else if (qmax <= 16)
         hipLaunchKernelGGL((k_flush<VT, 16>), g, b, 0, s, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    else
+        hipLaunchKernelGGL((k_flush<VT, 32>), g, b, 0, s, a);
     hipLaunchKernelGGL(k_flush_reset, dim3(1), dim3(kBlock), 0, s, a.state);
     return hipGetLastError();
 }

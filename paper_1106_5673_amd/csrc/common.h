@@ -41,7 +41,7 @@ struct Geom {
 constexpr int kBlock = 256;       // threads per block for every kernel
 constexpr int kMaxSys = 8;        // right-hand sides per operator launch
 constexpr int kMaxShift = 32;
-constexpr int kMaxBlockLen = 16;  // iterations between shifted-solution updates
+constexpr int kMaxBlockLen = 32;  // iterations between shifted-solution updates
 
 #if defined(__HIPCC__)
 // Blocks of a launch are dispatched round-robin over the eight XCDs; give
@@ -65,9 +65,13 @@ __device__ __forceinline__ void site_coords(const Geom& g, int eo, int par, int&
 }
 
 // Site visited by processing index p (0 <= p < Vh) of a hopping launch.
-// order 0 walks the eo index itself (x fastest, then y, z, t); order 1 walks
-// x, y, t, z, so that consecutive sites of one XCD's contiguous range share
-// z-planes and the reuse distance of the z and t neighbours stays small.
+// Blocks give each XCD a contiguous range of p, so the order decides how far
+// apart (in sites processed) the eight uses of an input site are:
+//   0: the eo index itself (x fastest, then y, z, t)
+//   1: x, y, t, z             (t neighbours one xy-plane apart)
+//   2: x, y, z mod 4, t, z/4  (z-tiles of 4 planes, t inside the tile)
+//   3: x, y, z mod 2, t, z/2  (z-tiles of 2 planes)
+// Order 2 needs Lz % 4 == 0 (the launcher falls back to 1 otherwise).
 __device__ __forceinline__ void process_site(const Geom& g, int p, int par, int order, int& eo,
                                              int& x, int& y, int& z, int& t) {
     if (order == 0) {
@@ -79,8 +83,16 @@ __device__ __forceinline__ void process_site(const Geom& g, int p, int par, int 
     int r = p / g.hx;
     y = r % g.Ly;
     r /= g.Ly;
-    t = r % g.Lt;
-    z = r / g.Lt;
+    if (order == 1) {
+        t = r % g.Lt;
+        z = r / g.Lt;
+    } else {
+        const int T = order == 2 ? 4 : 2;
+        const int tz = r % T;
+        r /= T;
+        t = r % g.Lt;
+        z = (r / g.Lt) * T + tz;
+    }
     eo = xh + g.hx * (y + g.Ly * (z + g.Lz * t));
     x = 2 * xh + ((par + y + z + t) & 1);
 }
@@ -182,12 +194,12 @@ struct DslashArgs {
     int variant;                  // launch variant (HopVariant index)
 };
 
-// Launch variants of the hopping kernel, index = order | nt << 1 | pipe << 2:
-//   order  site processing order (process_site)
+// Launch variants of the hopping kernel, index = order | nt << 2 | pipe << 3:
+//   order  site processing order (process_site), 0..3
 //   nt     non-temporal (streaming) loads of the links, which are read once
 //          per application and need not displace neighbour vectors
 //   pipe   issue the loads of two hops as one batch instead of one
-constexpr int kHopVariants = 8;
+constexpr int kHopVariants = 16;
 // right-hand-side classes of the kernel templates: 1, 2, 4, 8
 inline int nr_class(int nrhs) { return nrhs <= 1 ? 0 : nrhs <= 2 ? 1 : nrhs <= 4 ? 2 : 3; }
 // measured defaults on MI355X (48^3 x 12), [precision][rhs class]

@@ -6,10 +6,7 @@
 // Links are structure-of-arrays over the link index k = (2*mu + parity)*Vh + eo,
 // so the 64 lanes of a wave read 64 consecutive links per load; neighbour
 // vectors are colour-major [3][Vh] arrays, read by consecutive sites.
-#include <cstdlib>
-
 #include "common.h"
-#include "state.h"
 
 namespace rhmc {
 
@@ -172,7 +169,7 @@ __global__ __launch_bounds__(kBlock) void k_dslash(const LT* __restrict__ links,
 
     if (p < Vh) {
         int eo, x, y, z, t;
-        process_site(a.g, p, a.out_par, a.variant & 1, eo, x, y, z, t);
+        process_site(a.g, p, a.out_par, a.variant & 3, eo, x, y, z, t);
         const Hops h = make_hops(a.g, eo, x, y, z, t);
         RT ar[NR][3], ai[NR][3];
 #pragma unroll
@@ -307,21 +304,6 @@ __global__ __launch_bounds__(kBlock) void k_dslash(const LT* __restrict__ links,
 
 int dslash_grid(int Vh) { return (Vh + kBlock - 1) / kBlock; }
 
-void default_hop_variants(int (&v)[2][4]) {
-    // index = order | nt << 1 | pipe << 2
-    const int fp64[4] = {3, 3, 6, 6};
-    const int fp32[4] = {5, 7, 7, 6};
-    for (int k = 0; k < 4; ++k) {
-        v[RHMC_PREC_FP64][k] = fp64[k];
-        v[RHMC_PREC_FP32][k] = fp32[k];
-    }
-    if (const char* e = std::getenv("RHMC_HOP_VARIANT")) {
-        const int f = std::atoi(e) & (kHopVariants - 1);
-        for (auto& row : v)
-            for (int& x : row) x = f;
-    }
-}
-
 template <typename VT, typename LT, int MODE, bool NT, bool PIPE>
 static hipError_t dispatch_nt(const LT* links, int nlinks, const DslashArgs<VT>& a, hipStream_t s) {
     const dim3 grid(dslash_grid(a.g.Vh)), block(kBlock);
@@ -339,8 +321,10 @@ static hipError_t dispatch_nt(const LT* links, int nlinks, const DslashArgs<VT>&
 template <typename VT, typename LT, int MODE>
 static hipError_t dispatch(const LT* links, int nlinks, const DslashArgs<VT>& a0, hipStream_t s) {
     DslashArgs<VT> a = a0;
-    const int v = a.variant & (kHopVariants - 1);
-    const bool nt = (v >> 1) & 1, pipe = (v >> 2) & 1;
+    int v = a.variant & (kHopVariants - 1);
+    if ((v & 3) == 2 && a.g.Lz % 4 != 0) v = (v & ~3) | 1;   // z-tiles of 4 need Lz % 4 == 0
+    a.variant = v;
+    const bool nt = (v >> 2) & 1, pipe = (v >> 3) & 1;
     if (pipe) {
         if (nt) return dispatch_nt<VT, LT, MODE, true, true>(links, nlinks, a, s);
         return dispatch_nt<VT, LT, MODE, false, true>(links, nlinks, a, s);
@@ -356,67 +340,6 @@ hipError_t launch_dslash64(const double2* u64, int nlinks, const DslashArgs<doub
         case kModeA: return dispatch<double2, double2, kModeA>(u64, nlinks, a, s);
         default: return dispatch<double2, double2, kModeResid>(u64, nlinks, a, s);
     }
-}
-
-rhmc_status tune_hop(rhmc_gauge* g, rhmc_prec prec, int nrhs, const void* in, void* out,
-                     hipStream_t s) {
-    const int cls = nr_class(nrhs);
-    const int nlinks = (int)(4 * g->lat.V);
-    const size_t n = (size_t)3 * g->lat.Vh;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    RHMC_HIP_TRY(hipEventCreate(&e0));
-    RHMC_HIP_TRY(hipEventCreate(&e1));
-    float best = 1e30f;
-    int best_v = g->hop_variant[prec][cls];
-    for (int v = 0; v < kHopVariants; ++v) {
-        hipError_t err = hipSuccess;
-        auto launch = [&]() {
-            if (prec == RHMC_PREC_FP64) {
-                DslashArgs<double2> a{};
-                a.g = g->lat.geom;
-                a.out_par = 1;
-                a.nrhs = nrhs;
-                a.variant = v;
-                for (int r = 0; r < nrhs; ++r) {
-                    a.in[r] = reinterpret_cast<const double2*>(in) + r * n;
-                    a.out[r] = reinterpret_cast<double2*>(out) + r * n;
-                }
-                err = launch_dslash64(g->u64, nlinks, a, kModeD, s);
-            } else {
-                DslashArgs<float2> a{};
-                a.g = g->lat.geom;
-                a.out_par = 1;
-                a.nrhs = nrhs;
-                a.variant = v;
-                for (int r = 0; r < nrhs; ++r) {
-                    a.in[r] = reinterpret_cast<const float2*>(in) + r * n;
-                    a.out[r] = reinterpret_cast<float2*>(out) + r * n;
-                }
-                err = launch_dslash32(g->u32, nlinks, a, kModeD, s);
-            }
-        };
-        for (int w = 0; w < 2 && err == hipSuccess; ++w) launch();
-        if (err == hipSuccess) err = hipEventRecord(e0, s);
-        for (int w = 0; w < 5 && err == hipSuccess; ++w) launch();
-        if (err == hipSuccess) err = hipEventRecord(e1, s);
-        if (err == hipSuccess) err = hipEventSynchronize(e1);
-        float ms = 0.f;
-        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
-        if (err != hipSuccess) {
-            hipEventDestroy(e0);
-            hipEventDestroy(e1);
-            RHMC_HIP_TRY(err);
-        }
-        if (ms < best) {
-            best = ms;
-            best_v = v;
-        }
-    }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    g->hop_variant[prec][cls] = best_v;
-    g->hop_tuned[prec][cls] = 1;
-    return RHMC_OK;
 }
 
 hipError_t launch_dslash32(const float4* u32, int nlinks, const DslashArgs<float2>& a, int mode,

@@ -59,9 +59,11 @@ struct Workspace {
     double2* t64 = nullptr;    // [kMaxSys] odd parity, FP64
     double2* rb = nullptr;     // [kMaxSys] refinement right-hand sides
     double2* rx = nullptr;     // [kMaxSys] refinement corrections
-    double* partial = nullptr;
+    double* partial = nullptr;     // two regions of [kMaxSys][part_stride] block sums
+    size_t part_stride = 0;
     double* sums = nullptr;        // [kMaxSys]
     SolverState* st = nullptr;     // device
+    BlockCoef* coef = nullptr;     // device [kMaxSys][kMaxShift]
     SolverState* hst = nullptr;    // pinned host mirror
     int* flags_host = nullptr;     // pinned [2]
     double* sums_host = nullptr;   // pinned [kMaxSys]
@@ -87,7 +89,7 @@ void workspace_destroy(Workspace* w) {
     free_graphs(w);
     for (void* p : {w->ring, w->p, w->Ap, w->t, w->P, (void*)w->t64, (void*)w->rb, (void*)w->rx,
                     (void*)w->xr, (void*)w->partial, (void*)w->sums,
-                    (void*)w->st})
+                    (void*)w->st, (void*)w->coef})
         hipFree(p);
     hipHostFree(w->hst);
     hipHostFree(w->flags_host);
@@ -132,10 +134,11 @@ static rhmc_status ensure_workspace(rhmc_gauge* g, int nsys, int nshift, int K) 
         RHMC_TRY(alloc((void**)&w->t64, vb * kMaxSys));
         RHMC_TRY(alloc((void**)&w->rb, vb * kMaxSys));
         RHMC_TRY(alloc((void**)&w->rx, vb * kMaxSys));
-        const size_t nblk = w->n / 2 / kBlock + 2;
-        RHMC_TRY(alloc((void**)&w->partial, sizeof(double) * 2 * kMaxSys * nblk));
+        w->part_stride = w->n / 2 / kBlock + 2;
+        RHMC_TRY(alloc((void**)&w->partial, sizeof(double) * 2 * kMaxSys * w->part_stride));
         RHMC_TRY(alloc((void**)&w->sums, sizeof(double) * kMaxSys));
         RHMC_TRY(alloc((void**)&w->st, sizeof(SolverState)));
+        RHMC_TRY(alloc((void**)&w->coef, sizeof(BlockCoef) * kMaxSys * kMaxShift));
         RHMC_HIP_TRY(hipHostMalloc((void**)&w->hst, sizeof(SolverState), hipHostMallocDefault));
         RHMC_HIP_TRY(hipHostMalloc((void**)&w->flags_host, sizeof(int) * 2, hipHostMallocDefault));
         RHMC_HIP_TRY(hipHostMalloc((void**)&w->sums_host, sizeof(double) * kMaxSys, hipHostMallocDefault));
@@ -220,33 +223,38 @@ static rhmc_status enqueue_block(const rhmc_gauge* g, Workspace* w, const Proble
             RHMC_HIP_TRY(launch_dslash64(g->u64, nlinks, d, kModeD, s));
             RHMC_HIP_TRY(launch_dslash64(g->u64, nlinks, a, kModeA, s));
         }
-        RHMC_HIP_TRY(launch_finalize(kFinAlpha, w->st, w->partial, dgrid, ns, nullptr, s));
+        // r' = r - alpha A p (alpha from the A-kernel sums) and its block sums
+        double* partR = w->partial + kMaxSys * w->part_stride;
         VecArgs<VT> r{};
         r.state = w->st;
         r.n = n;
-        r.partial = w->partial;
+        r.partial = partR;
+        r.nblk = vgrid;
+        r.part2 = w->partial;
+        r.nblk2 = dgrid;
+        r.q = q;
         for (int j = 0; j < ns; ++j) {
             r.x[j] = vec<VT>(w->ring, n, (size_t)q * ns + j);
             r.y[j] = vec<VT>(w->Ap, n, j);
             r.z[j] = vec<VT>(w->ring, n, (size_t)(q + 1) * ns + j);
         }
         RHMC_HIP_TRY(launch_rupdate<VT>(r, ns, s));
-        RHMC_HIP_TRY(launch_finalize(kFinBeta, w->st, w->partial, vgrid, ns, nullptr, s));
-        VecArgs<VT> p{};
-        p.state = w->st;
-        p.n = n;
+        // p = r' + beta p, and the FP64 recurrences of this step
+        VecArgs<VT> p = r;
         for (int j = 0; j < ns; ++j) {
             p.x[j] = vec<VT>(w->ring, n, (size_t)(q + 1) * ns + j);
             p.y[j] = vec<VT>(w->p, n, j);
+            p.z[j] = nullptr;
         }
         RHMC_HIP_TRY(launch_pupdate<VT>(p, ns, s));
     }
     FlushArgs<VT> f{};
     f.state = w->st;
+    f.coef = w->coef;
     f.n = n;
     f.nshift = pb.nshift;
-    for (int l = 0; l <= pb.K; ++l)
-        for (int j = 0; j < ns; ++j) f.ring[l][j] = vec<VT>(w->ring, n, (size_t)l * ns + j);
+    f.nsys = ns;
+    f.ring = reinterpret_cast<VT*>(w->ring);
     f.P = reinterpret_cast<VT*>(w->P);
     f.X = pb.X;
     f.x_sys = pb.x_sys;
@@ -345,14 +353,14 @@ static rhmc_status run_krylov(rhmc_gauge* g, const Problem& pb, hipStream_t s, i
     h->nshift = pb.nshift;
     h->first_block = 1;
     h->maxiter = pb.maxiter;
+    h->coef = w->coef;
     for (int j = 0; j < pb.nsys; ++j) {
         h->sys[j].tolb = pb.tol[j];
         h->sys[j].base = pb.base[j];
         for (int i = 0; i < pb.nshift; ++i) {
             ShiftScalars& q = h->sh[j][i];
             q.off = pb.off[j][i];
-            q.zeta = q.zeta_prev = q.zeta_next = 1.0;
-            q.c = 1.0;
+            q.zeta = q.zeta_prev = 1.0;
             q.active = q.block_active = 1;
         }
     }

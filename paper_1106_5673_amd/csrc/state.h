@@ -3,9 +3,9 @@
 // Eq. shifted are solved from the Krylov space of the smallest shift, with the
 // shifted residuals kept collinear with the base one, r_i = zeta_i r).
 //
-// The recurrences run inside the last workgroup of the kernel that produces
-// the reduction they need, so a CG iteration needs no host round trip and can
-// be replayed from a hipGraph.
+// No host round trip is needed inside the iteration loop: every kernel reads
+// the scalars it needs from device memory, and one block updates them, so a
+// block of iterations can be replayed from a hipGraph.
 #pragma once
 
 #include "common.h"
@@ -13,9 +13,8 @@
 namespace rhmc {
 
 struct SysScalars {
-    double rr;          // <r, r> of the current residual
-    double alpha, alpha_prev, beta_prev;
-    double pAp;
+    double rr[2];       // <r, r>, double-buffered by step parity (see iteration_update)
+    double alpha_prev, beta_prev;
     double bnorm;       // ||b|| (FP64)
     double tolb;        // tol * ||b||
     int done;           // every shift of this system met its tolerance (or maxiter)
@@ -24,23 +23,32 @@ struct SysScalars {
     int blk_steps;      // iterations this system completed in the current block
 };
 
-// Shifted solutions are not touched every iteration.  Between two block
-// boundaries k0 and k0+q the recurrences x_i += a_i p_i, p_i = z_i r + b_i p_i
-// are carried as coefficients on P = p_i(k0), X = x_i(k0) and the stored base
-// residuals r(k0+1..k0+q):
+// Shifted solutions are not touched every iteration.  Inside a block of
+// iterations starting at k0 the recurrences of shift i,
+//   x_i(k+1) = x_i(k) + a_i(k) p_i(k),   p_i(k+1) = zeta_i(k+1) r(k+1) + b_i(k) p_i(k),
+// only record their scalars; at the block boundary they are folded into
+// coefficients on P = p_i(k0), X = x_i(k0) and the stored base residuals
+// r(k0+1..k0+q):
 //   p_i(k0+q) = c P + sum_l d[l] r(k0+l)
 //   x_i(k0+q) = X + e P + sum_l f[l] r(k0+l)
 struct ShiftScalars {
     double off;                 // sigma_i - sigma_0 >= 0
-    double zeta, zeta_prev, zeta_next;
-    double a;                   // alpha_i of the current step
-    double c, e;
-    double d[kMaxBlockLen + 1];
-    double f[kMaxBlockLen + 1];
+    double zeta, zeta_prev;
     int active;                 // still iterating
     int block_active;           // active when the current block started
     int conv_iter;
-    int pad;
+    int nsteps;                 // steps of the current block applied to this shift
+};
+
+// Per-step scalars of one shift in the current block (index m = k - k0) and
+// the block coefficients computed from them (flush_coefficients).
+struct BlockCoef {
+    double a[kMaxBlockLen];
+    double b[kMaxBlockLen];
+    double z[kMaxBlockLen + 1];   // z[l] = zeta_i(k0 + l)
+    double c, e;
+    double d[kMaxBlockLen + 1];
+    double f[kMaxBlockLen + 1];
 };
 
 struct SolverState {
@@ -51,6 +59,7 @@ struct SolverState {
     int iter;          // iterations completed by the shared solve
     int maxiter;
     int reliable_count;
+    BlockCoef* coef;   // device [kMaxSys][kMaxShift]
     SysScalars sys[kMaxSys];
     ShiftScalars sh[kMaxSys][kMaxShift];
 };
@@ -58,15 +67,14 @@ struct SolverState {
 enum FinalizeKind {
     kFinNone = 0,
     kFinInit = 1,      // after the start kernel: ||b||, rr
-    kFinAlpha = 2,     // after A p: alpha, zeta_next, a_i
-    kFinBeta = 3,      // after r -= alpha A p: beta, b_i, block coefficients, convergence
     kFinReliable = 4,  // after r = b - A x in FP64: rr
     kFinNorms = 5      // plain per-rhs sums into an output array
 };
 
 #if defined(__HIPCC__)
 
-// Sum partial[r*nblk + 0..nblk-1] over all threads of the block, fixed order.
+// Sum partial[r*nblk + 0..nblk-1] over all threads of the block, in a fixed
+// order (so every block that calls it gets the same bits).
 __device__ inline double block_sum_partials(const double* partial, int r, int nblk,
                                             double* smem) {
     double s = 0.0;
@@ -83,7 +91,7 @@ __device__ inline double block_sum_partials(const double* partial, int r, int nb
     return t;
 }
 
-// Runs in the last block of a reducing kernel (all its threads).
+// One-block finalize for the rare reductions (start, reliable update, norms).
 __device__ inline void solver_finalize(int kind, void* vstate, const double* partial, int nblk,
                                        int nrhs, double* out_sums) {
     __shared__ double smem[16];
@@ -97,7 +105,6 @@ __device__ inline void solver_finalize(int kind, void* vstate, const double* par
     }
     SolverState* st = reinterpret_cast<SolverState*>(vstate);
     const int nsys = st->nsys;
-    const int nsh = st->nshift;
     const int nsum = (kind == kFinInit) ? 2 * nsys : nsys;
     for (int r = 0; r < nsum; ++r) {
         const double t = block_sum_partials(partial, r, nblk, smem);
@@ -105,15 +112,13 @@ __device__ inline void solver_finalize(int kind, void* vstate, const double* par
     }
     __syncthreads();
     const int tid = threadIdx.x;
-
     if (kind == kFinInit) {
         if (tid < nsys) {
             SysScalars& s = st->sys[tid];
             const double b2 = sums[tid];
             s.bnorm = sqrt(b2);
             s.tolb = s.tolb * s.bnorm;   // tolb held the relative tolerance until now
-            s.rr = sums[nsys + tid];
-            s.alpha = 0.0;
+            s.rr[0] = s.rr[1] = sums[nsys + tid];
             s.alpha_prev = 1.0;
             s.beta_prev = 0.0;
             s.iters = 0;
@@ -127,80 +132,60 @@ __device__ inline void solver_finalize(int kind, void* vstate, const double* par
         }
         return;
     }
+    // kFinReliable: the residual was replaced at a block boundary (slot 0)
+    if (tid < nsys && !st->sys[tid].done) st->sys[tid].rr[0] = sums[tid];
+    if (tid == 0) st->reliable_count += 1;
+}
 
-    if (kind == kFinReliable) {
-        if (tid < nsys && !st->sys[tid].done) st->sys[tid].rr = sums[tid];
-        if (tid == 0) st->reliable_count += 1;
-        return;
-    }
-
-    if (kind == kFinAlpha) {
-        if (tid < nsys) {
-            SysScalars& s = st->sys[tid];
-            if (!s.done) {
-                s.pAp = sums[tid];
-                s.alpha = s.rr / s.pAp;
-            }
-        }
-        __syncthreads();
-        for (int p = tid; p < nsys * nsh; p += blockDim.x) {
-            const int j = p / nsh, i = p % nsh;
-            const SysScalars s = st->sys[j];
-            ShiftScalars* hp = &st->sh[j][i];
-            if (s.done || !hp->active) continue;
-            const double zeta = hp->zeta, zeta_prev = hp->zeta_prev, off = hp->off;
-            const double a = s.alpha;
-            const double zn = zeta * zeta_prev * s.alpha_prev /
-                              (zeta_prev * s.alpha_prev * (1.0 + a * off) +
-                               a * s.beta_prev * (zeta_prev - zeta));
-            hp->zeta_next = zn;
-            hp->a = a * zn / zeta;
-        }
-        return;
-    }
-
-    // kFinBeta
-    __shared__ double beta_s[kMaxSys];
+// The FP64 recurrences of one CG step q of the current block (block 0 of the
+// p-update kernel runs this while the other blocks update p):
+//   alpha = rr / <p, A p>, zeta_i', alpha_i, beta = rr' / rr, beta_i,
+//   the step's scalars of every shift, convergence and counters.
+// rr for step q is in rr[q & 1]; the new one goes to rr[(q + 1) & 1], which no
+// kernel of this step reads.
+__device__ inline void iteration_update(SolverState* st, const double* partA, int nblkA,
+                                        const double* partR, int nblkR, int q_step) {
+    __shared__ double smem[16];
+    __shared__ double pap_s[kMaxSys], rrn_s[kMaxSys];
     __shared__ int alive_s[kMaxSys];
-    if (tid < nsys) {
-        SysScalars& s = st->sys[tid];
-        beta_s[tid] = s.done ? 0.0 : sums[tid] / s.rr;
-        alive_s[tid] = 0;
+    const int nsys = st->nsys, nsh = st->nshift;
+    const int cur = q_step & 1, nxt = cur ^ 1;
+    for (int j = 0; j < nsys; ++j) {
+        const double a = block_sum_partials(partA, j, nblkA, smem);
+        const double b = block_sum_partials(partR, j, nblkR, smem);
+        if (threadIdx.x == 0) {
+            pap_s[j] = a;
+            rrn_s[j] = b;
+            alive_s[j] = 0;
+        }
     }
     __syncthreads();
-    const int q_all = st->blk_it;
+    const int tid = threadIdx.x;
     for (int p = tid; p < nsys * nsh; p += blockDim.x) {
         const int j = p / nsh, i = p % nsh;
-        const SysScalars s = st->sys[j];
-        ShiftScalars* hp = &st->sh[j][i];
-        if (s.done || !hp->active) continue;
-        // one bulk copy into registers, update, one bulk copy back
-        ShiftScalars h = *hp;
+        const SysScalars& s = st->sys[j];
+        ShiftScalars& h = st->sh[j][i];
+        if (s.done || !h.active) continue;
+        const double rr = s.rr[cur];
+        const double alpha = rr / pap_s[j];
+        const double beta = rrn_s[j] / rr;
+        const double zeta = h.zeta, zeta_prev = h.zeta_prev;
+        const double zn = zeta * zeta_prev * s.alpha_prev /
+                          (zeta_prev * s.alpha_prev * (1.0 + alpha * h.off) +
+                           alpha * s.beta_prev * (zeta_prev - zeta));
+        const double ratio = zn / zeta;
         const int q = s.blk_steps;   // this step's index inside the block (0-based)
-        const double ratio = h.zeta_next / h.zeta;
-        const double bi = beta_s[j] * ratio * ratio;
-        // x_i(k+1) = x_i(k) + a_i p_i(k);  p_i(k) = c P + sum_{l<=q} d[l] r(k0+l)
-        h.e += h.a * h.c;
-        // p_i(k+1) = zeta_i(k+1) r(k+1) + b_i p_i(k)
-        h.c *= bi;
-        // (fully unrolled with compile-time indices so h stays in registers)
-#pragma unroll
-        for (int l = 1; l <= kMaxBlockLen; ++l) {
-            if (l <= q) {
-                h.f[l] += h.a * h.d[l];
-                h.d[l] *= bi;
-            } else if (l == q + 1) {
-                h.d[l] = h.zeta_next;
-            }
-        }
-        h.zeta_prev = h.zeta;
-        h.zeta = h.zeta_next;
-        const double res = fabs(h.zeta) * sqrt(sums[j]);
-        if (res <= s.tolb) {
+        BlockCoef& bc = st->coef[j * kMaxShift + i];
+        bc.a[q] = alpha * ratio;
+        bc.b[q] = beta * ratio * ratio;
+        bc.z[q + 1] = zn;
+        h.nsteps = q + 1;
+        h.zeta_prev = zeta;
+        h.zeta = zn;
+        if (fabs(zn) * sqrt(rrn_s[j]) <= s.tolb) {
             h.active = 0;
             h.conv_iter = s.iters + 1;
         }
-        *hp = h;
     }
     __syncthreads();
     for (int p = tid; p < nsys * nsh; p += blockDim.x) {
@@ -211,12 +196,13 @@ __device__ inline void solver_finalize(int kind, void* vstate, const double* par
     if (tid < nsys) {
         SysScalars& s = st->sys[tid];
         if (!s.done) {
-            s.alpha_prev = s.alpha;
-            s.beta_prev = beta_s[tid];
-            s.rr = sums[tid];
+            const double rr = s.rr[cur];
+            s.alpha_prev = rr / pap_s[tid];
+            s.beta_prev = rrn_s[tid] / rr;
+            s.rr[nxt] = rrn_s[tid];
             s.iters += 1;
             s.blk_steps += 1;
-            if (!alive_s[tid] || s.iters >= st->maxiter || !isfinite(s.rr)) s.done = 1;
+            if (!alive_s[tid] || s.iters >= st->maxiter || !isfinite(rrn_s[tid])) s.done = 1;
         }
     }
     __syncthreads();
@@ -224,9 +210,25 @@ __device__ inline void solver_finalize(int kind, void* vstate, const double* par
         int all = 1;
         for (int j = 0; j < nsys; ++j) all &= st->sys[j].done;
         st->all_done = all;
-        st->blk_it = q_all + 1;
+        st->blk_it += 1;
         st->iter += 1;
     }
+}
+
+// Block coefficients of one shift from its recorded steps m = 0..q-1
+// (backward recursions, all terms positive):
+//   B_q = 1, B_m = b[m] B_{m+1};   G_q = 0, G_m = a[m] + b[m] G_{m+1}
+//   c = B_0, e = G_0, d[l] = z[l] B_l, f[l] = z[l] G_l.
+__device__ inline void flush_coefficients(BlockCoef& bc, int q) {
+    double B = 1.0, G = 0.0;
+    for (int m = q - 1; m >= 0; --m) {
+        bc.d[m + 1] = bc.z[m + 1] * B;
+        bc.f[m + 1] = bc.z[m + 1] * G;
+        G = bc.a[m] + bc.b[m] * G;
+        B = bc.b[m] * B;
+    }
+    bc.c = B;
+    bc.e = G;
 }
 
 #endif  // __HIPCC__

@@ -1,0 +1,89 @@
+// Launch-variant defaults and the autotuner of the hopping kernel (the
+// batching form of the solver: the launch shape of each (precision, rhs
+// count) is picked by timing, kept per gauge object).
+#include <cstdlib>
+
+#include "common.h"
+
+namespace rhmc {
+
+void default_hop_variants(int (&v)[2][4]) {
+    // index = order | nt << 2 | pipe << 3
+    // measured on MI355X at 48^3 x 12 (rhs classes 1, 2, 4, 8): z-tiles of 4
+    // planes with t inside the tile keep the neighbour vectors of a wave's
+    // sites in L2; the links, read once, are streamed (non-temporal)
+    const int fp64[4] = {7, 7, 6, 6};
+    const int fp32[4] = {10, 10, 14, 14};
+    for (int k = 0; k < 4; ++k) {
+        v[RHMC_PREC_FP64][k] = fp64[k];
+        v[RHMC_PREC_FP32][k] = fp32[k];
+    }
+    if (const char* e = std::getenv("RHMC_HOP_VARIANT")) {
+        const int f = std::atoi(e) & (kHopVariants - 1);
+        for (auto& row : v)
+            for (int& x : row) x = f;
+    }
+}
+
+rhmc_status tune_hop(rhmc_gauge* g, rhmc_prec prec, int nrhs, const void* in, void* out,
+                     hipStream_t s) {
+    const int cls = nr_class(nrhs);
+    const int nlinks = (int)(4 * g->lat.V);
+    const size_t n = (size_t)3 * g->lat.Vh;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    RHMC_HIP_TRY(hipEventCreate(&e0));
+    RHMC_HIP_TRY(hipEventCreate(&e1));
+    float best = 1e30f;
+    int best_v = g->hop_variant[prec][cls];
+    for (int v = 0; v < kHopVariants; ++v) {
+        hipError_t err = hipSuccess;
+        auto launch = [&]() {
+            if (prec == RHMC_PREC_FP64) {
+                DslashArgs<double2> a{};
+                a.g = g->lat.geom;
+                a.out_par = 1;
+                a.nrhs = nrhs;
+                a.variant = v;
+                for (int r = 0; r < nrhs; ++r) {
+                    a.in[r] = reinterpret_cast<const double2*>(in) + r * n;
+                    a.out[r] = reinterpret_cast<double2*>(out) + r * n;
+                }
+                err = launch_dslash64(g->u64, nlinks, a, kModeD, s);
+            } else {
+                DslashArgs<float2> a{};
+                a.g = g->lat.geom;
+                a.out_par = 1;
+                a.nrhs = nrhs;
+                a.variant = v;
+                for (int r = 0; r < nrhs; ++r) {
+                    a.in[r] = reinterpret_cast<const float2*>(in) + r * n;
+                    a.out[r] = reinterpret_cast<float2*>(out) + r * n;
+                }
+                err = launch_dslash32(g->u32, nlinks, a, kModeD, s);
+            }
+        };
+        for (int w = 0; w < 2 && err == hipSuccess; ++w) launch();
+        if (err == hipSuccess) err = hipEventRecord(e0, s);
+        for (int w = 0; w < 5 && err == hipSuccess; ++w) launch();
+        if (err == hipSuccess) err = hipEventRecord(e1, s);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        if (err != hipSuccess) {
+            hipEventDestroy(e0);
+            hipEventDestroy(e1);
+            RHMC_HIP_TRY(err);
+        }
+        if (ms < best) {
+            best = ms;
+            best_v = v;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    g->hop_variant[prec][cls] = best_v;
+    g->hop_tuned[prec][cls] = 1;
+    return RHMC_OK;
+}
+
+}  // namespace rhmc

@@ -36,8 +36,8 @@ RHMC_MODE_MIXED = 1
 EXPORTED = (
     "rhmc_solver_params_default", "rhmc_lattice_create", "rhmc_lattice_destroy",
     "rhmc_debug_neighbors", "rhmc_gauge_create", "rhmc_gauge_destroy", "rhmc_dslash_eo",
-    "rhmc_apply_mdagm", "rhmc_multishift_cg", "rhmc_rational_apply", "rhmc_status_string",
-    "rhmc_last_error",
+    "rhmc_apply_mdagm", "rhmc_multishift_cg", "rhmc_rational_apply", "rhmc_tune_dslash",
+    "rhmc_dslash_variant", "rhmc_status_string", "rhmc_last_error",
 )
 
 
@@ -90,6 +90,8 @@ def load():
                                      C.POINTER(rhmc_solver_params), C.POINTER(rhmc_solver_stats), vp]),
         "rhmc_rational_apply": (i32, [vp, f64, C.POINTER(rhmc_rational), i32, vp, vp,
                                       C.POINTER(rhmc_solver_params), C.POINTER(rhmc_solver_stats), vp]),
+        "rhmc_tune_dslash": (i32, [vp, i32, i32, vp, vp, vp]),
+        "rhmc_dslash_variant": (i32, [vp, i32, i32, C.POINTER(C.c_int32)]),
         "rhmc_status_string": (C.c_char_p, [i32]),
         "rhmc_last_error": (C.c_char_p, []),
     }
@@ -296,6 +298,21 @@ def rhmc_rational_apply(g: Gauge, m: float, alpha0: float, alpha, beta, b, y, pa
     if not (allow_not_converged and status == RHMC_ERR_NOT_CONVERGED):
         _check(status)
     return st.as_dict(nrhs, alpha.size, status)
+
+
+def rhmc_tune_dslash(g: Gauge, prec: int, nrhs: int, inp, out, stream=None):
+    """Time every launch variant of the hopping kernel and keep the fastest."""
+    Vh = g.lattice.Vh
+    dt = _vec_dtype(prec)
+    _check(load().rhmc_tune_dslash(g.handle, int(prec), int(nrhs), _ptr(inp, dt, (nrhs, 3, Vh), "in"),
+                                   _ptr(out, dt, (nrhs, 3, Vh), "out"), _stream(stream)))
+
+
+def rhmc_dslash_variant(g: Gauge, prec: int, nrhs: int) -> int:
+    """Launch variant of the hopping kernel in use for (prec, nrhs)."""
+    v = C.c_int32(-1)
+    _check(load().rhmc_dslash_variant(g.handle, int(prec), int(nrhs), C.byref(v)))
+    return v.value
 
 
 def rhmc_status_string(status: int) -> str:

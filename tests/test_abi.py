@@ -44,7 +44,7 @@ def test_status_strings(rh):
 
 def test_params_defaults(rh):
     p = rh.rhmc_solver_params_default()
-    assert p.tol == 1e-10 and p.reliable_every == 50 and p.block == 10 and p.use_graph == 1
+    assert p.tol == 1e-10 and p.reliable_every == 50 and p.block == 25 and p.use_graph == 1
 
 
 @pytest.mark.parametrize("L", [(4, 4, 3, 4), (1, 4, 4, 4), (0, 2, 2, 2)])
