@@ -313,6 +313,18 @@ rhmc_status rhmc_dslash_variant(const rhmc_gauge* g, rhmc_prec prec, int32_t nrh
     return RHMC_OK;
 }
 
+rhmc_status rhmc_set_dslash_variant(rhmc_gauge* g, rhmc_prec prec, int32_t nrhs,
+                                    int32_t variant) {
+    if (!g) return invalid("null argument");
+    if (nrhs < 1 || nrhs > 64) return invalid("nrhs must be in 1..64");
+    if (variant < 0 || variant >= kHopVariants) return invalid("variant must be in 0..63");
+    RHMC_TRY(check_prec(g, prec));
+    const int cls = nr_class(nrhs < kMaxSys ? nrhs : kMaxSys);
+    g->hop_variant[prec][cls] = variant;
+    g->hop_tuned[prec][cls] = 1;
+    return RHMC_OK;
+}
+
 const char* rhmc_status_string(rhmc_status s) {
     switch (s) {
         case RHMC_OK: return "ok";

@@ -95,74 +95,111 @@ __global__ __launch_bounds__(kBlock) void k_start(VecArgs<VT> a) {
 }
 
 // ------------------------------------------------------------------ r update
+// Vector kernels stride over the pairs of a system with kUnroll pairs per
+// thread per pass, all loads of a pass issued before its stores.
+constexpr int kUnroll = 4;
+
 // r(k+1) = r(k) - alpha A p;  sum ||r(k+1)||^2  -> beta, shift recurrences.
 template <typename VT>
 __global__ __launch_bounds__(kBlock) void k_rupdate(VecArgs<VT> a) {
     SolverState* st = reinterpret_cast<SolverState*>(a.state);
     if (st->all_done) return;
-    __shared__ double smem[16];
+    __shared__ double sums[kMaxSys];
     const int j = blockIdx.y;
     const bool live = !st->sys[j].done;
     double r2 = 0.0;
     if (live) {
         // alpha = rr / <p, A p>; every block adds the A-kernel partials itself,
         // in the same fixed order, so all blocks use the same alpha bits
-        const double pap = block_sum_partials(a.part2, j, a.nblk2, smem);
+        block_sum_rows(a.part2 + (size_t)j * a.nblk2, 1, a.nblk2, sums);
+        const double pap = sums[0];
+        if (blockIdx.x == 0 && threadIdx.x == 0) st->sys[j].pap = pap;
         const double alpha = st->sys[j].rr[a.q & 1] / pap;
-        for (size_t i = ((size_t)blockIdx.x * kBlock + threadIdx.x) * 2; i < a.n;
-             i += (size_t)gridDim.x * kBlock * 2) {
-            Pair<VT> r, ap;
-            r.load(a.x[j], i);
-            ap.load(a.y[j], i);
-            for (int k = 0; k < 2; ++k) {
-                const double nr = (double)r.re[k] - alpha * (double)ap.re[k];
-                const double ni = (double)r.im[k] - alpha * (double)ap.im[k];
-                r.re[k] = nr;
-                r.im[k] = ni;
-                r2 += (double)r.re[k] * r.re[k] + (double)r.im[k] * r.im[k];
+        const VT* __restrict__ x = a.x[j];
+        const VT* __restrict__ y = a.y[j];
+        VT* __restrict__ z = a.z[j];
+        const size_t stride = (size_t)gridDim.x * kBlock * 2;
+        for (size_t i0 = ((size_t)blockIdx.x * kBlock + threadIdx.x) * 2; i0 < a.n;
+             i0 += stride * kUnroll) {
+            Pair<VT> r[kUnroll], ap[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const size_t i = i0 + u * stride;
+                if (i < a.n) {
+                    r[u].load(x, i);
+                    ap[u].load(y, i);
+                }
             }
-            r.store(a.z[j], i);
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const size_t i = i0 + u * stride;
+                if (i < a.n) {
+                    for (int k = 0; k < 2; ++k) {
+                        const double nr = (double)r[u].re[k] - alpha * (double)ap[u].re[k];
+                        const double ni = (double)r[u].im[k] - alpha * (double)ap[u].im[k];
+                        r[u].re[k] = nr;
+                        r[u].im[k] = ni;
+                        r2 += (double)r[u].re[k] * r[u].re[k] + (double)r[u].im[k] * r[u].im[k];
+                    }
+                    r[u].store(z, i);
+                }
+            }
         }
     }
     reduce_store(r2, 0.0, j, -1, a.partial);
 }
 
 // ------------------------------------------------------------------ p update
-// p(k+1) = r(k+1) + beta p(k); block (0, 0) also runs the FP64 recurrences
-// of this step (iteration_update), which the other blocks do not read.
+// p(k+1) = r(k+1) + beta p(k).  Block x = 0 of system 0 has no vector work:
+// it runs the FP64 recurrences of this step (iteration_update), which no
+// other block of this kernel reads; blocks x = 0 of the other systems idle.
 template <typename VT>
 __global__ __launch_bounds__(kBlock) void k_pupdate(VecArgs<VT> a) {
     SolverState* st = reinterpret_cast<SolverState*>(a.state);
-    __shared__ double smem[16];
+    __shared__ double sums[kMaxSys];
     __shared__ int flags[2];
     const int j = blockIdx.y;
-    // Block (0, 0) writes done / all_done during this kernel: every other block
-    // reads them once, through shared memory, so its threads agree on the
-    // branches around the barriers below.
+    // The recurrence block writes done / all_done during this kernel: every
+    // other block reads them once, through shared memory, so its threads
+    // agree on the branches around the barriers below.
     if (threadIdx.x == 0) {
         flags[0] = st->all_done;
         flags[1] = st->sys[j].done;
     }
     __syncthreads();
     if (flags[0]) return;
-    if (!flags[1]) {
-        const double rrn = block_sum_partials(a.partial, j, a.nblk, smem);
-        const double beta = rrn / st->sys[j].rr[a.q & 1];
-        for (size_t i = ((size_t)blockIdx.x * kBlock + threadIdx.x) * 2; i < a.n;
-             i += (size_t)gridDim.x * kBlock * 2) {
-            Pair<VT> r, p;
-            r.load(a.x[j], i);
-            p.load(a.y[j], i);
-            for (int k = 0; k < 2; ++k) {
-                p.re[k] = (double)r.re[k] + beta * (double)p.re[k];
-                p.im[k] = (double)r.im[k] + beta * (double)p.im[k];
-            }
-            p.store(a.y[j], i);
-        }
+    if (blockIdx.x == 0) {
+        if (j == 0) iteration_update(st, a.partial, a.nblk, a.q);
+        return;
     }
-    if (blockIdx.x == 0 && blockIdx.y == 0) {
-        __syncthreads();
-        iteration_update(st, a.part2, a.nblk2, a.partial, a.nblk, a.q);
+    if (flags[1]) return;
+    block_sum_rows(a.partial + (size_t)j * a.nblk, 1, a.nblk, sums);
+    const double beta = sums[0] / st->sys[j].rr[a.q & 1];
+    const VT* __restrict__ x = a.x[j];
+    VT* __restrict__ y = a.y[j];
+    const size_t stride = (size_t)(gridDim.x - 1) * kBlock * 2;
+    for (size_t i0 = ((size_t)(blockIdx.x - 1) * kBlock + threadIdx.x) * 2; i0 < a.n;
+         i0 += stride * kUnroll) {
+        Pair<VT> r[kUnroll], p[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const size_t i = i0 + u * stride;
+            if (i < a.n) {
+                r[u].load(x, i);
+                p[u].load(y, i);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const size_t i = i0 + u * stride;
+            if (i < a.n) {
+                for (int k = 0; k < 2; ++k) {
+                    p[u].re[k] = (double)r[u].re[k] + beta * (double)p[u].re[k];
+                    p[u].im[k] = (double)r[u].im[k] + beta * (double)p[u].im[k];
+                }
+                p[u].store(y, i);
+            }
+        }
     }
 }
 
@@ -179,95 +216,75 @@ __global__ __launch_bounds__(kBlock) void k_flush_coef(void* state) {
     }
 }
 
-template <typename VT> struct Comp;
-template <> struct Comp<float2> { using type = float; };
-template <> struct Comp<double2> { using type = double; };
-
-// One thread per complex element of one system's vectors: the q+1 stored base
-// residuals stay in registers while every shift's X and P stream through
-// once.  Shifts go in chunks of U: their loads are issued together, then each
-// residual is widened to FP64 once and applied to all U shifts.
+// One thread per complex element of one system's vectors: the stored base
+// residuals r(k0+l), l <= q, are widened to FP64 once and stay in registers
+// while every shift's X and P stream through once.  The coefficients d_l, f_l
+// of a shift are zero beyond its last step (k_flush_coef), so the inner loop
+// is straight-line code over l = 1..Q with wave-uniform coefficients (scalar
+// registers).  Shifts go in pairs whose loads are issued together.
 template <typename VT, int Q>
-__global__ __launch_bounds__(kBlock) void k_flush(FlushArgs<VT> a) {
-    using RT = typename Comp<VT>::type;
-    constexpr int U = (sizeof(VT) == 16 && Q > 16) ? 2 : 4;
+__global__ __launch_bounds__(kBlock) void k_flush(FlushArgs<VT> a,
+                                                  const BlockCoef* __restrict__ coef) {
+    constexpr int U = 2;
     const SolverState* st = reinterpret_cast<const SolverState*>(a.state);
-    const BlockCoef* coef = reinterpret_cast<const BlockCoef*>(a.coef);
     const int j = blockIdx.y;
     const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
     const int q = st->sys[j].blk_steps;
     if (q == 0 || i >= a.n) return;
-    RT rre[Q + 1], rim[Q + 1];
+    double rre[Q + 1], rim[Q + 1];
 #pragma unroll
-    for (int l = 0; l <= Q; ++l)
+    for (int l = 0; l <= Q; ++l) {
+        rre[l] = rim[l] = 0.0;
         if (l <= q) {
             const VT v = a.ring[((size_t)l * a.nsys + j) * a.n + i];
-            rre[l] = v.x;
-            rim[l] = v.y;
+            rre[l] = (double)v.x;
+            rim[l] = (double)v.y;
         }
+    }
     const bool first = st->first_block != 0;
     const int nsh = a.nshift;
+    double2* __restrict__ X = a.X;
+    VT* __restrict__ P = a.P;
+#pragma unroll 1
     for (int s0 = 0; s0 < nsh; s0 += U) {
-        // keep the widening of the residuals inside this chunk (not hoisted
-        // out of the shift loop, which would hold them all as FP64)
-#pragma unroll
-        for (int l = 0; l <= Q; ++l) asm volatile("" : "+v"(rre[l]), "+v"(rim[l]));
         bool act[U];
-        int qi[U];
-        double xr[U], xi[U], pr[U], pi[U];
+        double2 xv[U];
+        double p0r[U], p0i[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int sh = s0 + u;
             act[u] = sh < nsh && st->sh[j][sh].block_active;
-            qi[u] = act[u] ? st->sh[j][sh].nsteps : 0;
-            xr[u] = xi[u] = pr[u] = pi[u] = 0.0;
-            if (act[u]) {
-                double p0r, p0i;
-                if (first) {
-                    p0r = (double)rre[0];
-                    p0i = (double)rim[0];
-                } else {
-                    const double2 x = a.X[j * a.x_sys + sh * a.x_shift + i];
-                    const VT p = a.P[((size_t)j * nsh + sh) * a.n + i];
-                    xr[u] = x.x;
-                    xi[u] = x.y;
-                    p0r = (double)p.x;
-                    p0i = (double)p.y;
-                }
-                const BlockCoef& bc = coef[j * kMaxShift + sh];
-                xr[u] += bc.e * p0r;
-                xi[u] += bc.e * p0i;
-                pr[u] = bc.c * p0r;
-                pi[u] = bc.c * p0i;
-            }
-        }
-#pragma unroll
-        for (int l = 1; l <= Q; ++l) {
-            if (l <= q) {
-                const double rr = (double)rre[l], ri = (double)rim[l];
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    if (l <= qi[u]) {
-                        const BlockCoef& bc = coef[j * kMaxShift + s0 + u];
-                        const double f = bc.f[l], d = bc.d[l];
-                        xr[u] += f * rr;
-                        xi[u] += f * ri;
-                        pr[u] += d * rr;
-                        pi[u] += d * ri;
-                    }
-                }
+            xv[u] = make_double2(0.0, 0.0);
+            p0r[u] = rre[0];
+            p0i[u] = rim[0];
+            if (act[u] && !first) {
+                xv[u] = X[j * a.x_sys + sh * a.x_shift + i];
+                const VT pv = P[((size_t)j * nsh + sh) * a.n + i];
+                p0r[u] = (double)pv.x;
+                p0i[u] = (double)pv.y;
             }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (!act[u]) continue;
             const int sh = s0 + u;
-            a.X[j * a.x_sys + sh * a.x_shift + i] = make_double2(xr[u], xi[u]);
+            const BlockCoef& bc = coef[j * kMaxShift + sh];
+            double xr = xv[u].x + bc.e * p0r[u], xi = xv[u].y + bc.e * p0i[u];
+            double pr = bc.c * p0r[u], pi = bc.c * p0i[u];
+#pragma unroll
+            for (int l = 1; l <= Q; ++l) {
+                const double f = bc.f[l], d = bc.d[l];
+                xr += f * rre[l];
+                xi += f * rim[l];
+                pr += d * rre[l];
+                pi += d * rim[l];
+            }
+            X[j * a.x_sys + sh * a.x_shift + i] = make_double2(xr, xi);
             if (st->sh[j][sh].active) {
                 VT pv;
-                pv.x = (RT)pr[u];
-                pv.y = (RT)pi[u];
-                a.P[((size_t)j * nsh + sh) * a.n + i] = pv;
+                pv.x = pr;
+                pv.y = pi;
+                P[((size_t)j * nsh + sh) * a.n + i] = pv;
             }
         }
     }
@@ -365,7 +382,9 @@ hipError_t launch_rupdate(const VecArgs<VT>& a, int nsys, hipStream_t s) {
 }
 template <typename VT>
 hipError_t launch_pupdate(const VecArgs<VT>& a, int nsys, hipStream_t s) {
-    hipLaunchKernelGGL(k_pupdate<VT>, red_grid(a.n, nsys), dim3(kBlock), 0, s, a);
+    // one extra block column: x = 0 runs the scalar recurrences
+    const dim3 g(vec_blocks(a.n) + 1, (unsigned)nsys);
+    hipLaunchKernelGGL(k_pupdate<VT>, g, dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 int vec_blocks(size_t n) {
@@ -383,15 +402,20 @@ hipError_t launch_finalize(int kind, void* state, const double* partial, int nbl
 template <typename VT>
 hipError_t launch_flush(const FlushArgs<VT>& a, int nsys, int qmax, hipStream_t s) {
     hipLaunchKernelGGL(k_flush_coef, dim3(1), dim3(kBlock), 0, s, a.state);
+    const BlockCoef* coef = reinterpret_cast<const BlockCoef*>(a.coef);
     const dim3 g((unsigned)((a.n + kBlock - 1) / kBlock), (unsigned)nsys), b(kBlock);
+    // register arrays sized by the block length (coefficients beyond a
+    // shift's last step are zero, so rounding up only adds idle terms)
     if (qmax <= 4)
-        hipLaunchKernelGGL((k_flush<VT, 4>), g, b, 0, s, a);
-    else if (qmax <= 8)
-        hipLaunchKernelGGL((k_flush<VT, 8>), g, b, 0, s, a);
+        hipLaunchKernelGGL((k_flush<VT, 4>), g, b, 0, s, a, coef);
     else if (qmax <= 16)
-        hipLaunchKernelGGL((k_flush<VT, 16>), g, b, 0, s, a);
+        hipLaunchKernelGGL((k_flush<VT, 16>), g, b, 0, s, a, coef);
+    else if (qmax <= 20)
+        hipLaunchKernelGGL((k_flush<VT, 20>), g, b, 0, s, a, coef);
+    else if (qmax <= 25)
+        hipLaunchKernelGGL((k_flush<VT, 25>), g, b, 0, s, a, coef);
     else
-        hipLaunchKernelGGL((k_flush<VT, 32>), g, b, 0, s, a);
+        hipLaunchKernelGGL((k_flush<VT, 32>), g, b, 0, s, a, coef);
     hipLaunchKernelGGL(k_flush_reset, dim3(1), dim3(kBlock), 0, s, a.state);
     return hipGetLastError();
 }

@@ -194,12 +194,18 @@ struct DslashArgs {
     int variant;                  // launch variant (HopVariant index)
 };
 
-// Launch variants of the hopping kernel, index = order | nt << 2 | pipe << 3:
+// Launch variants of the hopping kernel, index = order | nt << 2 | pipe << 3
+// | occ << 4:
 //   order  site processing order (process_site), 0..3
 //   nt     non-temporal (streaming) loads of the links, which are read once
 //          per application and need not displace neighbour vectors
 //   pipe   issue the loads of two hops as one batch instead of one
-constexpr int kHopVariants = 16;
+//   occ    cap on resident workgroups per CU (none, 5, 4, 3), set through an
+//          unused dynamic LDS allocation: fewer sites in flight per XCD keep
+//          the neighbour vectors they share inside that XCD's L2
+constexpr int kHopVariants = 64;
+// dynamic LDS bytes per workgroup for occ = 0..3 (160 KB of LDS per CU)
+constexpr int kOccLds[4] = {0, 32 * 1024, 40 * 1024, 53 * 1024};
 // right-hand-side classes of the kernel templates: 1, 2, 4, 8
 inline int nr_class(int nrhs) { return nrhs <= 1 ? 0 : nrhs <= 2 ? 1 : nrhs <= 4 ? 2 : 3; }
 // measured defaults on MI355X (48^3 x 12), [precision][rhs class]

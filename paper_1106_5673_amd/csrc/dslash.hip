@@ -305,16 +305,17 @@ __global__ __launch_bounds__(kBlock) void k_dslash(const LT* __restrict__ links,
 int dslash_grid(int Vh) { return (Vh + kBlock - 1) / kBlock; }
 
 template <typename VT, typename LT, int MODE, bool NT, bool PIPE>
-static hipError_t dispatch_nt(const LT* links, int nlinks, const DslashArgs<VT>& a, hipStream_t s) {
+static hipError_t dispatch_nt(const LT* links, int nlinks, const DslashArgs<VT>& a, size_t lds,
+                              hipStream_t s) {
     const dim3 grid(dslash_grid(a.g.Vh)), block(kBlock);
     if (a.nrhs <= 1)
-        hipLaunchKernelGGL((k_dslash<VT, LT, 1, MODE, NT, PIPE>), grid, block, 0, s, links, nlinks, a);
+        hipLaunchKernelGGL((k_dslash<VT, LT, 1, MODE, NT, PIPE>), grid, block, lds, s, links, nlinks, a);
     else if (a.nrhs <= 2)
-        hipLaunchKernelGGL((k_dslash<VT, LT, 2, MODE, NT, PIPE>), grid, block, 0, s, links, nlinks, a);
+        hipLaunchKernelGGL((k_dslash<VT, LT, 2, MODE, NT, PIPE>), grid, block, lds, s, links, nlinks, a);
     else if (a.nrhs <= 4)
-        hipLaunchKernelGGL((k_dslash<VT, LT, 4, MODE, NT, PIPE>), grid, block, 0, s, links, nlinks, a);
+        hipLaunchKernelGGL((k_dslash<VT, LT, 4, MODE, NT, PIPE>), grid, block, lds, s, links, nlinks, a);
     else
-        hipLaunchKernelGGL((k_dslash<VT, LT, 8, MODE, NT, PIPE>), grid, block, 0, s, links, nlinks, a);
+        hipLaunchKernelGGL((k_dslash<VT, LT, 8, MODE, NT, PIPE>), grid, block, lds, s, links, nlinks, a);
     return hipGetLastError();
 }
 
@@ -325,12 +326,13 @@ static hipError_t dispatch(const LT* links, int nlinks, const DslashArgs<VT>& a0
     if ((v & 3) == 2 && a.g.Lz % 4 != 0) v = (v & ~3) | 1;   // z-tiles of 4 need Lz % 4 == 0
     a.variant = v;
     const bool nt = (v >> 2) & 1, pipe = (v >> 3) & 1;
+    const size_t lds = (size_t)kOccLds[(v >> 4) & 3];
     if (pipe) {
-        if (nt) return dispatch_nt<VT, LT, MODE, true, true>(links, nlinks, a, s);
-        return dispatch_nt<VT, LT, MODE, false, true>(links, nlinks, a, s);
+        if (nt) return dispatch_nt<VT, LT, MODE, true, true>(links, nlinks, a, lds, s);
+        return dispatch_nt<VT, LT, MODE, false, true>(links, nlinks, a, lds, s);
     }
-    if (nt) return dispatch_nt<VT, LT, MODE, true, false>(links, nlinks, a, s);
-    return dispatch_nt<VT, LT, MODE, false, false>(links, nlinks, a, s);
+    if (nt) return dispatch_nt<VT, LT, MODE, true, false>(links, nlinks, a, lds, s);
+    return dispatch_nt<VT, LT, MODE, false, false>(links, nlinks, a, lds, s);
 }
 
 hipError_t launch_dslash64(const double2* u64, int nlinks, const DslashArgs<double2>& a, int mode,

@@ -14,6 +14,7 @@ namespace rhmc {
 
 struct SysScalars {
     double rr[2];       // <r, r>, double-buffered by step parity (see iteration_update)
+    double pap;         // <p, A p> of the current step (stored by the r-update kernel)
     double alpha_prev, beta_prev;
     double bnorm;       // ||b|| (FP64)
     double tolb;        // tol * ||b||
@@ -91,6 +92,38 @@ __device__ inline double block_sum_partials(const double* partial, int r, int nb
     return t;
 }
 
+// Sum rows 0..nrows-1 of partial[r*nblk + b] over b for all rows in one pass
+// (fixed order: the same bits in every block that calls it); out[r] in shared
+// memory holds the sums on return.  nrows <= kMaxSys.
+__device__ inline void block_sum_rows(const double* partial, int nrows, int nblk, double* out) {
+    __shared__ double wsum[kMaxSys][16];
+    double acc[kMaxSys];
+#pragma unroll
+    for (int r = 0; r < kMaxSys; ++r) acc[r] = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+#pragma unroll
+        for (int r = 0; r < kMaxSys; ++r)
+            if (r < nrows) acc[r] += partial[(size_t)r * nblk + b];
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int r = 0; r < kMaxSys; ++r) {
+        if (r < nrows) {
+            double v = acc[r];
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            if (lane == 0) wsum[r][wid] = v;
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nrows) {
+        const int nw = blockDim.x >> 6;
+        double t = 0.0;
+        for (int w = 0; w < nw; ++w) t += wsum[threadIdx.x][w];
+        out[threadIdx.x] = t;
+    }
+    __syncthreads();
+}
+
 // One-block finalize for the rare reductions (start, reliable update, norms).
 __device__ inline void solver_finalize(int kind, void* vstate, const double* partial, int nblk,
                                        int nrhs, double* out_sums) {
@@ -137,27 +170,22 @@ __device__ inline void solver_finalize(int kind, void* vstate, const double* par
     if (tid == 0) st->reliable_count += 1;
 }
 
-// The FP64 recurrences of one CG step q of the current block (block 0 of the
-// p-update kernel runs this while the other blocks update p):
+// The FP64 recurrences of one CG step q of the current block (a block of the
+// p-update kernel with no vector work runs this while the others update p):
 //   alpha = rr / <p, A p>, zeta_i', alpha_i, beta = rr' / rr, beta_i,
 //   the step's scalars of every shift, convergence and counters.
 // rr for step q is in rr[q & 1]; the new one goes to rr[(q + 1) & 1], which no
 // kernel of this step reads.
-__device__ inline void iteration_update(SolverState* st, const double* partA, int nblkA,
-                                        const double* partR, int nblkR, int q_step) {
-    __shared__ double smem[16];
+__device__ inline void iteration_update(SolverState* st, const double* partR, int nblkR,
+                                        int q_step) {
     __shared__ double pap_s[kMaxSys], rrn_s[kMaxSys];
     __shared__ int alive_s[kMaxSys];
     const int nsys = st->nsys, nsh = st->nshift;
     const int cur = q_step & 1, nxt = cur ^ 1;
-    for (int j = 0; j < nsys; ++j) {
-        const double a = block_sum_partials(partA, j, nblkA, smem);
-        const double b = block_sum_partials(partR, j, nblkR, smem);
-        if (threadIdx.x == 0) {
-            pap_s[j] = a;
-            rrn_s[j] = b;
-            alive_s[j] = 0;
-        }
+    block_sum_rows(partR, nsys, nblkR, rrn_s);
+    if ((int)threadIdx.x < nsys) {
+        pap_s[threadIdx.x] = st->sys[threadIdx.x].pap;
+        alive_s[threadIdx.x] = 0;
     }
     __syncthreads();
     const int tid = threadIdx.x;
@@ -216,10 +244,11 @@ __device__ inline void iteration_update(SolverState* st, const double* partA, in
 }
 
 // Block coefficients of one shift from its recorded steps m = 0..q-1
-// (backward recursions, all terms positive):
+// (backward recursions, all terms positive; d[l] = f[l] = 0 for l > q):
 //   B_q = 1, B_m = b[m] B_{m+1};   G_q = 0, G_m = a[m] + b[m] G_{m+1}
 //   c = B_0, e = G_0, d[l] = z[l] B_l, f[l] = z[l] G_l.
 __device__ inline void flush_coefficients(BlockCoef& bc, int q) {
+    for (int l = q + 1; l <= kMaxBlockLen; ++l) bc.d[l] = bc.f[l] = 0.0;
     double B = 1.0, G = 0.0;
     for (int m = q - 1; m >= 0; --m) {
         bc.d[m + 1] = bc.z[m + 1] * B;

@@ -11,9 +11,10 @@ void default_hop_variants(int (&v)[2][4]) {
     // index = order | nt << 2 | pipe << 3
     // measured on MI355X at 48^3 x 12 (rhs classes 1, 2, 4, 8): z-tiles of 4
     // planes with t inside the tile keep the neighbour vectors of a wave's
-    // sites in L2; the links, read once, are streamed (non-temporal)
-    const int fp64[4] = {7, 7, 6, 6};
-    const int fp32[4] = {10, 10, 14, 14};
+    // sites in L2; the links, read once, are streamed (non-temporal); a cap
+    // of 4-5 resident workgroups per CU helps the one-rhs kernels
+    const int fp64[4] = {38, 7, 38, 14};
+    const int fp32[4] = {18, 10, 14, 14};
     for (int k = 0; k < 4; ++k) {
         v[RHMC_PREC_FP64][k] = fp64[k];
         v[RHMC_PREC_FP32][k] = fp32[k];

@@ -37,7 +37,7 @@ EXPORTED = (
     "rhmc_solver_params_default", "rhmc_lattice_create", "rhmc_lattice_destroy",
     "rhmc_debug_neighbors", "rhmc_gauge_create", "rhmc_gauge_destroy", "rhmc_dslash_eo",
     "rhmc_apply_mdagm", "rhmc_multishift_cg", "rhmc_rational_apply", "rhmc_tune_dslash",
-    "rhmc_dslash_variant", "rhmc_status_string", "rhmc_last_error",
+    "rhmc_dslash_variant", "rhmc_set_dslash_variant", "rhmc_status_string", "rhmc_last_error",
 )
 
 
@@ -92,6 +92,7 @@ def load():
                                       C.POINTER(rhmc_solver_params), C.POINTER(rhmc_solver_stats), vp]),
         "rhmc_tune_dslash": (i32, [vp, i32, i32, vp, vp, vp]),
         "rhmc_dslash_variant": (i32, [vp, i32, i32, C.POINTER(C.c_int32)]),
+        "rhmc_set_dslash_variant": (i32, [vp, i32, i32, i32]),
         "rhmc_status_string": (C.c_char_p, [i32]),
         "rhmc_last_error": (C.c_char_p, []),
     }
@@ -313,6 +314,11 @@ def rhmc_dslash_variant(g: Gauge, prec: int, nrhs: int) -> int:
     v = C.c_int32(-1)
     _check(load().rhmc_dslash_variant(g.handle, int(prec), int(nrhs), C.byref(v)))
     return v.value
+
+
+def rhmc_set_dslash_variant(g: Gauge, prec: int, nrhs: int, variant: int):
+    """Pin the hopping kernel's launch variant for (prec, nrhs)."""
+    _check(load().rhmc_set_dslash_variant(g.handle, int(prec), int(nrhs), int(variant)))
 
 
 def rhmc_status_string(status: int) -> str:
