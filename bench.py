@@ -33,6 +33,7 @@ if ROOT not in sys.path:
 
 METRIC = ("Dslash GB/s (% HBM peak); multi-shift CG time to r≤10^-10, FP64 vs mixed+batched")
 HBM_PEAK_GBPS = 8000.0
+FLOPS_PER_SITE = 570   # 8 SU(3) x vector products (66) + 7 vector additions (6)
 WORKLOADS = {
     # name: (config index, description)
     "c5": (5, "48^3x12, eps 0.8, m 0.005, 4 rhs x 20-pole x^-1/4, MIXED batched, tol 1e-10"),
@@ -123,7 +124,9 @@ def main():
     ap.add_argument("--workload", default="c5", choices=sorted(WORKLOADS))
     ap.add_argument("--dslash-reps", type=int, default=200)
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison solve")
+    ap.add_argument("--fp64-runs", type=int, default=3, help="timed plain FP64 solves (median reported)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-pf", action="store_true", help="skip the pseudofermion heat bath + action")
     ap.add_argument("--only-dslash", action="store_true",
                     help="only the hopping-kernel timing and a copy of known size (counter runs)")
     args = ap.parse_args()
@@ -160,23 +163,27 @@ def main():
     log("gauge packed on the device")
 
     # ---------------------------------------------------------------- hopping kernel
-    def time_dslash(prec, k, reps):
+    def time_dslash(prec, k, reps, gauge=None, vh=None, warm=20):
+        """Median and min launch time of D_oe over `reps` launches, each
+        bracketed by its own pair of HIP events on the launching stream."""
+        gg = gauge if gauge is not None else g
+        n = vh if vh is not None else Vh
         dt = torch.complex64 if prec == "fp32" else torch.complex128
         pr = rhmc.RHMC_PREC_FP32 if prec == "fp32" else rhmc.RHMC_PREC_FP64
-        vin = bd[:k].to(dt).contiguous()
+        src = bd[:k] if vh is None else torch.randn((k, 3, n), dtype=torch.complex128, device=dev)
+        vin = src.to(dt).contiguous()
         vout = torch.empty_like(vin)
-        for _ in range(5):
-            rhmc.rhmc_dslash_eo(g, 1, pr, k, vin, vout)
+        for _ in range(warm):
+            rhmc.rhmc_dslash_eo(gg, 1, pr, k, vin, vout)
         s = torch.cuda.current_stream()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(s)
-        for _ in range(reps):
-            rhmc.rhmc_dslash_eo(g, 1, pr, k, vin, vout)
-        e1.record(s)
-        e1.synchronize()
-        avg_s = e0.elapsed_time(e1) / 1e3 / reps
-        byts = dslash_bytes_per_site(prec, k) * Vh
-        return avg_s, byts
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for e0, e1 in ev:
+            e0.record(s)
+            rhmc.rhmc_dslash_eo(gg, 1, pr, k, vin, vout)
+            e1.record(s)
+        ev[-1][1].synchronize()
+        ts = sorted(e0.elapsed_time(e1) / 1e3 for e0, e1 in ev)
+        return ts[len(ts) // 2], ts[0], dslash_bytes_per_site(prec, k) * n
 
     # the timed hopping launches use the library's measured default launch
     # variants (the solver below tunes its own), so that counter runs of
@@ -184,11 +191,13 @@ def main():
     var32 = rhmc.rhmc_dslash_variant(g, rhmc.RHMC_PREC_FP32, nrhs)
     var64 = rhmc.rhmc_dslash_variant(g, rhmc.RHMC_PREC_FP64, 1)
     log(f"hopping launch variants: fp32 x{nrhs} {var32}, fp64 x1 {var64}")
-    avg, byts = time_dslash("fp32", nrhs, args.dslash_reps)
-    avg64, byts64 = time_dslash("fp64", 1, args.dslash_reps // 2)
+    avg, avg_min, byts = time_dslash("fp32", nrhs, args.dslash_reps)
+    avg64, avg64_min, byts64 = time_dslash("fp64", 1, args.dslash_reps)
+    avg1, avg1_min, byts1 = time_dslash("fp32", 1, args.dslash_reps)
     achieved = byts / avg / 1e9
     log(f"hopping fp32-12 x{nrhs}: {avg * 1e6:.1f} us ({achieved:.0f} GB/s); "
-        f"fp64-18 x1: {avg64 * 1e6:.1f} us ({byts64 / avg64 / 1e9:.0f} GB/s)")
+        f"fp64-18 x1: {avg64 * 1e6:.1f} us ({byts64 / avg64 / 1e9:.0f} GB/s); "
+        f"fp32-12 x1: {avg1 * 1e6:.1f} us ({byts1 / avg1 / 1e9:.0f} GB/s)")
 
     if args.only_dslash:
         # a plain copy of known size for calibrating the HBM byte counters
@@ -221,16 +230,68 @@ def main():
 
     t_fp64 = None
     st64 = None
+    fp64_times = []
     if not args.no_fp64:
-        t1 = time.perf_counter()
-        st64 = step(prm_fp64)
+        step(prm_fp64)   # tunes the FP64 launch variants and builds the FP64 graphs (untimed)
+        for k in range(args.fp64_runs):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            st64 = step(prm_fp64)
+            torch.cuda.synchronize()
+            fp64_times.append(time.perf_counter() - t1)
+            log(f"fp64 solve {k}: {fp64_times[-1] * 1e3:.1f} ms, {st64['total_iterations']} iterations")
+        t_fp64 = sorted(fp64_times)[len(fp64_times) // 2]
+    mixed_times = sorted(s_['time_ms'] / 1e3 for s_ in stats)
+
+    # pseudofermion heat bath phi = r_h(A) R (x^{+1/8}) and action phi^dagger r(A) phi
+    pf = None
+    if not args.no_pf:
+        rh_ = rational_for(cfg, c["hb_power"])
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(3000 + cfg)
+        R = torch.complex(torch.randn((nrhs, 3, Vh), dtype=torch.float64, device=dev, generator=gen),
+                          torch.randn((nrhs, 3, Vh), dtype=torch.float64, device=dev, generator=gen))
+        R *= 0.5 ** 0.5
+        phi = torch.empty_like(R)
         torch.cuda.synchronize()
-        t_fp64 = time.perf_counter() - t1
-        log(f"fp64 solve: {t_fp64 * 1e3:.1f} ms, {st64['total_iterations']} iterations")
+        t1 = time.perf_counter()
+        rhmc.rhmc_rational_apply(g, m, rh_.alpha0, rh_.alpha, rh_.beta, R, phi, prm_mixed)
+        torch.cuda.synchronize()
+        t_hb = time.perf_counter() - t1
+        t1 = time.perf_counter()
+        S, st_pf = rhmc.rhmc_pf_action(g, m, rat.alpha0, rat.alpha, rat.beta, phi, prm_mixed)
+        torch.cuda.synchronize()
+        t_act = time.perf_counter() - t1
+        R2 = (R.abs() ** 2).sum(dim=(1, 2)).cpu().numpy()
+        pf = {"heatbath_s": round(t_hb, 4), "action_s": round(t_act, 4),
+              "max_abs_S_over_RR_minus_1": float(np.max(np.abs(S / R2 - 1))),
+              "note": "MIXED batched, x^{+1/8} heat bath then x^{-1/4} action; "
+                      "S = R^dagger R up to the minimax errors and the solver tolerance"}
+        log(f"pseudofermion heat bath {t_hb * 1e3:.0f} ms, action {t_act * 1e3:.0f} ms, "
+            f"max |S/RR - 1| = {pf['max_abs_S_over_RR_minus_1']:.2e}")
 
     tag = f"dslash_fp32_{nrhs}rhs_{'x'.join(str(v) for v in L)}"
     traffic = traffic_from_profile(tag, var32)
     g.close()
+
+    # 16^3x4 (cache resident: 9.4 MB of FP64 links): 1000 standalone FP64 D_oe
+    c2 = synth.CONFIGS[2]
+    lat2 = rhmc.rhmc_lattice_create(c2["L"], -1)
+    g2 = rhmc.rhmc_gauge_create(lat2, synth.gauge_field(c2["L"], c2["eps"], synth.fields.seed_gauge(2)))
+    t2, t2_min, byts2 = time_dslash("fp64", 1, 1000, gauge=g2, vh=lat2.Vh)
+    # the same 1000 launches back to back between one pair of events
+    v2 = torch.randn((1, 3, lat2.Vh), dtype=torch.complex128, device=dev)
+    o2 = torch.empty_like(v2)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(1000):
+        rhmc.rhmc_dslash_eo(g2, 1, rhmc.RHMC_PREC_FP64, 1, v2, o2)
+    e1.record()
+    e1.synchronize()
+    t2_stream = e0.elapsed_time(e1) / 1e3 / 1000
+    g2.close()
+    log(f"16^3x4 fp64 x1 (cache resident): {t2 * 1e6:.2f} us per timed launch, "
+        f"{t2_stream * 1e6:.2f} us back to back ({byts2 / t2_stream / 1e9:.0f} GB/s)")
 
     out = {
         "metric": METRIC,
@@ -261,21 +322,43 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBPS, 4),
             "traffic": traffic,
             "kernel": f"hopping FP32 12-real, {nrhs} rhs, launch variant {var32}, "
-                      f"{avg * 1e6:.2f} us per launch, {byts / 1e6:.1f} MB algorithmic per launch",
+                      f"{avg * 1e6:.2f} us per launch (median of {args.dslash_reps}; min "
+                      f"{avg_min * 1e6:.2f}), {byts / 1e6:.1f} MB algorithmic per launch",
+            "gflops": round(FLOPS_PER_SITE * Vh * nrhs / avg / 1e9, 1),
+        },
+        "dslash": {
+            "fp32_12_4rhs": {"us_median": round(avg * 1e6, 2), "us_min": round(avg_min * 1e6, 2),
+                             "GBps": round(achieved, 1),
+                             "gflops": round(FLOPS_PER_SITE * Vh * nrhs / avg / 1e9, 1)},
+            "fp32_12_1rhs": {"us_median": round(avg1 * 1e6, 2), "us_min": round(avg1_min * 1e6, 2),
+                             "GBps": round(byts1 / avg1 / 1e9, 1),
+                             "gflops": round(FLOPS_PER_SITE * Vh / avg1 / 1e9, 1)},
+            "fp64_18_1rhs": {"us_median": round(avg64 * 1e6, 2), "us_min": round(avg64_min * 1e6, 2),
+                             "GBps": round(byts64 / avg64 / 1e9, 1),
+                             "gflops": round(FLOPS_PER_SITE * Vh / avg64 / 1e9, 1)},
+            "fp64_18_1rhs_16x16x16x4_cache_resident": {
+                "us_median": round(t2 * 1e6, 3), "us_min": round(t2_min * 1e6, 3),
+                "us_back_to_back": round(t2_stream * 1e6, 3),
+                "GBps_back_to_back": round(byts2 / t2_stream / 1e9, 1), "launches": 1000,
+                "note": "32 workgroups per launch: launch- and cache-bound"},
         },
         "time_to_solution_s": {
             "mixed_batched": round(t_mixed, 4),
             "fp64": None if t_fp64 is None else round(t_fp64, 4),
+            "mixed_batched_runs": [round(v, 4) for v in mixed_times],
+            "fp64_runs": [round(v, 4) for v in sorted(fp64_times)],
+            "note": "mixed: mean wall time of the timed steps (library time per step listed); "
+                    "fp64: median of the listed runs, after one untimed run",
         },
         "iterations": {"mixed_batched": st["total_iterations"],
                        "fp64": None if st64 is None else st64["total_iterations"]},
         "max_true_residual": {"mixed_batched": st["max_true_residual"],
                               "fp64": None if st64 is None else st64["max_true_residual"]},
+        "pseudofermion": pf,
         "reliable_updates": st["reliable_updates"],
         "refine_rounds": st["refine_rounds"],
         "refine_iterations": int(st["refine_iterations"].sum()),
         "shifts_refined": int((st["refine_iterations"] > 0).sum()),
-        "dslash_fp64_1rhs_GBps": round(byts64 / avg64 / 1e9, 1),
     }
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")

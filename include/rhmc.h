@@ -167,6 +167,31 @@ rhmc_status rhmc_rational_apply(const rhmc_gauge* g, double m, const rhmc_ration
                                 const rhmc_solver_params* params, rhmc_solver_stats* stats,
                                 hipStream_t stream);
 
+/* Pseudofermion field of the Phi algorithm (Sec. 2.1) on even sites:
+ *   phi_e = (M^dagger R)_e = m R_e - D_eo R_o      (M = m + D, D^dagger = -D),
+ * whose covariance is A, i.e. phi is distributed as exp(-phi^dagger A^-1 phi)
+ * for complex Gaussian R (real and imaginary parts N(0, 1/2)).  FP64 links.
+ * r_even, r_odd, phi: device complex128 [nrhs][3][V/2] (R on the even and odd
+ * sites, in the eo order of rhmc_dslash_eo); phi must not overlap R.
+ * Asynchronous on `stream`.  For the rooted action below, the matching heat
+ * bath is phi = r_h(A) R with r_h ~ x^{+1/8}: rhmc_rational_apply with that
+ * approximation. */
+rhmc_status rhmc_pf_phi(const rhmc_gauge* g, double m, int32_t nrhs, const void* r_even,
+                        const void* r_odd, void* phi, hipStream_t stream);
+
+/* Pseudofermion action S[r] = Re <phi_r, r(A) phi_r> for each right-hand side:
+ * with r ~ x^{-1/4} this is the RHMC action of one pseudofermion carrying
+ * det A^{1/4} (Eq. system_r with two flavours and two pseudofermions).  r(A)
+ * phi is computed exactly as rhmc_rational_apply does (same params, same
+ * stats, same per-shift FP64 certification); the inner products are FP64
+ * with a fixed summation order.  phi: device complex128 [nrhs][3][V/2];
+ * S: host double[nrhs].  Blocks until S is on the host.  On NOT_CONVERGED, S
+ * holds the action of the last iterates. */
+rhmc_status rhmc_pf_action(const rhmc_gauge* g, double m, const rhmc_rational* rat,
+                           int32_t nrhs, const void* phi, double* S,
+                           const rhmc_solver_params* params, rhmc_solver_stats* stats,
+                           hipStream_t stream);
+
 /* Autotuner of the hopping kernel (the batching form's launch shapes): times
  * every launch variant (site processing order, non-temporal link loads, loads
  * of one or two hops per batch) of one application D_oe on the given vectors

@@ -294,6 +294,43 @@ rhmc_status rhmc_rational_apply(const rhmc_gauge* gc, double m, const rhmc_ratio
                     reinterpret_cast<double2*>(y), prm, stats, stream);
 }
 
+rhmc_status rhmc_pf_phi(const rhmc_gauge* gc, double m, int32_t nrhs, const void* r_even,
+                        const void* r_odd, void* phi, hipStream_t stream) {
+    rhmc_gauge* g = const_cast<rhmc_gauge*>(gc);
+    if (!g || !r_even || !r_odd || !phi) return invalid("null argument");
+    if (nrhs < 1 || nrhs > 64) return invalid("nrhs must be in 1..64");
+    if (phi == r_even || phi == r_odd) return invalid("phi must not overlap R");
+    if (!std::isfinite(m)) return invalid("m must be finite");
+    RHMC_TRY(check_prec(g, RHMC_PREC_FP64));
+    RHMC_TRY(use_device(g->device));
+    // A-mode of the hopping kernel: out = c * self - D_eo in, with c = m
+    return hop<double2>(g, 0, RHMC_PREC_FP64, nrhs, r_odd, phi, kModeA, r_even, m, stream);
+}
+
+rhmc_status rhmc_pf_action(const rhmc_gauge* gc, double m, const rhmc_rational* rat, int32_t nrhs,
+                           const void* phi, double* S, const rhmc_solver_params* params,
+                           rhmc_solver_stats* stats, hipStream_t stream) {
+    rhmc_gauge* g = const_cast<rhmc_gauge*>(gc);
+    if (!g || !rat || !phi || !S) return invalid("null argument");
+    if (nrhs < 1 || nrhs > 64) return invalid("nrhs must be in 1..64");
+    if (!std::isfinite(m) || !std::isfinite(rat->alpha0)) return invalid("non-finite coefficient");
+    if (rat->npole < 1 || !rat->alpha) return invalid("rational needs npole >= 1 and alpha");
+    for (int i = 0; i < rat->npole; ++i)
+        if (!std::isfinite(rat->alpha[i])) return invalid("non-finite coefficient");
+    RHMC_TRY(check_shifts(m, rat->npole, rat->beta));
+    rhmc_solver_params prm;
+    RHMC_TRY(check_params(params, g, &prm));
+    RHMC_TRY(use_device(g->device));
+    if (stats) {
+        stats->total_iterations = 0;
+        stats->reliable_updates = 0;
+        stats->refine_rounds = 0;
+        stats->time_ms = 0;
+        stats->max_true_residual = 0;
+    }
+    return pf_action(g, m, rat, nrhs, reinterpret_cast<const double2*>(phi), S, prm, stats, stream);
+}
+
 rhmc_status rhmc_tune_dslash(rhmc_gauge* g, rhmc_prec prec, int32_t nrhs, const void* in,
                              void* out, hipStream_t stream) {
     if (!g || !in || !out) return invalid("null argument");

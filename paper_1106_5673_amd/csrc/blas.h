@@ -65,4 +65,13 @@ hipError_t launch_finalize(int kind, void* state, const double* partial, int nbl
                            double* out_sums, hipStream_t s);
 hipError_t launch_add(const AddArgs& a, int nsys, hipStream_t s);
 
+// Re <a_j, b_j> per system, as block partials [nsys][vec_blocks(n)]
+struct DotArgs {
+    size_t n;
+    const double2* a[kMaxSys];
+    const double2* b[kMaxSys];
+    double* partial;
+};
+hipError_t launch_dot(const DotArgs& a, int nsys, hipStream_t s);
+
 }  // namespace rhmc

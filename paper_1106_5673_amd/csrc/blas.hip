@@ -344,6 +344,21 @@ __global__ __launch_bounds__(kBlock) void k_combine(CombineArgs a) {
     y.store(a.y[j], i);
 }
 
+// ------------------------------------------------------------------ dot
+// Re <a, b> (FP64) per system; block partials finished by k_finalize.
+__global__ __launch_bounds__(kBlock) void k_dot(DotArgs a) {
+    const int j = blockIdx.y;
+    double d = 0.0;
+    for (size_t i = ((size_t)blockIdx.x * kBlock + threadIdx.x) * 2; i < a.n;
+         i += (size_t)gridDim.x * kBlock * 2) {
+        Pair<double2> u, v;
+        u.load(a.a[j], i);
+        v.load(a.b[j], i);
+        for (int k = 0; k < 2; ++k) d += u.re[k] * v.re[k] + u.im[k] * v.im[k];
+    }
+    reduce_store(d, 0.0, j, -1, a.partial);
+}
+
 // ------------------------------------------------------------------ axpy
 // y += x (FP64), for folding a correction into a solution
 __global__ __launch_bounds__(kBlock) void k_add(AddArgs a) {
@@ -421,6 +436,10 @@ hipError_t launch_flush(const FlushArgs<VT>& a, int nsys, int qmax, hipStream_t 
 }
 hipError_t launch_combine(const CombineArgs& a, int nsys, hipStream_t s) {
     hipLaunchKernelGGL(k_combine, vec_grid(a.n, nsys), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+hipError_t launch_dot(const DotArgs& a, int nsys, hipStream_t s) {
+    hipLaunchKernelGGL(k_dot, red_grid(a.n, nsys), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 hipError_t launch_add(const AddArgs& a, int nsys, hipStream_t s) {

@@ -15,4 +15,9 @@ rhmc_status rational(rhmc_gauge* g, double m, const rhmc_rational* rat, int nrhs
                      const double2* b, double2* y, const rhmc_solver_params& prm,
                      rhmc_solver_stats* stats, hipStream_t s);
 
+// S[r] = Re <phi[r], r(A) phi[r]> (host array), r(A) as in rational()
+rhmc_status pf_action(rhmc_gauge* g, double m, const rhmc_rational* rat, int nrhs,
+                      const double2* phi, double* S, const rhmc_solver_params& prm,
+                      rhmc_solver_stats* stats, hipStream_t s);
+
 }  // namespace rhmc

@@ -72,6 +72,9 @@ struct Workspace {
     // rational apply: [nsys][npole] shifted solutions
     double2* xr = nullptr;
     size_t xr_cap = 0;
+    // pseudofermion action: r(A) phi, [nrhs]
+    double2* ya = nullptr;
+    size_t ya_cap = 0;
     CachedGraph graphs[4];
     int graph_next = 0;
 };
@@ -88,7 +91,7 @@ void workspace_destroy(Workspace* w) {
     if (!w) return;
     free_graphs(w);
     for (void* p : {w->ring, w->p, w->Ap, w->t, w->P, (void*)w->t64, (void*)w->rb, (void*)w->rx,
-                    (void*)w->xr, (void*)w->partial, (void*)w->sums,
+                    (void*)w->xr, (void*)w->ya, (void*)w->partial, (void*)w->sums,
                     (void*)w->st, (void*)w->coef})
         hipFree(p);
     hipHostFree(w->hst);
@@ -701,6 +704,35 @@ rhmc_status rational(rhmc_gauge* g, double m, const rhmc_rational* rat, int nrhs
     }
     RHMC_HIP_TRY(hipStreamSynchronize(s));
     return RHMC_OK;
+}
+
+rhmc_status pf_action(rhmc_gauge* g, double m, const rhmc_rational* rat, int nrhs,
+                      const double2* phi, double* S, const rhmc_solver_params& prm,
+                      rhmc_solver_stats* stats, hipStream_t s) {
+    const size_t n = (size_t)3 * g->lat.Vh;
+    const int K = std::max(1, std::min(kMaxBlockLen, prm.block));
+    RHMC_TRY(ensure_workspace(g, std::min(nrhs, kMaxSys), rat->npole, K));
+    Workspace* w = g->ws;
+    RHMC_TRY(grow(w, (void**)&w->ya, &w->ya_cap, w->vec_bytes * (size_t)nrhs));
+    const rhmc_status rs = rational(g, m, rat, nrhs, phi, w->ya, prm, stats, s);
+    if (rs != RHMC_OK && rs != RHMC_ERR_NOT_CONVERGED) return rs;
+    for (int r0 = 0; r0 < nrhs; r0 += kMaxSys) {
+        const int cnt = std::min(kMaxSys, nrhs - r0);
+        DotArgs d{};
+        d.n = n;
+        d.partial = w->partial;
+        for (int k = 0; k < cnt; ++k) {
+            d.a[k] = phi + (size_t)(r0 + k) * n;
+            d.b[k] = w->ya + (size_t)(r0 + k) * n;
+        }
+        RHMC_HIP_TRY(launch_dot(d, cnt, s));
+        RHMC_HIP_TRY(launch_finalize(kFinNorms, nullptr, w->partial, vec_blocks(n), cnt, w->sums, s));
+        RHMC_HIP_TRY(hipMemcpyAsync(w->sums_host, w->sums, sizeof(double) * cnt,
+                                    hipMemcpyDeviceToHost, s));
+        RHMC_HIP_TRY(hipStreamSynchronize(s));
+        for (int k = 0; k < cnt; ++k) S[r0 + k] = w->sums_host[k];
+    }
+    return rs;
 }
 
 }  // namespace rhmc

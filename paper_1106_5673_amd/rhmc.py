@@ -37,7 +37,8 @@ EXPORTED = (
     "rhmc_solver_params_default", "rhmc_lattice_create", "rhmc_lattice_destroy",
     "rhmc_debug_neighbors", "rhmc_gauge_create", "rhmc_gauge_destroy", "rhmc_dslash_eo",
     "rhmc_apply_mdagm", "rhmc_multishift_cg", "rhmc_rational_apply", "rhmc_tune_dslash",
-    "rhmc_dslash_variant", "rhmc_set_dslash_variant", "rhmc_status_string", "rhmc_last_error",
+    "rhmc_dslash_variant", "rhmc_set_dslash_variant", "rhmc_pf_phi", "rhmc_pf_action",
+    "rhmc_status_string", "rhmc_last_error",
 )
 
 
@@ -91,6 +92,9 @@ def load():
         "rhmc_rational_apply": (i32, [vp, f64, C.POINTER(rhmc_rational), i32, vp, vp,
                                       C.POINTER(rhmc_solver_params), C.POINTER(rhmc_solver_stats), vp]),
         "rhmc_tune_dslash": (i32, [vp, i32, i32, vp, vp, vp]),
+        "rhmc_pf_phi": (i32, [vp, f64, i32, vp, vp, vp, vp]),
+        "rhmc_pf_action": (i32, [vp, f64, C.POINTER(rhmc_rational), i32, vp, C.POINTER(C.c_double),
+                                 C.POINTER(rhmc_solver_params), C.POINTER(rhmc_solver_stats), vp]),
         "rhmc_dslash_variant": (i32, [vp, i32, i32, C.POINTER(C.c_int32)]),
         "rhmc_set_dslash_variant": (i32, [vp, i32, i32, i32]),
         "rhmc_status_string": (C.c_char_p, [i32]),
@@ -299,6 +303,43 @@ def rhmc_rational_apply(g: Gauge, m: float, alpha0: float, alpha, beta, b, y, pa
     if not (allow_not_converged and status == RHMC_ERR_NOT_CONVERGED):
         _check(status)
     return st.as_dict(nrhs, alpha.size, status)
+
+
+def rhmc_pf_phi(g: Gauge, m: float, r_even, r_odd, phi, stream=None):
+    """phi_e = m R_e - D_eo R_o (Phi-algorithm pseudofermion field, FP64)."""
+    import torch
+
+    nrhs = int(r_even.shape[0])
+    Vh = g.lattice.Vh
+    shape = (nrhs, 3, Vh)
+    _check(load().rhmc_pf_phi(g.handle, float(m), nrhs, _ptr(r_even, torch.complex128, shape, "r_even"),
+                              _ptr(r_odd, torch.complex128, shape, "r_odd"),
+                              _ptr(phi, torch.complex128, shape, "phi"), _stream(stream)))
+
+
+def rhmc_pf_action(g: Gauge, m: float, alpha0: float, alpha, beta, phi, params=None, stream=None,
+                   allow_not_converged=False):
+    """S[r] = Re <phi_r, r(A) phi_r>; returns (S as numpy float64[nrhs], statistics)."""
+    import torch
+
+    alpha = np.ascontiguousarray(alpha, dtype=np.float64)
+    beta = np.ascontiguousarray(beta, dtype=np.float64)
+    if alpha.shape != beta.shape or alpha.ndim != 1:
+        raise ValueError("alpha and beta must be 1-D of equal length")
+    nrhs = int(phi.shape[0])
+    Vh = g.lattice.Vh
+    pp = _ptr(phi, torch.complex128, (nrhs, 3, Vh), "phi")
+    rat = rhmc_rational(float(alpha0), alpha.size, alpha.ctypes.data_as(C.POINTER(C.c_double)),
+                        beta.ctypes.data_as(C.POINTER(C.c_double)))
+    S = np.zeros(nrhs, dtype=np.float64)
+    st = _Stats(nrhs, alpha.size)
+    prm = params if params is not None else rhmc_solver_params_default()
+    status = load().rhmc_pf_action(g.handle, float(m), C.byref(rat), nrhs, pp,
+                                   S.ctypes.data_as(C.POINTER(C.c_double)), C.byref(prm),
+                                   C.byref(st.c), _stream(stream))
+    if not (allow_not_converged and status == RHMC_ERR_NOT_CONVERGED):
+        _check(status)
+    return S, st.as_dict(nrhs, alpha.size, status)
 
 
 def rhmc_tune_dslash(g: Gauge, prec: int, nrhs: int, inp, out, stream=None):

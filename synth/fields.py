@@ -31,20 +31,21 @@ from __future__ import annotations
 import numpy as np
 
 # The five workloads: lattice, link roughness eps, quark mass m, number of
-# right-hand sides, number of poles, exponent p of x^p, solver tolerance and
-# arithmetic mode.  The rational interval is [m^2, 16 + m^2] for all of them
+# right-hand sides, number of poles, exponents p of x^p, solver tolerance and
+# arithmetic mode.  hb_power is the exponent of the pseudofermion heat bath
+# phi = A^{1/8} R that goes with the action phi^dagger A^{-1/4} phi.  The rational interval is [m^2, 16 + m^2] for all of them
 # (the spectrum of M^dagger M on even sites lies there because ||D|| <= 4).
 CONFIGS = {
     1: dict(L=(4, 4, 4, 4), eps=0.5, m=0.1, nrhs=1, npole=8, powers=(-0.25,),
-            tol=1e-12, mode="fp64"),
+            tol=1e-12, mode="fp64", hb_power=0.125),
     2: dict(L=(16, 16, 16, 4), eps=0.5, m=0.02, nrhs=1, npole=15,
-            powers=(-0.25, 0.25), tol=1e-10, mode="fp64"),
+            powers=(-0.25, 0.25), tol=1e-10, mode="fp64", hb_power=0.125),
     3: dict(L=(32, 32, 32, 8), eps=0.7, m=0.01, nrhs=1, npole=15,
-            powers=(-0.25,), tol=1e-10, mode="mixed"),
+            powers=(-0.25,), tol=1e-10, mode="mixed", hb_power=0.125),
     4: dict(L=(32, 32, 32, 8), eps=0.7, m=0.01, nrhs=8, npole=15,
-            powers=(-0.25,), tol=1e-10, mode="mixed"),
+            powers=(-0.25,), tol=1e-10, mode="mixed", hb_power=0.125),
     5: dict(L=(48, 48, 48, 12), eps=0.8, m=0.005, nrhs=4, npole=20,
-            powers=(-0.25,), tol=1e-10, mode="mixed"),
+            powers=(-0.25,), tol=1e-10, mode="mixed", hb_power=0.125),
 }
 
 

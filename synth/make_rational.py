@@ -13,7 +13,7 @@ def workload_rationals():
     seen = []
     for cfg, c in CONFIGS.items():
         lo = c["m"] ** 2
-        for p in c["powers"]:
+        for p in tuple(c["powers"]) + (c["hb_power"],):
             key = (p, c["npole"], lo, 16.0 + lo)
             if key not in seen:
                 seen.append(key)
