@@ -51,6 +51,8 @@ def dslash_bytes_per_site(prec: str, nrhs: int) -> int:
     read once, the input vector read once and the output written once."""
     if prec == "fp32":
         return 8 * 48 + nrhs * (24 + 24)
+    if prec == "fp64hl":   # hi/lo links: two FP32-12 planes per link
+        return 8 * 96 + nrhs * (48 + 48)
     return 8 * 144 + nrhs * (48 + 48)
 
 
@@ -274,6 +276,13 @@ def main():
     traffic = traffic_from_profile(tag, var32)
     g.close()
 
+    # FP64 operator from hi/lo links (Sec. 4.2 split), same lattice
+    ghl = rhmc.rhmc_gauge_create(lat, U, flags=rhmc.RHMC_LINKS_HILO_12)
+    thl, thl_min, _ = time_dslash("fp64", 1, args.dslash_reps, gauge=ghl)
+    ghl.close()
+    byts_hl = dslash_bytes_per_site("fp64hl", 1) * Vh
+    log(f"hopping fp64 hi/lo x1: {thl * 1e6:.1f} us ({byts_hl / thl / 1e9:.0f} GB/s)")
+
     # 16^3x4 (cache resident: 9.4 MB of FP64 links): 1000 standalone FP64 D_oe
     c2 = synth.CONFIGS[2]
     lat2 = rhmc.rhmc_lattice_create(c2["L"], -1)
@@ -336,6 +345,9 @@ def main():
             "fp64_18_1rhs": {"us_median": round(avg64 * 1e6, 2), "us_min": round(avg64_min * 1e6, 2),
                              "GBps": round(byts64 / avg64 / 1e9, 1),
                              "gflops": round(FLOPS_PER_SITE * Vh / avg64 / 1e9, 1)},
+            "fp64_hilo12_1rhs": {"us_median": round(thl * 1e6, 2), "us_min": round(thl_min * 1e6, 2),
+                                 "GBps": round(byts_hl / thl / 1e9, 1),
+                                 "gflops": round(FLOPS_PER_SITE * Vh / thl / 1e9, 1)},
             "fp64_18_1rhs_16x16x16x4_cache_resident": {
                 "us_median": round(t2 * 1e6, 3), "us_min": round(t2_min * 1e6, 3),
                 "us_back_to_back": round(t2_stream * 1e6, 3),

@@ -66,6 +66,14 @@ typedef enum { RHMC_PREC_FP64 = 0, RHMC_PREC_FP32 = 1 } rhmc_prec;
 /* Link storage requested from rhmc_gauge_create (bit flags). */
 #define RHMC_LINKS_FP64_18 1u /* 18 doubles per link: FP64 operator */
 #define RHMC_LINKS_FP32_12 2u /* first two rows in FP32, third rebuilt: FP32 operator */
+/* hi/lo split of Sec. 4.2: besides the FP32-12 copy (hi = RNE rounding of each
+ * FP64 entry of rows 1-2) store lo = RNE rounding of (entry - hi).  Without
+ * RHMC_LINKS_FP64_18 the FP64 operator (FP64 precision, reliable updates, true
+ * residuals) is then built from hi + lo in FP64 arithmetic with the third row
+ * rebuilt in FP64: about 48 significant bits per entry, relative operator error
+ * ~2^-47 instead of ~2^-53, from 2 x 48 B per link instead of 144 B.  Implies
+ * RHMC_LINKS_FP32_12. */
+#define RHMC_LINKS_HILO_12 4u
 
 typedef enum {
     RHMC_MODE_FP64 = 0,  /* every operator application and vector in FP64 */
@@ -126,7 +134,7 @@ rhmc_status rhmc_debug_neighbors(const rhmc_lattice* lat, int32_t parity, int32_
 
 /* Upload and pack one gauge field (Sec. 4.2 storage: structure of arrays so that
  * consecutive sites read consecutive memory).  links: host array described
- * above, 4*V*9 complex128.  flags: any of RHMC_LINKS_*; 0 means both.
+ * above, 4*V*9 complex128.  flags: any of RHMC_LINKS_*; 0 means FP64_18 | FP32_12.
  * The links are copied; the host array may be freed on return. */
 rhmc_status rhmc_gauge_create(const rhmc_lattice* lat, const double* links, uint32_t flags,
                               hipStream_t stream, rhmc_gauge** out);
@@ -134,8 +142,8 @@ void rhmc_gauge_destroy(rhmc_gauge* g);
 
 /* One application of the hopping term of Eq. (stag) between parities:
  * out_parity 0: out_even = D_eo in_odd;  1: out_odd = D_oe in_even.
- * prec FP64 uses the 18-real links and complex128 vectors, FP32 the 12-real
- * links and complex64 vectors.  in and out: device [nrhs][3][Vh], must not
+ * prec FP64 uses the 18-real links (or hi + lo when only those are stored) and
+ * complex128 vectors, FP32 the 12-real links and complex64 vectors.  in and out: device [nrhs][3][Vh], must not
  * overlap.  1 <= nrhs <= 64. */
 rhmc_status rhmc_dslash_eo(const rhmc_gauge* g, int32_t out_parity, rhmc_prec prec, int32_t nrhs,
                            const void* in, void* out, hipStream_t stream);

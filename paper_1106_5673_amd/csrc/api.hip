@@ -61,7 +61,7 @@ static rhmc_status hop(rhmc_gauge* g, int out_par, rhmc_prec prec, int nrhs, con
         }
         set_variant(a, g);
         if constexpr (std::is_same<VT, double2>::value) {
-            RHMC_HIP_TRY(launch_dslash64(g->u64, nlinks, a, mode, s));
+            RHMC_HIP_TRY(launch_fp64_op(g, a, mode, s));
         } else {
             RHMC_HIP_TRY(launch_dslash32(g->u32, nlinks, a, mode, s));
         }
@@ -71,7 +71,8 @@ static rhmc_status hop(rhmc_gauge* g, int out_par, rhmc_prec prec, int nrhs, con
 }
 
 static rhmc_status check_prec(const rhmc_gauge* g, rhmc_prec prec) {
-    if (prec == RHMC_PREC_FP64 && !g->u64) return invalid("gauge object has no FP64 links");
+    if (prec == RHMC_PREC_FP64 && !has_fp64_op(g))
+        return invalid("gauge object has no FP64 operator (FP64-18 or hi/lo links)");
     if (prec == RHMC_PREC_FP32 && !g->u32) return invalid("gauge object has no FP32-12 links");
     if (prec != RHMC_PREC_FP64 && prec != RHMC_PREC_FP32) return invalid("unknown precision");
     return RHMC_OK;
@@ -86,7 +87,8 @@ static rhmc_status check_params(const rhmc_solver_params* p, const rhmc_gauge* g
     if (out->mode != RHMC_MODE_FP64 && out->mode != RHMC_MODE_MIXED) return invalid("unknown mode");
     if (out->block < 1 || out->block > kMaxBlockLen) return invalid("block must be in 1..32");
     if (out->reliable_every < 1) return invalid("reliable_every must be >= 1");
-    if (!g->u64) return invalid("solvers need the FP64 links (true residuals are FP64)");
+    if (!has_fp64_op(g))
+        return invalid("solvers need an FP64 operator (FP64-18 or hi/lo links): true residuals are FP64");
     if (out->mode == RHMC_MODE_MIXED && !g->u32) return invalid("MIXED mode needs the FP32-12 links");
     return RHMC_OK;
 }
@@ -165,10 +167,13 @@ rhmc_status rhmc_gauge_create(const rhmc_lattice* lat, const double* links, uint
     if (!lat || !links || !out) return invalid("null argument");
     *out = nullptr;
     if (flags == 0) flags = RHMC_LINKS_FP64_18 | RHMC_LINKS_FP32_12;
-    if (flags & ~(RHMC_LINKS_FP64_18 | RHMC_LINKS_FP32_12)) return invalid("unknown link flags");
+    if (flags & ~(RHMC_LINKS_FP64_18 | RHMC_LINKS_FP32_12 | RHMC_LINKS_HILO_12))
+        return invalid("unknown link flags");
+    if (flags & RHMC_LINKS_HILO_12) flags |= RHMC_LINKS_FP32_12;   // hi is the FP32-12 copy
     rhmc_gauge* g = new (std::nothrow) rhmc_gauge();
     if (!g) return RHMC_ERR_OOM;
     g->lat = *lat;
+    g->hilo = (flags & RHMC_LINKS_HILO_12) ? 1 : 0;
     default_hop_variants(g->hop_variant);
     hipError_t e = hipGetDevice(&g->device);
     const size_t nlinks = (size_t)4 * lat->V;
@@ -176,7 +181,7 @@ rhmc_status rhmc_gauge_create(const rhmc_lattice* lat, const double* links, uint
     if (e == hipSuccess && (flags & RHMC_LINKS_FP64_18))
         e = hipMalloc(&g->u64, nlinks * 9 * sizeof(double2));
     if (e == hipSuccess && (flags & RHMC_LINKS_FP32_12))
-        e = hipMalloc(&g->u32, nlinks * 3 * sizeof(float4));
+        e = hipMalloc(&g->u32, nlinks * (g->hilo ? 6 : 3) * sizeof(float4));
     if (e == hipSuccess)
         e = hipMalloc(&g->partial, sizeof(double) * kMaxSys * (size_t)dslash_grid((int)lat->Vh));
     if (e == hipSuccess) e = hipMalloc(&canon, nlinks * 9 * sizeof(double2));

@@ -156,7 +156,9 @@ struct rhmc_gauge {
     rhmc_lattice lat;
     int device;
     double2* u64;  // FP64-18: [9][8*Vh] entry-major, link k = (2*mu + parity)*Vh + eo
-    float4* u32;   // FP32-12: [3][8*Vh], rows 1-2 as three float4 per link
+    float4* u32;   // FP32-12: [3][8*Vh], rows 1-2 as three float4 per link; with
+                   // hilo, [6][8*Vh]: planes 3-5 hold the FP32 remainders (lo)
+    int hilo;      // FP64 operator available from hi + lo (no u64 needed)
     void* tmp_odd;           // odd-parity temporary for rhmc_apply_mdagm
     size_t tmp_odd_bytes;
     double* partial;         // [kMaxSys][hopping grid] block sums of rhmc_apply_mdagm
@@ -215,11 +217,26 @@ void default_hop_variants(int (&v)[2][4]);
 int dslash_grid(int Vh);
 
 hipError_t launch_pack_links(const rhmc_gauge* g, const double2* canon, hipStream_t s);
+// Links of the FP64 operator rebuilt from the FP32 hi and lo planes.
+struct HiLoLink {
+    float4 v;
+};
+hipError_t launch_dslash64hl(const HiLoLink* u, int nlinks, const DslashArgs<double2>& a,
+                             int mode, hipStream_t s);
 hipError_t launch_dslash64(const double2* u64, int nlinks, const DslashArgs<double2>& a,
                            int mode, hipStream_t s);
 hipError_t launch_dslash32(const float4* u32, int nlinks, const DslashArgs<float2>& a,
                            int mode, hipStream_t s);
 hipError_t launch_neighbors(const Geom& g, int par, int* nb, int* sign, hipStream_t s);
+
+// The FP64 operator of a gauge object: FP64-18 links if stored, else hi + lo.
+inline hipError_t launch_fp64_op(const rhmc_gauge* g, const DslashArgs<double2>& a, int mode,
+                                 hipStream_t s) {
+    const int nlinks = (int)(4 * g->lat.V);
+    if (g->u64) return launch_dslash64(g->u64, nlinks, a, mode, s);
+    return launch_dslash64hl(reinterpret_cast<const HiLoLink*>(g->u32), nlinks, a, mode, s);
+}
+inline bool has_fp64_op(const rhmc_gauge* g) { return g->u64 || (g->u32 && g->hilo); }
 
 // Pick the launch variant of the gauge object for this precision and nrhs.
 template <typename VT>

@@ -13,7 +13,8 @@ namespace rhmc {
 // ------------------------------------------------------------------ pack
 __global__ __launch_bounds__(kBlock) void k_pack_links(const double2* __restrict__ canon, Geom g,
                                                         double2* __restrict__ u64,
-                                                        float4* __restrict__ u32, int nlinks) {
+                                                        float4* __restrict__ u32, int hilo,
+                                                        int nlinks) {
     const int id = blockIdx.x * blockDim.x + threadIdx.x;  // lex * 4 + mu
     const int V = 2 * g.Vh;
     if (id >= 4 * V) return;
@@ -39,6 +40,19 @@ __global__ __launch_bounds__(kBlock) void k_pack_links(const double2* __restrict
         u32[(size_t)0 * nlinks + k] = make_float4((float)e[0].x, (float)e[0].y, (float)e[1].x, (float)e[1].y);
         u32[(size_t)1 * nlinks + k] = make_float4((float)e[2].x, (float)e[2].y, (float)e[3].x, (float)e[3].y);
         u32[(size_t)2 * nlinks + k] = make_float4((float)e[4].x, (float)e[4].y, (float)e[5].x, (float)e[5].y);
+        if (hilo) {
+            // lo = the FP32 rounding of what hi leaves out: hi + lo carries
+            // about 48 significant bits of each FP64 entry (Sec. 4.2)
+            float lo[12];
+#pragma unroll
+            for (int i = 0; i < 6; ++i) {
+                lo[2 * i] = (float)(e[i].x - (double)(float)e[i].x);
+                lo[2 * i + 1] = (float)(e[i].y - (double)(float)e[i].y);
+            }
+            u32[(size_t)3 * nlinks + k] = make_float4(lo[0], lo[1], lo[2], lo[3]);
+            u32[(size_t)4 * nlinks + k] = make_float4(lo[4], lo[5], lo[6], lo[7]);
+            u32[(size_t)5 * nlinks + k] = make_float4(lo[8], lo[9], lo[10], lo[11]);
+        }
     }
 }
 
@@ -47,7 +61,7 @@ hipError_t launch_pack_links(const rhmc_gauge* g, const double2* canon, hipStrea
     const int nlinks = 4 * V;
     const int grid = (4 * V + kBlock - 1) / kBlock;
     hipLaunchKernelGGL(k_pack_links, dim3(grid), dim3(kBlock), 0, s, canon, g->lat.geom, g->u64,
-                       g->u32, nlinks);
+                       g->u32, g->hilo, nlinks);
     return hipGetLastError();
 }
 
@@ -131,6 +145,41 @@ __device__ __forceinline__ void load_link(const float4* __restrict__ u, int nlin
                        - (L.re[0][j2] * L.re[1][j1] - L.im[0][j2] * L.im[1][j1]);
         const float pi = L.re[0][j1] * L.im[1][j2] + L.im[0][j1] * L.re[1][j2]
                        - (L.re[0][j2] * L.im[1][j1] + L.im[0][j2] * L.re[1][j1]);
+        L.re[2][j] = pr;
+        L.im[2][j] = -pi;
+    }
+}
+
+// FP64 link from hi + lo planes: rows 1-2 = hi + lo in FP64, row 3 rebuilt in
+// FP64 as conj(row1 x row2).
+template <bool NT>
+__device__ __forceinline__ void load_link(const HiLoLink* __restrict__ uh, int nlinks, int k,
+                                          Link<double>& L) {
+    const float4* u = reinterpret_cast<const float4*>(uh);
+    float4 h[3], l[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        h[i] = ldg<NT>(u + (size_t)i * nlinks + k);
+        l[i] = ldg<NT>(u + (size_t)(3 + i) * nlinks + k);
+    }
+    const double w[12] = {(double)h[0].x + (double)l[0].x, (double)h[0].y + (double)l[0].y,
+                          (double)h[0].z + (double)l[0].z, (double)h[0].w + (double)l[0].w,
+                          (double)h[1].x + (double)l[1].x, (double)h[1].y + (double)l[1].y,
+                          (double)h[1].z + (double)l[1].z, (double)h[1].w + (double)l[1].w,
+                          (double)h[2].x + (double)l[2].x, (double)h[2].y + (double)l[2].y,
+                          (double)h[2].z + (double)l[2].z, (double)h[2].w + (double)l[2].w};
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+        L.re[e / 3][e % 3] = w[2 * e];
+        L.im[e / 3][e % 3] = w[2 * e + 1];
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const int j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+        const double pr = L.re[0][j1] * L.re[1][j2] - L.im[0][j1] * L.im[1][j2]
+                        - (L.re[0][j2] * L.re[1][j1] - L.im[0][j2] * L.im[1][j1]);
+        const double pi = L.re[0][j1] * L.im[1][j2] + L.im[0][j1] * L.re[1][j2]
+                        - (L.re[0][j2] * L.im[1][j1] + L.im[0][j2] * L.re[1][j1]);
         L.re[2][j] = pr;
         L.im[2][j] = -pi;
     }
@@ -341,6 +390,15 @@ hipError_t launch_dslash64(const double2* u64, int nlinks, const DslashArgs<doub
         case kModeD: return dispatch<double2, double2, kModeD>(u64, nlinks, a, s);
         case kModeA: return dispatch<double2, double2, kModeA>(u64, nlinks, a, s);
         default: return dispatch<double2, double2, kModeResid>(u64, nlinks, a, s);
+    }
+}
+
+hipError_t launch_dslash64hl(const HiLoLink* u, int nlinks, const DslashArgs<double2>& a,
+                             int mode, hipStream_t s) {
+    switch (mode) {
+        case kModeD: return dispatch<double2, HiLoLink, kModeD>(u, nlinks, a, s);
+        case kModeA: return dispatch<double2, HiLoLink, kModeA>(u, nlinks, a, s);
+        default: return dispatch<double2, HiLoLink, kModeResid>(u, nlinks, a, s);
     }
 }
 

@@ -223,8 +223,8 @@ static rhmc_status enqueue_block(const rhmc_gauge* g, Workspace* w, const Proble
             RHMC_HIP_TRY(launch_dslash32(g->u32, nlinks, d, kModeD, s));
             RHMC_HIP_TRY(launch_dslash32(g->u32, nlinks, a, kModeA, s));
         } else {
-            RHMC_HIP_TRY(launch_dslash64(g->u64, nlinks, d, kModeD, s));
-            RHMC_HIP_TRY(launch_dslash64(g->u64, nlinks, a, kModeA, s));
+            RHMC_HIP_TRY(launch_fp64_op(g, d, kModeD, s));
+            RHMC_HIP_TRY(launch_fp64_op(g, a, kModeA, s));
         }
         // r' = r - alpha A p (alpha from the A-kernel sums) and its block sums
         double* partR = w->partial + kMaxSys * w->part_stride;
@@ -291,8 +291,8 @@ static rhmc_status enqueue_block(const rhmc_gauge* g, Workspace* w, const Proble
             for (int j = 0; j < ns; ++j) r64.out[j] = reinterpret_cast<double2*>(vec<VT>(w->ring, n, j));
         set_variant(d64, g);
         set_variant(r64, g);
-        RHMC_HIP_TRY(launch_dslash64(g->u64, nlinks, d64, kModeD, s));
-        RHMC_HIP_TRY(launch_dslash64(g->u64, nlinks, r64, kModeResid, s));
+        RHMC_HIP_TRY(launch_fp64_op(g, d64, kModeD, s));
+        RHMC_HIP_TRY(launch_fp64_op(g, r64, kModeResid, s));
         RHMC_HIP_TRY(launch_finalize(kFinReliable, w->st, w->partial, dgrid, ns, nullptr, s));
     }
     return RHMC_OK;
@@ -464,8 +464,8 @@ static rhmc_status true_residuals(rhmc_gauge* g, const Problem& pb, const std::v
         }
         set_variant(d, g);
         set_variant(r, g);
-        RHMC_HIP_TRY(launch_dslash64(g->u64, nlinks, d, kModeD, s));
-        RHMC_HIP_TRY(launch_dslash64(g->u64, nlinks, r, kModeResid, s));
+        RHMC_HIP_TRY(launch_fp64_op(g, d, kModeD, s));
+        RHMC_HIP_TRY(launch_fp64_op(g, r, kModeResid, s));
         RHMC_HIP_TRY(launch_finalize(kFinNorms, nullptr, w->partial, dslash_grid(g->lat.geom.Vh), cnt,
                                      w->sums, s));
         RHMC_HIP_TRY(hipMemcpyAsync(w->sums_host, w->sums, sizeof(double) * cnt,
@@ -475,6 +475,13 @@ static rhmc_status true_residuals(rhmc_gauge* g, const Problem& pb, const std::v
     }
     return RHMC_OK;
 }
+
+// The shared Krylov solve stops each shift at kKrylovMargin * tol of its
+// recurrence residual, so that the FP64 true residual (which differs from it
+// by rounding) still meets tol without a refinement round; a refinement
+// solve aims at kRefineMargin * tol for the same reason.
+constexpr double kKrylovMargin = 0.9;
+constexpr double kRefineMargin = 0.8;
 
 static rhmc_status solve_impl(rhmc_gauge* g, Problem pb, const rhmc_solver_params& prm,
                               rhmc_solver_stats* stats, hipStream_t s) {
@@ -539,7 +546,7 @@ static rhmc_status solve_impl(rhmc_gauge* g, Problem pb, const rhmc_solver_param
                 rp.base[k] = 0;
                 rp.b[k] = w->rb + (size_t)k * w->n;
                 const double rn = std::sqrt(r2[k]);
-                rp.tol[k] = rn > 0 ? std::min(0.5, 0.5 * tol * bnorm[j] / rn) : 0.5;
+                rp.tol[k] = rn > 0 ? std::min(0.5, kRefineMargin * tol * bnorm[j] / rn) : 0.5;
             }
             int it2 = 0, rel2 = 0;
             if (pb.mode == RHMC_MODE_MIXED)
@@ -621,7 +628,7 @@ rhmc_status multishift(rhmc_gauge* g, double m, int nshift, const double* shifts
         for (int j = 0; j < cnt; ++j) {
             pb.sigma0[j] = smin;
             pb.base[j] = base;
-            pb.tol[j] = prm.tol;
+            pb.tol[j] = kKrylovMargin * prm.tol;
             pb.b[j] = b + (size_t)(r0 + j) * n;
             for (int i = 0; i < nshift; ++i) pb.off[j][i] = shifts[i] - smin;
         }

@@ -49,7 +49,7 @@ rhmc_status tune_hop(rhmc_gauge* g, rhmc_prec prec, int nrhs, const void* in, vo
                     a.in[r] = reinterpret_cast<const double2*>(in) + r * n;
                     a.out[r] = reinterpret_cast<double2*>(out) + r * n;
                 }
-                err = launch_dslash64(g->u64, nlinks, a, kModeD, s);
+                err = launch_fp64_op(g, a, kModeD, s);
             } else {
                 DslashArgs<float2> a{};
                 a.g = g->lat.geom;

@@ -227,3 +227,30 @@ def test_refinement_batch_larger_than_rhs_count(rh):
         for i, s in enumerate(shifts[:3]):
             assert solvers.true_residual(A, b2[r], x2[r, i], s) <= 1e-10
     g.close()
+
+
+def test_mixed_solve_with_hilo_links_only(rh):
+    """With only the hi/lo planes stored, reliable updates and the true
+    residual use the hi + lo FP64 operator; the oracle certifies every shift.
+    The hi + lo operator differs from the FP64 one by ~1e-13 ||x|| (relative
+    link error ~2^-47 through ||D|| <= 4), so the shifts keep ||x|| / ||b|| <=
+    1 / (m^2 + 0.01) ~ 92 and that difference far below tol."""
+    L = (8, 8, 8, 6)
+    m = 0.03
+    U = synth.gauge_field(L, 0.6, 5300)
+    lat = rh.rhmc_lattice_create(L, -1)
+    g = rh.rhmc_gauge_create(lat, U, flags=rh.RHMC_LINKS_HILO_12)
+    b = synth.source(L, 6300, 2)
+    shifts = np.array([0.01, 0.05, 0.3, 2.0])
+    import torch
+
+    x = torch.empty((2, shifts.size, 3, lat.Vh), dtype=torch.complex128, device="cuda:0")
+    st = rh.rhmc_multishift_cg(g, m, shifts, torch.from_numpy(b).to("cuda:0"), x,
+                               rh.solver_params(tol=1e-10, mode=rh.RHMC_MODE_MIXED))
+    assert st["reliable_updates"] > 0
+    A = lambda v: dirac.mdagm(U, m, v)  # noqa: E731
+    xs = x.cpu().numpy()
+    for r in range(2):
+        for i, s in enumerate(shifts):
+            assert solvers.true_residual(A, b[r], xs[r, i], s) <= 1e-10
+    g.close()
