@@ -51,7 +51,7 @@ def dslash_bytes_per_site(prec: str, nrhs: int) -> int:
     read once, the input vector read once and the output written once."""
     if prec == "fp32":
         return 8 * 48 + nrhs * (24 + 24)
-    if prec == "fp64hl":   # hi/lo links: two FP32-12 planes per link
+    if prec in ("fp64hl", "fp64c"):   # hi/lo FP32-12 planes or FP64-12 links: 96 B per link
         return 8 * 96 + nrhs * (48 + 48)
     return 8 * 144 + nrhs * (48 + 48)
 
@@ -127,6 +127,8 @@ def main():
     ap.add_argument("--dslash-reps", type=int, default=200)
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison solve")
     ap.add_argument("--fp64-runs", type=int, default=3, help="timed plain FP64 solves (median reported)")
+    ap.add_argument("--md-tol", type=float, default=1e-7,
+                    help="also time MIXED and FP64 at this looser tolerance (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-pf", action="store_true", help="skip the pseudofermion heat bath + action")
     ap.add_argument("--only-dslash", action="store_true",
@@ -194,11 +196,12 @@ def main():
     var64 = rhmc.rhmc_dslash_variant(g, rhmc.RHMC_PREC_FP64, 1)
     log(f"hopping launch variants: fp32 x{nrhs} {var32}, fp64 x1 {var64}")
     avg, avg_min, byts = time_dslash("fp32", nrhs, args.dslash_reps)
-    avg64, avg64_min, byts64 = time_dslash("fp64", 1, args.dslash_reps)
+    avg64, avg64_min, _ = time_dslash("fp64", 1, args.dslash_reps)
+    byts64 = dslash_bytes_per_site("fp64c", 1) * Vh   # default storage: FP64-12 links
     avg1, avg1_min, byts1 = time_dslash("fp32", 1, args.dslash_reps)
     achieved = byts / avg / 1e9
     log(f"hopping fp32-12 x{nrhs}: {avg * 1e6:.1f} us ({achieved:.0f} GB/s); "
-        f"fp64-18 x1: {avg64 * 1e6:.1f} us ({byts64 / avg64 / 1e9:.0f} GB/s); "
+        f"fp64-12 x1: {avg64 * 1e6:.1f} us ({byts64 / avg64 / 1e9:.0f} GB/s); "
         f"fp32-12 x1: {avg1 * 1e6:.1f} us ({byts1 / avg1 / 1e9:.0f} GB/s)")
 
     if args.only_dslash:
@@ -245,6 +248,22 @@ def main():
         t_fp64 = sorted(fp64_times)[len(fp64_times) // 2]
     mixed_times = sorted(s_['time_ms'] / 1e3 for s_ in stats)
 
+    # the same rational apply at a molecular-dynamics tolerance, where the
+    # FP32 operator's shifted-residual gap needs little or no refinement
+    md = None
+    if args.md_tol > 0:
+        md = {"tol": args.md_tol}
+        for name, mode in (("mixed_batched", rhmc.RHMC_MODE_MIXED), ("fp64", rhmc.RHMC_MODE_FP64)):
+            prm = rhmc.solver_params(tol=args.md_tol, mode=mode, tune=1)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            st_md = step(prm)
+            torch.cuda.synchronize()
+            md[name] = round(time.perf_counter() - t1, 4)
+            md[name + "_iterations"] = st_md["total_iterations"]
+            md[name + "_refine_iterations"] = int(st_md["refine_iterations"].sum())
+        log(f"tol {args.md_tol:g}: mixed {md['mixed_batched'] * 1e3:.0f} ms, fp64 {md['fp64'] * 1e3:.0f} ms")
+
     # pseudofermion heat bath phi = r_h(A) R (x^{+1/8}) and action phi^dagger r(A) phi
     pf = None
     if not args.no_pf:
@@ -276,17 +295,22 @@ def main():
     traffic = traffic_from_profile(tag, var32)
     g.close()
 
-    # FP64 operator from hi/lo links (Sec. 4.2 split), same lattice
+    # FP64 operator from hi/lo links (Sec. 4.2 split) and from FP64-18 links, same lattice
     ghl = rhmc.rhmc_gauge_create(lat, U, flags=rhmc.RHMC_LINKS_HILO_12)
     thl, thl_min, _ = time_dslash("fp64", 1, args.dslash_reps, gauge=ghl)
     ghl.close()
     byts_hl = dslash_bytes_per_site("fp64hl", 1) * Vh
-    log(f"hopping fp64 hi/lo x1: {thl * 1e6:.1f} us ({byts_hl / thl / 1e9:.0f} GB/s)")
+    g18 = rhmc.rhmc_gauge_create(lat, U, flags=rhmc.RHMC_LINKS_FP64_18)
+    t18, t18_min, byts18 = time_dslash("fp64", 1, args.dslash_reps, gauge=g18)
+    g18.close()
+    log(f"hopping fp64 hi/lo x1: {thl * 1e6:.1f} us ({byts_hl / thl / 1e9:.0f} GB/s); "
+        f"fp64-18 x1: {t18 * 1e6:.1f} us ({byts18 / t18 / 1e9:.0f} GB/s)")
 
     # 16^3x4 (cache resident: 9.4 MB of FP64 links): 1000 standalone FP64 D_oe
     c2 = synth.CONFIGS[2]
     lat2 = rhmc.rhmc_lattice_create(c2["L"], -1)
-    g2 = rhmc.rhmc_gauge_create(lat2, synth.gauge_field(c2["L"], c2["eps"], synth.fields.seed_gauge(2)))
+    g2 = rhmc.rhmc_gauge_create(lat2, synth.gauge_field(c2["L"], c2["eps"], synth.fields.seed_gauge(2)),
+                                flags=rhmc.RHMC_LINKS_FP64_18)
     t2, t2_min, byts2 = time_dslash("fp64", 1, 1000, gauge=g2, vh=lat2.Vh)
     # the same 1000 launches back to back between one pair of events
     v2 = torch.randn((1, 3, lat2.Vh), dtype=torch.complex128, device=dev)
@@ -342,9 +366,12 @@ def main():
             "fp32_12_1rhs": {"us_median": round(avg1 * 1e6, 2), "us_min": round(avg1_min * 1e6, 2),
                              "GBps": round(byts1 / avg1 / 1e9, 1),
                              "gflops": round(FLOPS_PER_SITE * Vh / avg1 / 1e9, 1)},
-            "fp64_18_1rhs": {"us_median": round(avg64 * 1e6, 2), "us_min": round(avg64_min * 1e6, 2),
+            "fp64_12_1rhs": {"us_median": round(avg64 * 1e6, 2), "us_min": round(avg64_min * 1e6, 2),
                              "GBps": round(byts64 / avg64 / 1e9, 1),
                              "gflops": round(FLOPS_PER_SITE * Vh / avg64 / 1e9, 1)},
+            "fp64_18_1rhs": {"us_median": round(t18 * 1e6, 2), "us_min": round(t18_min * 1e6, 2),
+                             "GBps": round(byts18 / t18 / 1e9, 1),
+                             "gflops": round(FLOPS_PER_SITE * Vh / t18 / 1e9, 1)},
             "fp64_hilo12_1rhs": {"us_median": round(thl * 1e6, 2), "us_min": round(thl_min * 1e6, 2),
                                  "GBps": round(byts_hl / thl / 1e9, 1),
                                  "gflops": round(FLOPS_PER_SITE * Vh / thl / 1e9, 1)},
@@ -362,6 +389,7 @@ def main():
             "note": "mixed: mean wall time of the timed steps (library time per step listed); "
                     "fp64: median of the listed runs, after one untimed run",
         },
+        "time_to_solution_md_tol_s": md,
         "iterations": {"mixed_batched": st["total_iterations"],
                        "fp64": None if st64 is None else st64["total_iterations"]},
         "max_true_residual": {"mixed_batched": st["max_true_residual"],

@@ -74,6 +74,10 @@ typedef enum { RHMC_PREC_FP64 = 0, RHMC_PREC_FP32 = 1 } rhmc_prec;
  * ~2^-47 instead of ~2^-53, from 2 x 48 B per link instead of 144 B.  Implies
  * RHMC_LINKS_FP32_12. */
 #define RHMC_LINKS_HILO_12 4u
+/* FP64 rows 1-2 (12 doubles, 96 B per link), third row rebuilt in FP64 as
+ * conj(row1 x row2): the storage of Sec. 4.2 in double precision.  The FP64
+ * operator of choice when present (needs the links SU(3) to 1e-12). */
+#define RHMC_LINKS_FP64_12 8u
 
 typedef enum {
     RHMC_MODE_FP64 = 0,  /* every operator application and vector in FP64 */
@@ -134,7 +138,11 @@ rhmc_status rhmc_debug_neighbors(const rhmc_lattice* lat, int32_t parity, int32_
 
 /* Upload and pack one gauge field (Sec. 4.2 storage: structure of arrays so that
  * consecutive sites read consecutive memory).  links: host array described
- * above, 4*V*9 complex128.  flags: any of RHMC_LINKS_*; 0 means FP64_18 | FP32_12.
+ * above, 4*V*9 complex128.  flags: any of RHMC_LINKS_*; 0 means FP32_12 plus
+ * FP64_12, or plus FP64_18 if row 3 of some link differs from conj(row1 x row2)
+ * by more than 1e-12.  The FP64 operator uses FP64_12 if stored, else FP64_18,
+ * else hi + lo.  12-real storage needs SU(3) links: INVALID_ARG if row 3 is
+ * off by more than 1e-12 (FP64_12) or 1e-6 (FP32_12), or links hold NaN/Inf.
  * The links are copied; the host array may be freed on return. */
 rhmc_status rhmc_gauge_create(const rhmc_lattice* lat, const double* links, uint32_t flags,
                               hipStream_t stream, rhmc_gauge** out);
@@ -142,8 +150,9 @@ void rhmc_gauge_destroy(rhmc_gauge* g);
 
 /* One application of the hopping term of Eq. (stag) between parities:
  * out_parity 0: out_even = D_eo in_odd;  1: out_odd = D_oe in_even.
- * prec FP64 uses the 18-real links (or hi + lo when only those are stored) and
- * complex128 vectors, FP32 the 12-real links and complex64 vectors.  in and out: device [nrhs][3][Vh], must not
+ * prec FP64 uses the FP64 operator (FP64-12, FP64-18 or hi + lo links, see
+ * rhmc_gauge_create) and complex128 vectors, FP32 the 12-real FP32 links and
+ * complex64 vectors.  in and out: device [nrhs][3][Vh], must not
  * overlap.  1 <= nrhs <= 64. */
 rhmc_status rhmc_dslash_eo(const rhmc_gauge* g, int32_t out_parity, rhmc_prec prec, int32_t nrhs,
                            const void* in, void* out, hipStream_t stream);

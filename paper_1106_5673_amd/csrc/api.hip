@@ -162,14 +162,47 @@ rhmc_status rhmc_debug_neighbors(const rhmc_lattice* lat, int32_t parity, int32_
     return RHMC_OK;
 }
 
+// Largest |U_3j - conj(row1 x row2)_j| over all links (host array, complex128
+// [..][3][3]): how far row 3 is from what 12-real storage rebuilds.
+static double su3_defect(const double* links, size_t nlinks) {
+    double worst = 0.0;
+    for (size_t k = 0; k < nlinks; ++k) {
+        const double* u = links + k * 18;
+        for (int j = 0; j < 3; ++j) {
+            const int j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+            const double a1r = u[2 * j1], a1i = u[2 * j1 + 1], a2r = u[2 * j2], a2i = u[2 * j2 + 1];
+            const double b1r = u[6 + 2 * j1], b1i = u[6 + 2 * j1 + 1];
+            const double b2r = u[6 + 2 * j2], b2i = u[6 + 2 * j2 + 1];
+            const double pr = a1r * b2r - a1i * b2i - (a2r * b1r - a2i * b1i);
+            const double pi = a1r * b2i + a1i * b2r - (a2r * b1i + a2i * b1r);
+            const double dr = u[12 + 2 * j] - pr, di = u[12 + 2 * j + 1] + pi;
+            const double d = std::sqrt(dr * dr + di * di);
+            if (!(d <= worst)) worst = d;   // also propagates NaN
+        }
+    }
+    return worst;
+}
+constexpr double kFp64x12Defect = 1e-12;   // rebuilt row within 1e-12 of the stored one
+constexpr double kFp32x12Defect = 1e-6;
+
 rhmc_status rhmc_gauge_create(const rhmc_lattice* lat, const double* links, uint32_t flags,
                               hipStream_t stream, rhmc_gauge** out) {
     if (!lat || !links || !out) return invalid("null argument");
     *out = nullptr;
-    if (flags == 0) flags = RHMC_LINKS_FP64_18 | RHMC_LINKS_FP32_12;
-    if (flags & ~(RHMC_LINKS_FP64_18 | RHMC_LINKS_FP32_12 | RHMC_LINKS_HILO_12))
-        return invalid("unknown link flags");
+    const uint32_t known = RHMC_LINKS_FP64_18 | RHMC_LINKS_FP32_12 | RHMC_LINKS_HILO_12 |
+                           RHMC_LINKS_FP64_12;
+    if (flags & ~known) return invalid("unknown link flags");
+    // 12-real storage rebuilds row 3 as conj(row1 x row2), which needs det U = 1
+    const double defect = su3_defect(links, (size_t)4 * lat->V);
+    if (!std::isfinite(defect)) return invalid("links hold NaN or Inf");
+    if (flags == 0) {
+        flags = RHMC_LINKS_FP32_12 | (defect <= kFp64x12Defect ? RHMC_LINKS_FP64_12 : RHMC_LINKS_FP64_18);
+    }
+    if ((flags & RHMC_LINKS_FP64_12) && defect > kFp64x12Defect)
+        return invalid("FP64-12 links need SU(3) input to FP64 accuracy (row 3 = conj(row1 x row2))");
     if (flags & RHMC_LINKS_HILO_12) flags |= RHMC_LINKS_FP32_12;   // hi is the FP32-12 copy
+    if ((flags & RHMC_LINKS_FP32_12) && defect > kFp32x12Defect)
+        return invalid("12-real FP32 links need SU(3) input (row 3 = conj(row1 x row2))");
     rhmc_gauge* g = new (std::nothrow) rhmc_gauge();
     if (!g) return RHMC_ERR_OOM;
     g->lat = *lat;
@@ -180,6 +213,8 @@ rhmc_status rhmc_gauge_create(const rhmc_lattice* lat, const double* links, uint
     double2* canon = nullptr;
     if (e == hipSuccess && (flags & RHMC_LINKS_FP64_18))
         e = hipMalloc(&g->u64, nlinks * 9 * sizeof(double2));
+    if (e == hipSuccess && (flags & RHMC_LINKS_FP64_12))
+        e = hipMalloc(&g->u64c, nlinks * 6 * sizeof(double2));
     if (e == hipSuccess && (flags & RHMC_LINKS_FP32_12))
         e = hipMalloc(&g->u32, nlinks * (g->hilo ? 6 : 3) * sizeof(float4));
     if (e == hipSuccess)
@@ -204,6 +239,7 @@ void rhmc_gauge_destroy(rhmc_gauge* g) {
     hipSetDevice(g->device);
     workspace_destroy(g->ws);
     hipFree(g->u64);
+    hipFree(g->u64c);
     hipFree(g->u32);
     hipFree(g->tmp_odd);
     hipFree(g->partial);

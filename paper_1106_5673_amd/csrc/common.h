@@ -155,6 +155,7 @@ void workspace_destroy(Workspace* w);
 struct rhmc_gauge {
     rhmc_lattice lat;
     int device;
+    double2* u64c; // FP64-12: [6][8*Vh], rows 1-2; row 3 rebuilt in FP64
     double2* u64;  // FP64-18: [9][8*Vh] entry-major, link k = (2*mu + parity)*Vh + eo
     float4* u32;   // FP32-12: [3][8*Vh], rows 1-2 as three float4 per link; with
                    // hilo, [6][8*Vh]: planes 3-5 hold the FP32 remainders (lo)
@@ -221,6 +222,12 @@ hipError_t launch_pack_links(const rhmc_gauge* g, const double2* canon, hipStrea
 struct HiLoLink {
     float4 v;
 };
+// FP64 links with the first two rows stored (12 reals).
+struct Fp64x12Link {
+    double2 v;
+};
+hipError_t launch_dslash64c(const Fp64x12Link* u, int nlinks, const DslashArgs<double2>& a,
+                            int mode, hipStream_t s);
 hipError_t launch_dslash64hl(const HiLoLink* u, int nlinks, const DslashArgs<double2>& a,
                              int mode, hipStream_t s);
 hipError_t launch_dslash64(const double2* u64, int nlinks, const DslashArgs<double2>& a,
@@ -229,14 +236,19 @@ hipError_t launch_dslash32(const float4* u32, int nlinks, const DslashArgs<float
                            int mode, hipStream_t s);
 hipError_t launch_neighbors(const Geom& g, int par, int* nb, int* sign, hipStream_t s);
 
-// The FP64 operator of a gauge object: FP64-18 links if stored, else hi + lo.
+// The FP64 operator of a gauge object: FP64-12 links if stored, else FP64-18,
+// else hi + lo.
 inline hipError_t launch_fp64_op(const rhmc_gauge* g, const DslashArgs<double2>& a, int mode,
                                  hipStream_t s) {
     const int nlinks = (int)(4 * g->lat.V);
+    if (g->u64c)
+        return launch_dslash64c(reinterpret_cast<const Fp64x12Link*>(g->u64c), nlinks, a, mode, s);
     if (g->u64) return launch_dslash64(g->u64, nlinks, a, mode, s);
     return launch_dslash64hl(reinterpret_cast<const HiLoLink*>(g->u32), nlinks, a, mode, s);
 }
-inline bool has_fp64_op(const rhmc_gauge* g) { return g->u64 || (g->u32 && g->hilo); }
+inline bool has_fp64_op(const rhmc_gauge* g) {
+    return g->u64c || g->u64 || (g->u32 && g->hilo);
+}
 
 // Pick the launch variant of the gauge object for this precision and nrhs.
 template <typename VT>

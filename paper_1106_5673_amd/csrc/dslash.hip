@@ -14,7 +14,7 @@ namespace rhmc {
 __global__ __launch_bounds__(kBlock) void k_pack_links(const double2* __restrict__ canon, Geom g,
                                                         double2* __restrict__ u64,
                                                         float4* __restrict__ u32, int hilo,
-                                                        int nlinks) {
+                                                        double2* __restrict__ u64c, int nlinks) {
     const int id = blockIdx.x * blockDim.x + threadIdx.x;  // lex * 4 + mu
     const int V = 2 * g.Vh;
     if (id >= 4 * V) return;
@@ -34,6 +34,10 @@ __global__ __launch_bounds__(kBlock) void k_pack_links(const double2* __restrict
     if (u64) {
 #pragma unroll
         for (int i = 0; i < 9; ++i) u64[(size_t)i * nlinks + k] = e[i];
+    }
+    if (u64c) {
+#pragma unroll
+        for (int i = 0; i < 6; ++i) u64c[(size_t)i * nlinks + k] = e[i];
     }
     if (u32) {
         // rows 1-2 rounded to nearest FP32; row 3 is rebuilt in the kernel
@@ -61,7 +65,7 @@ hipError_t launch_pack_links(const rhmc_gauge* g, const double2* canon, hipStrea
     const int nlinks = 4 * V;
     const int grid = (4 * V + kBlock - 1) / kBlock;
     hipLaunchKernelGGL(k_pack_links, dim3(grid), dim3(kBlock), 0, s, canon, g->lat.geom, g->u64,
-                       g->u32, g->hilo, nlinks);
+                       g->u32, g->hilo, g->u64c, nlinks);
     return hipGetLastError();
 }
 
@@ -127,6 +131,25 @@ __device__ __forceinline__ void load_link(const double2* __restrict__ u, int nli
         }
 }
 
+// Row 3 of an SU(3) matrix from rows 1-2: conj(row1 x row2) (valid for det U = 1).
+template <typename RT>
+__device__ __forceinline__ void rebuild_row3(Link<RT>& L) {
+    // No contraction into FMA here: which products fuse would otherwise depend
+    // on the surrounding code, and every launch variant must give the same bits.
+#pragma clang fp contract(off)
+    // (row1 x row2)_j = row1_{j+1} row2_{j+2} - row1_{j+2} row2_{j+1}
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const int j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+        const RT pr = L.re[0][j1] * L.re[1][j2] - L.im[0][j1] * L.im[1][j2]
+                    - (L.re[0][j2] * L.re[1][j1] - L.im[0][j2] * L.im[1][j1]);
+        const RT pi = L.re[0][j1] * L.im[1][j2] + L.im[0][j1] * L.re[1][j2]
+                    - (L.re[0][j2] * L.im[1][j1] + L.im[0][j2] * L.re[1][j1]);
+        L.re[2][j] = pr;
+        L.im[2][j] = -pi;
+    }
+}
+
 // 12-real link: rows 1-2 stored, row 3 = conj(row1 x row2) (valid for det U = 1).
 template <bool NT>
 __device__ __forceinline__ void load_link(const float4* __restrict__ u, int nlinks, int k,
@@ -137,17 +160,7 @@ __device__ __forceinline__ void load_link(const float4* __restrict__ u, int nlin
     L.re[0][0] = a.x; L.im[0][0] = a.y; L.re[0][1] = a.z; L.im[0][1] = a.w;
     L.re[0][2] = b.x; L.im[0][2] = b.y; L.re[1][0] = b.z; L.im[1][0] = b.w;
     L.re[1][1] = c.x; L.im[1][1] = c.y; L.re[1][2] = c.z; L.im[1][2] = c.w;
-    // (row1 x row2)_j = row1_{j+1} row2_{j+2} - row1_{j+2} row2_{j+1}; row3 = its conjugate
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        const int j1 = (j + 1) % 3, j2 = (j + 2) % 3;
-        const float pr = L.re[0][j1] * L.re[1][j2] - L.im[0][j1] * L.im[1][j2]
-                       - (L.re[0][j2] * L.re[1][j1] - L.im[0][j2] * L.im[1][j1]);
-        const float pi = L.re[0][j1] * L.im[1][j2] + L.im[0][j1] * L.re[1][j2]
-                       - (L.re[0][j2] * L.im[1][j1] + L.im[0][j2] * L.re[1][j1]);
-        L.re[2][j] = pr;
-        L.im[2][j] = -pi;
-    }
+    rebuild_row3(L);
 }
 
 // FP64 link from hi + lo planes: rows 1-2 = hi + lo in FP64, row 3 rebuilt in
@@ -173,16 +186,21 @@ __device__ __forceinline__ void load_link(const HiLoLink* __restrict__ uh, int n
         L.re[e / 3][e % 3] = w[2 * e];
         L.im[e / 3][e % 3] = w[2 * e + 1];
     }
+    rebuild_row3(L);
+}
+
+// FP64 link from 12 stored doubles (rows 1-2), row 3 rebuilt in FP64.
+template <bool NT>
+__device__ __forceinline__ void load_link(const Fp64x12Link* __restrict__ uc, int nlinks, int k,
+                                          Link<double>& L) {
+    const double2* u = reinterpret_cast<const double2*>(uc);
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        const int j1 = (j + 1) % 3, j2 = (j + 2) % 3;
-        const double pr = L.re[0][j1] * L.re[1][j2] - L.im[0][j1] * L.im[1][j2]
-                        - (L.re[0][j2] * L.re[1][j1] - L.im[0][j2] * L.im[1][j1]);
-        const double pi = L.re[0][j1] * L.im[1][j2] + L.im[0][j1] * L.re[1][j2]
-                        - (L.re[0][j2] * L.im[1][j1] + L.im[0][j2] * L.re[1][j1]);
-        L.re[2][j] = pr;
-        L.im[2][j] = -pi;
+    for (int e = 0; e < 6; ++e) {
+        const double2 v = ldg<NT>(u + (size_t)e * nlinks + k);
+        L.re[e / 3][e % 3] = v.x;
+        L.im[e / 3][e % 3] = v.y;
     }
+    rebuild_row3(L);
 }
 
 template <typename VT> struct RealOf;
@@ -390,6 +408,15 @@ hipError_t launch_dslash64(const double2* u64, int nlinks, const DslashArgs<doub
         case kModeD: return dispatch<double2, double2, kModeD>(u64, nlinks, a, s);
         case kModeA: return dispatch<double2, double2, kModeA>(u64, nlinks, a, s);
         default: return dispatch<double2, double2, kModeResid>(u64, nlinks, a, s);
+    }
+}
+
+hipError_t launch_dslash64c(const Fp64x12Link* u, int nlinks, const DslashArgs<double2>& a,
+                            int mode, hipStream_t s) {
+    switch (mode) {
+        case kModeD: return dispatch<double2, Fp64x12Link, kModeD>(u, nlinks, a, s);
+        case kModeA: return dispatch<double2, Fp64x12Link, kModeA>(u, nlinks, a, s);
+        default: return dispatch<double2, Fp64x12Link, kModeResid>(u, nlinks, a, s);
     }
 }
 

@@ -440,7 +440,6 @@ static rhmc_status true_residuals(rhmc_gauge* g, const Problem& pb, const std::v
                                   double* out2, double2* store, hipStream_t s) {
     Workspace* w = g->ws;
     const size_t n = w->n;
-    const int nlinks = (int)(4 * g->lat.V);
     for (size_t c0 = 0; c0 < list.size(); c0 += kMaxSys) {
         const int cnt = (int)std::min<size_t>(kMaxSys, list.size() - c0);
         DslashArgs<double2> d{};

@@ -13,7 +13,7 @@ void default_hop_variants(int (&v)[2][4]) {
     // planes with t inside the tile keep the neighbour vectors of a wave's
     // sites in L2; the links, read once, are streamed (non-temporal); a cap
     // of 4-5 resident workgroups per CU helps the one-rhs kernels
-    const int fp64[4] = {38, 7, 38, 14};
+    const int fp64[4] = {20, 31, 14, 63};   // FP64-12 links (the default FP64 storage)
     const int fp32[4] = {18, 10, 14, 14};
     for (int k = 0; k < 4; ++k) {
         v[RHMC_PREC_FP64][k] = fp64[k];

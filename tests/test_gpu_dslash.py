@@ -285,3 +285,49 @@ def test_hilo_links_fp64_operator(rh):
         assert torch.equal(a32, b32)
     g18.close()
     ghl.close()
+
+
+def test_fp64_12_links_and_su3_check(rh):
+    """FP64-12 storage (rows 1-2, row 3 rebuilt in FP64) gives the FP64-18
+    operator to rounding; links that are not SU(3) to 1e-12 are refused for
+    it (and default storage falls back to FP64-18), and links far from SU(3)
+    are refused for the 12-real FP32 copy."""
+    import torch
+
+    L = (6, 4, 4, 8)
+    U = synth.gauge_field(L, 0.7, 4500)
+    lat = rh.rhmc_lattice_create(L, -1)
+    g12 = rh.rhmc_gauge_create(lat, U, flags=rh.RHMC_LINKS_FP64_12)
+    g18 = rh.rhmc_gauge_create(lat, U, flags=rh.RHMC_LINKS_FP64_18)
+    rng = np.random.default_rng(16)
+    v = _rand_vec(rng, 2, lat.Vh)
+    vin = _to(v)
+    a, b = torch.empty_like(vin), torch.empty_like(vin)
+    rh.rhmc_dslash_eo(g12, 1, rh.RHMC_PREC_FP64, 2, vin, a)
+    rh.rhmc_dslash_eo(g18, 1, rh.RHMC_PREC_FP64, 2, vin, b)
+    want = dirac.dslash(U, v, 1, -1)
+    scale = np.abs(want).max()
+    assert np.abs(a.cpu().numpy() - want).max() <= 1e-13 * scale
+    assert np.abs(a.cpu().numpy() - b.cpu().numpy()).max() <= 1e-14 * scale
+    with pytest.raises(rh.RhmcError):   # FP64-12 has no FP32 copy
+        rh.rhmc_dslash_eo(g12, 1, rh.RHMC_PREC_FP32, 1, vin[:1].to(torch.complex64).contiguous(),
+                          torch.empty((1, 3, lat.Vh), dtype=torch.complex64, device="cuda:0"))
+    g12.close()
+    g18.close()
+    # row 3 off by 1e-9: no FP64-12, default storage falls back to FP64-18
+    Ub = np.array(U)
+    Ub[..., 2, :] *= 1 + 1e-9
+    with pytest.raises(rh.RhmcError):
+        rh.rhmc_gauge_create(lat, Ub, flags=rh.RHMC_LINKS_FP64_12)
+    gb = rh.rhmc_gauge_create(lat, Ub)
+    out = torch.empty_like(vin)
+    rh.rhmc_dslash_eo(gb, 1, rh.RHMC_PREC_FP64, 2, vin, out)
+    wantb = dirac.dslash(Ub, v, 1, -1)
+    assert np.abs(out.cpu().numpy() - wantb).max() <= 1e-13 * np.abs(wantb).max()
+    gb.close()
+    # far from SU(3): refused for 12-real FP32 storage, accepted as FP64-18 only
+    Uc = np.array(U)
+    Uc[..., 2, :] *= 1.01
+    with pytest.raises(rh.RhmcError):
+        rh.rhmc_gauge_create(lat, Uc)
+    rh.rhmc_gauge_create(lat, Uc, flags=rh.RHMC_LINKS_FP64_18).close()
