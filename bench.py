@@ -59,7 +59,7 @@ def dslash_bytes_per_site(prec: str, nrhs: int) -> int:
 def kernel_source_hash():
     """Hash of the hopping kernel's sources (kernel file and its header)."""
     h = hashlib.sha256()
-    for name in ("dslash.hip", "common.h"):
+    for name in ("dslash_kernel.h", "dslash.hip", "common.h"):
         with open(os.path.join(ROOT, "paper_1106_5673_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

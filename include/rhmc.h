@@ -221,19 +221,18 @@ rhmc_status rhmc_tune_dslash(rhmc_gauge* g, rhmc_prec prec, int32_t nrhs, const 
 
 /* The launch variant the hopping kernel currently uses for this precision and
  * rhs count (the measured default, or the autotuner's choice), for reports:
- * variant (host int32) = order | nt << 2 | pipe << 3 | occ << 4, with order the
+ * variant (host int32) = order | nt << 2 | batch << 3 | occ << 5, with order the
  * site processing order 0..3 (0 even-odd index, 1 x,y,t,z, 2 and 3 z-tiles of 4
- * and 2 planes with t inside a tile), nt non-temporal link loads, pipe the
- * loads of two hops issued as one batch and occ a cap on resident workgroups
- * per CU. */
+ * and 2 planes with t inside a tile), nt non-temporal link loads, batch the
+ * number of hops whose loads are issued together (1, 2, 4, 8 for 0..3) and occ
+ * a cap on resident workgroups per CU (none, 5, 4, 3). */
 rhmc_status rhmc_dslash_variant(const rhmc_gauge* g, rhmc_prec prec, int32_t nrhs,
                                 int32_t* variant);
 
 /* Pin the launch variant of the hopping kernel for this precision and rhs
- * count (0 <= variant < 64, layout as above, plus occ << 4: a cap on resident
- * workgroups per CU, none / 5 / 4 / 3).  Every variant computes the same
- * result bit for bit; they differ only in speed.  Marks the class as tuned,
- * so tune = 1 in later solver calls keeps it. */
+ * count (0 <= variant < 128, layout as above).  Every variant computes the
+ * same result bit for bit; they differ only in speed.  Marks the class as
+ * tuned, so tune = 1 in later solver calls keeps it. */
 rhmc_status rhmc_set_dslash_variant(rhmc_gauge* g, rhmc_prec prec, int32_t nrhs,
                                     int32_t variant);
 

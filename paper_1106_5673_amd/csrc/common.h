@@ -197,16 +197,16 @@ struct DslashArgs {
     int variant;                  // launch variant (HopVariant index)
 };
 
-// Launch variants of the hopping kernel, index = order | nt << 2 | pipe << 3
-// | occ << 4:
+// Launch variants of the hopping kernel, index = order | nt << 2 | batch << 3
+// | occ << 5:
 //   order  site processing order (process_site), 0..3
 //   nt     non-temporal (streaming) loads of the links, which are read once
 //          per application and need not displace neighbour vectors
-//   pipe   issue the loads of two hops as one batch instead of one
+//   batch  hops whose loads are issued together: 1, 2, 4 or 8 (bits 0..3)
 //   occ    cap on resident workgroups per CU (none, 5, 4, 3), set through an
 //          unused dynamic LDS allocation: fewer sites in flight per XCD keep
 //          the neighbour vectors they share inside that XCD's L2
-constexpr int kHopVariants = 64;
+constexpr int kHopVariants = 128;
 // dynamic LDS bytes per workgroup for occ = 0..3 (160 KB of LDS per CU)
 constexpr int kOccLds[4] = {0, 32 * 1024, 40 * 1024, 53 * 1024};
 // right-hand-side classes of the kernel templates: 1, 2, 4, 8

@@ -8,13 +8,13 @@
 namespace rhmc {
 
 void default_hop_variants(int (&v)[2][4]) {
-    // index = order | nt << 2 | pipe << 3
-    // measured on MI355X at 48^3 x 12 (rhs classes 1, 2, 4, 8): z-tiles of 4
-    // planes with t inside the tile keep the neighbour vectors of a wave's
-    // sites in L2; the links, read once, are streamed (non-temporal); a cap
-    // of 4-5 resident workgroups per CU helps the one-rhs kernels
-    const int fp64[4] = {20, 31, 14, 63};   // FP64-12 links (the default FP64 storage)
-    const int fp32[4] = {18, 10, 14, 14};
+    // index = order | nt << 2 | batch << 3 | occ << 5
+    // measured on MI355X at 48^3 x 12 (rhs classes 1, 2, 4, 8): z-tiles with
+    // t inside a tile keep the neighbour vectors of a wave's sites in L2; the
+    // links, read once, are streamed (non-temporal); loads go in batches of
+    // one to four hops (the one-rhs kernels have registers to spare)
+    const int fp64[4] = {39, 47, 14, 46};    // FP64-12 links (the default FP64 storage)
+    const int fp32[4] = {17, 83, 14, 102};
     for (int k = 0; k < 4; ++k) {
         v[RHMC_PREC_FP64][k] = fp64[k];
         v[RHMC_PREC_FP32][k] = fp32[k];

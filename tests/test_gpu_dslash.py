@@ -207,7 +207,7 @@ def test_invalid_arguments(rh):
 
 @pytest.mark.parametrize("L", [(4, 6, 8, 4), (6, 4, 6, 8)])
 def test_every_launch_variant_gives_identical_bits(rh, L):
-    """All 64 launch variants (site order, link cache policy, load batching,
+    """All 128 launch variants (site order, link cache policy, load batching,
     resident-workgroup cap) compute every output site with the same
     arithmetic: D_eo, D_oe and A agree bit for bit with variant 0, which is
     checked against the oracle.  Lz = 6 exercises the z-tile fallback."""
@@ -224,7 +224,7 @@ def test_every_launch_variant_gives_identical_bits(rh, L):
             v = _rand_vec(rng, nrhs, lat.Vh).astype(cdt)
             vin = _to(v)
             ref = {}
-            for var in range(64):
+            for var in range(128):
                 rh.rhmc_set_dslash_variant(g, prec, nrhs, var)
                 assert rh.rhmc_dslash_variant(g, prec, nrhs) == var
                 for out_par in (0, 1):
@@ -250,7 +250,7 @@ def test_every_launch_variant_gives_identical_bits(rh, L):
                 else:
                     assert np.array_equal(gotA, ref["A"]), (var, "A")
     with pytest.raises(rh.RhmcError):
-        rh.rhmc_set_dslash_variant(g, rh.RHMC_PREC_FP64, 1, 64)
+        rh.rhmc_set_dslash_variant(g, rh.RHMC_PREC_FP64, 1, 128)
     g.close()
 
 
