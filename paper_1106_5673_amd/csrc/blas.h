@@ -30,7 +30,9 @@ struct FlushArgs {
     int nshift;
     int nsys;
     VT* ring;               // stored base residuals: r(k0+l) of system j at ring + (l*nsys + j)*n
-    VT* P;                  // shifted directions [nsys][nshift][n]
+    double2* P;             // shifted directions [nsys][nshift][n], FP64 in every mode:
+                            // rounding them is what limits a mixed solve's shifted
+                            // true residuals, and they move only once per block
     double2* X;             // shifted solutions
     size_t x_sys, x_shift;  // element strides of X between systems / shifts
 };

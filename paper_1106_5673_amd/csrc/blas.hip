@@ -244,7 +244,7 @@ __global__ __launch_bounds__(kBlock) void k_flush(FlushArgs<VT> a,
     const bool first = st->first_block != 0;
     const int nsh = a.nshift;
     double2* __restrict__ X = a.X;
-    VT* __restrict__ P = a.P;
+    double2* __restrict__ P = a.P;
 #pragma unroll 1
     for (int s0 = 0; s0 < nsh; s0 += U) {
         bool act[U];
@@ -259,7 +259,7 @@ __global__ __launch_bounds__(kBlock) void k_flush(FlushArgs<VT> a,
             p0i[u] = rim[0];
             if (act[u] && !first) {
                 xv[u] = X[j * a.x_sys + sh * a.x_shift + i];
-                const VT pv = P[((size_t)j * nsh + sh) * a.n + i];
+                const double2 pv = P[((size_t)j * nsh + sh) * a.n + i];
                 p0r[u] = (double)pv.x;
                 p0i[u] = (double)pv.y;
             }
@@ -280,12 +280,7 @@ __global__ __launch_bounds__(kBlock) void k_flush(FlushArgs<VT> a,
                 pi += d * rim[l];
             }
             X[j * a.x_sys + sh * a.x_shift + i] = make_double2(xr, xi);
-            if (st->sh[j][sh].active) {
-                VT pv;
-                pv.x = pr;
-                pv.y = pi;
-                P[((size_t)j * nsh + sh) * a.n + i] = pv;
-            }
+            if (st->sh[j][sh].active) P[((size_t)j * nsh + sh) * a.n + i] = make_double2(pr, pi);
         }
     }
     // the last stored residual is r(k0) of the next block

@@ -258,7 +258,7 @@ static rhmc_status enqueue_block(const rhmc_gauge* g, Workspace* w, const Proble
     f.nshift = pb.nshift;
     f.nsys = ns;
     f.ring = reinterpret_cast<VT*>(w->ring);
-    f.P = reinterpret_cast<VT*>(w->P);
+    f.P = reinterpret_cast<double2*>(w->P);
     f.X = pb.X;
     f.x_sys = pb.x_sys;
     f.x_shift = pb.x_shift;
