@@ -73,3 +73,19 @@ def test_product_path_has_no_oracle_import():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt, f
+
+
+def test_lattice_rejects_too_many_sites(rh):
+    """Site indices are 32-bit: V above 2^28 is refused before any allocation."""
+    with pytest.raises(rh.RhmcError) as e:
+        rh.rhmc_lattice_create((256, 256, 128, 64))
+    assert e.value.status == rh.RHMC_ERR_INVALID_ARG
+
+
+def test_variant_encoding_limits(rh):
+    """The launch-variant index has 7 bits (order, nt, batch, occ)."""
+    import re
+
+    hdr = open(os.path.join(ROOT, "include", "rhmc.h")).read()
+    assert "0 <= variant < 128" in hdr
+    assert re.search(r"batch << 3 \| occ << 5", hdr)

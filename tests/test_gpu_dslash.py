@@ -331,3 +331,32 @@ def test_fp64_12_links_and_su3_check(rh):
     with pytest.raises(rh.RhmcError):
         rh.rhmc_gauge_create(lat, Uc)
     rh.rhmc_gauge_create(lat, Uc, flags=rh.RHMC_LINKS_FP64_18).close()
+
+
+def test_max_rhs_and_direct_tuning(rh):
+    """64 right-hand sides in one call (eight launches of eight) equal
+    one-at-a-time results to FP64 rounding, and rhmc_tune_dslash picks a valid
+    variant without changing any result bit."""
+    import torch
+
+    L = (4, 4, 4, 6)
+    U = synth.gauge_field(L, 0.6, 4600)
+    lat = rh.rhmc_lattice_create(L, -1)
+    g = rh.rhmc_gauge_create(lat, U)
+    rng = np.random.default_rng(17)
+    v = _to(_rand_vec(rng, 64, lat.Vh))
+    out = torch.empty_like(v)
+    rh.rhmc_dslash_eo(g, 0, rh.RHMC_PREC_FP64, 64, v, out)
+    one = torch.empty_like(v[:1])
+    for r in (0, 7, 8, 63):
+        rh.rhmc_dslash_eo(g, 0, rh.RHMC_PREC_FP64, 1, v[r:r + 1].contiguous(), one)
+        assert (one[0] - out[r]).abs().max().item() <= 1e-15 * one.abs().max().item()
+    v32 = v[:4].to(torch.complex64).contiguous()
+    a, b = torch.empty_like(v32), torch.empty_like(v32)
+    rh.rhmc_dslash_eo(g, 1, rh.RHMC_PREC_FP32, 4, v32, a)
+    rh.rhmc_tune_dslash(g, rh.RHMC_PREC_FP32, 4, v32, b)
+    var = rh.rhmc_dslash_variant(g, rh.RHMC_PREC_FP32, 4)
+    assert 0 <= var < 128
+    rh.rhmc_dslash_eo(g, 1, rh.RHMC_PREC_FP32, 4, v32, b)
+    assert torch.equal(a, b)
+    g.close()
