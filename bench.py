@@ -284,11 +284,18 @@ def main():
         torch.cuda.synchronize()
         t_act = time.perf_counter() - t1
         R2 = (R.abs() ** 2).sum(dim=(1, 2)).cpu().numpy()
-        pf = {"heatbath_s": round(t_hb, 4), "action_s": round(t_act, 4),
+        Fdev = torch.empty(tuple(reversed(L)) + (4, 3, 3), dtype=torch.complex128, device=dev)
+        t1 = time.perf_counter()
+        rhmc.rhmc_pf_force(g, m, rat.alpha0, rat.alpha, rat.beta, phi, Fdev, prm_mixed)
+        torch.cuda.synchronize()
+        t_force = time.perf_counter() - t1
+        del Fdev
+        pf = {"heatbath_s": round(t_hb, 4), "action_s": round(t_act, 4), "force_s": round(t_force, 4),
               "max_abs_S_over_RR_minus_1": float(np.max(np.abs(S / R2 - 1))),
-              "note": "MIXED batched, x^{+1/8} heat bath then x^{-1/4} action; "
+              "note": "MIXED batched, x^{+1/8} heat bath, x^{-1/4} action and force; "
                       "S = R^dagger R up to the minimax errors and the solver tolerance"}
         log(f"pseudofermion heat bath {t_hb * 1e3:.0f} ms, action {t_act * 1e3:.0f} ms, "
+            f"force {t_force * 1e3:.0f} ms, "
             f"max |S/RR - 1| = {pf['max_abs_S_over_RR_minus_1']:.2e}")
 
     tag = f"dslash_fp32_{nrhs}rhs_{'x'.join(str(v) for v in L)}"

@@ -209,6 +209,23 @@ rhmc_status rhmc_pf_action(const rhmc_gauge* g, double m, const rhmc_rational* r
                            const rhmc_solver_params* params, rhmc_solver_stats* stats,
                            hipStream_t stream);
 
+/* Pseudofermion force: the derivative of S = sum_r phi_r^dagger r(A) phi_r
+ * with respect to the links, the molecular-dynamics force of Sec. 2.1.  For
+ * the variation U_mu(n) -> exp(i eps T) U_mu(n) of one link (T Hermitian and
+ * traceless), dS/deps = i Tr(T F_mu(n)) with
+ *   F_mu(n) = TA(U_mu(n) M_mu(n)),   TA(X) = (X - X^dagger)/2 - Tr(X - X^dagger)/6,
+ *   M_mu(n) = s_mu(n) sum_i alpha_i y_i(n+mu) x_i(n)^dagger   (n even),
+ *            -s_mu(n) sum_i alpha_i x_i(n+mu) y_i(n)^dagger   (n odd),
+ * x_i = (A + beta_i)^-1 phi (solved as rhmc_multishift_cg does, same params
+ * and stats), y_i = D_oe x_i with the FP64 operator, s_mu(n) = eta_mu(n) times
+ * the time-boundary sign of the hop n -> n+mu.  phi: device complex128
+ * [nrhs][3][V/2]; force: device complex128 [Lt][Lz][Ly][Lx][4][3][3] (the
+ * layout of the links given to rhmc_gauge_create), overwritten; traceless
+ * anti-Hermitian.  Needs an FP64 operator.  Blocks until done. */
+rhmc_status rhmc_pf_force(const rhmc_gauge* g, double m, const rhmc_rational* rat, int32_t nrhs,
+                          const void* phi, void* force, const rhmc_solver_params* params,
+                          rhmc_solver_stats* stats, hipStream_t stream);
+
 /* Autotuner of the hopping kernel (the batching form's launch shapes): times
  * every launch variant (site processing order, non-temporal link loads, loads
  * of one or two hops per batch) of one application D_oe on the given vectors

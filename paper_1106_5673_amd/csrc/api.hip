@@ -372,6 +372,31 @@ rhmc_status rhmc_pf_action(const rhmc_gauge* gc, double m, const rhmc_rational* 
     return pf_action(g, m, rat, nrhs, reinterpret_cast<const double2*>(phi), S, prm, stats, stream);
 }
 
+rhmc_status rhmc_pf_force(const rhmc_gauge* gc, double m, const rhmc_rational* rat, int32_t nrhs,
+                          const void* phi, void* force, const rhmc_solver_params* params,
+                          rhmc_solver_stats* stats, hipStream_t stream) {
+    rhmc_gauge* g = const_cast<rhmc_gauge*>(gc);
+    if (!g || !rat || !phi || !force) return invalid("null argument");
+    if (nrhs < 1 || nrhs > 64) return invalid("nrhs must be in 1..64");
+    if (!std::isfinite(m) || !std::isfinite(rat->alpha0)) return invalid("non-finite coefficient");
+    if (rat->npole < 1 || !rat->alpha) return invalid("rational needs npole >= 1 and alpha");
+    for (int i = 0; i < rat->npole; ++i)
+        if (!std::isfinite(rat->alpha[i])) return invalid("non-finite coefficient");
+    RHMC_TRY(check_shifts(m, rat->npole, rat->beta));
+    rhmc_solver_params prm;
+    RHMC_TRY(check_params(params, g, &prm));
+    RHMC_TRY(use_device(g->device));
+    if (stats) {
+        stats->total_iterations = 0;
+        stats->reliable_updates = 0;
+        stats->refine_rounds = 0;
+        stats->time_ms = 0;
+        stats->max_true_residual = 0;
+    }
+    return pf_force(g, m, rat, nrhs, reinterpret_cast<const double2*>(phi),
+                    reinterpret_cast<double2*>(force), prm, stats, stream);
+}
+
 rhmc_status rhmc_tune_dslash(rhmc_gauge* g, rhmc_prec prec, int32_t nrhs, const void* in,
                              void* out, hipStream_t stream) {
     if (!g || !in || !out) return invalid("null argument");

@@ -20,4 +20,9 @@ rhmc_status pf_action(rhmc_gauge* g, double m, const rhmc_rational* rat, int nrh
                       const double2* phi, double* S, const rhmc_solver_params& prm,
                       rhmc_solver_stats* stats, hipStream_t s);
 
+// force[lex][mu] = TA(U M) of S = sum_r phi[r]^dagger r(A) phi[r] (force.hip)
+rhmc_status pf_force(rhmc_gauge* g, double m, const rhmc_rational* rat, int nrhs,
+                     const double2* phi, double2* force, const rhmc_solver_params& prm,
+                     rhmc_solver_stats* stats, hipStream_t s);
+
 }  // namespace rhmc

@@ -24,6 +24,7 @@
 
 #include "blas.h"
 #include "solver.h"
+#include "force.h"
 #include "state.h"
 
 namespace rhmc {
@@ -75,6 +76,9 @@ struct Workspace {
     // pseudofermion action: r(A) phi, [nrhs]
     double2* ya = nullptr;
     size_t ya_cap = 0;
+    // pseudofermion force: D_oe x_i, [nsys][npole]
+    double2* yf = nullptr;
+    size_t yf_cap = 0;
     CachedGraph graphs[4];
     int graph_next = 0;
 };
@@ -91,7 +95,7 @@ void workspace_destroy(Workspace* w) {
     if (!w) return;
     free_graphs(w);
     for (void* p : {w->ring, w->p, w->Ap, w->t, w->P, (void*)w->t64, (void*)w->rb, (void*)w->rx,
-                    (void*)w->xr, (void*)w->ya, (void*)w->partial, (void*)w->sums,
+                    (void*)w->xr, (void*)w->ya, (void*)w->yf, (void*)w->partial, (void*)w->sums,
                     (void*)w->st, (void*)w->coef})
         hipFree(p);
     hipHostFree(w->hst);
@@ -739,6 +743,69 @@ rhmc_status pf_action(rhmc_gauge* g, double m, const rhmc_rational* rat, int nrh
         for (int k = 0; k < cnt; ++k) S[r0 + k] = w->sums_host[k];
     }
     return rs;
+}
+
+rhmc_status pf_force(rhmc_gauge* g, double m, const rhmc_rational* rat, int nrhs,
+                     const double2* phi, double2* force, const rhmc_solver_params& prm,
+                     rhmc_solver_stats* stats, hipStream_t s) {
+    const size_t n = (size_t)3 * g->lat.Vh;
+    const int np = rat->npole;
+    const int grp = std::min(nrhs, kMaxSys);
+    const int K = std::max(1, std::min(kMaxBlockLen, prm.block));
+    RHMC_TRY(ensure_workspace(g, grp, np, K));
+    Workspace* w = g->ws;
+    double2* xr = nullptr;
+    RHMC_TRY(ensure_rational_buffer(g, (size_t)grp * np, &xr));
+    RHMC_TRY(grow(w, (void**)&w->yf, &w->yf_cap, w->vec_bytes * (size_t)grp * np));
+    rhmc_status worst = RHMC_OK;
+    for (int r0 = 0; r0 < nrhs; r0 += kMaxSys) {
+        const int cnt = std::min(kMaxSys, nrhs - r0);
+        rhmc_solver_stats st{};
+        if (stats) {
+            st.iterations = stats->iterations ? stats->iterations + (size_t)r0 * np : nullptr;
+            st.true_residual = stats->true_residual ? stats->true_residual + (size_t)r0 * np : nullptr;
+            st.refine_iterations =
+                stats->refine_iterations ? stats->refine_iterations + (size_t)r0 * np : nullptr;
+        }
+        // x_i = (A + beta_i)^-1 phi for every pole
+        const rhmc_status rs = multishift(g, m, np, rat->beta, cnt, phi + (size_t)r0 * n, xr,
+                                          (size_t)np * n, n, prm, &st, s);
+        if (stats) {
+            stats->total_iterations = std::max(stats->total_iterations, st.total_iterations);
+            stats->reliable_updates += st.reliable_updates;
+            stats->refine_rounds = std::max(stats->refine_rounds, st.refine_rounds);
+            stats->time_ms += st.time_ms;
+            stats->max_true_residual = std::max(stats->max_true_residual, st.max_true_residual);
+        }
+        if (rs != RHMC_OK && rs != RHMC_ERR_NOT_CONVERGED) return rs;
+        if (rs != RHMC_OK) worst = rs;
+        // y_i = D_oe x_i with the FP64 operator, kMaxSys vectors per launch
+        const int nvec = cnt * np;
+        for (int v0 = 0; v0 < nvec; v0 += kMaxSys) {
+            DslashArgs<double2> d{};
+            d.g = g->lat.geom;
+            d.out_par = 1;
+            d.nrhs = std::min(kMaxSys, nvec - v0);
+            for (int k = 0; k < d.nrhs; ++k) {
+                d.in[k] = xr + (size_t)(v0 + k) * n;
+                d.out[k] = w->yf + (size_t)(v0 + k) * n;
+            }
+            set_variant(d, g);
+            RHMC_HIP_TRY(launch_fp64_op(g, d, kModeD, s));
+        }
+        ForceArgs f{};
+        f.g = g->lat.geom;
+        f.x = xr;
+        f.y = w->yf;
+        f.nrhs = cnt;
+        f.npole = np;
+        for (int i = 0; i < np; ++i) f.alpha[i] = rat->alpha[i];
+        f.out = force;
+        f.accumulate = r0 > 0;
+        RHMC_HIP_TRY(launch_force(g, f, s));
+    }
+    RHMC_HIP_TRY(hipStreamSynchronize(s));
+    return worst;
 }
 
 }  // namespace rhmc

@@ -40,6 +40,7 @@ EXPORTED = (
     "rhmc_debug_neighbors", "rhmc_gauge_create", "rhmc_gauge_destroy", "rhmc_dslash_eo",
     "rhmc_apply_mdagm", "rhmc_multishift_cg", "rhmc_rational_apply", "rhmc_tune_dslash",
     "rhmc_dslash_variant", "rhmc_set_dslash_variant", "rhmc_pf_phi", "rhmc_pf_action",
+    "rhmc_pf_force",
     "rhmc_status_string", "rhmc_last_error",
 )
 
@@ -94,6 +95,8 @@ def load():
         "rhmc_rational_apply": (i32, [vp, f64, C.POINTER(rhmc_rational), i32, vp, vp,
                                       C.POINTER(rhmc_solver_params), C.POINTER(rhmc_solver_stats), vp]),
         "rhmc_tune_dslash": (i32, [vp, i32, i32, vp, vp, vp]),
+        "rhmc_pf_force": (i32, [vp, f64, C.POINTER(rhmc_rational), i32, vp, vp,
+                                C.POINTER(rhmc_solver_params), C.POINTER(rhmc_solver_stats), vp]),
         "rhmc_pf_phi": (i32, [vp, f64, i32, vp, vp, vp, vp]),
         "rhmc_pf_action": (i32, [vp, f64, C.POINTER(rhmc_rational), i32, vp, C.POINTER(C.c_double),
                                  C.POINTER(rhmc_solver_params), C.POINTER(rhmc_solver_stats), vp]),
@@ -342,6 +345,30 @@ def rhmc_pf_action(g: Gauge, m: float, alpha0: float, alpha, beta, phi, params=N
     if not (allow_not_converged and status == RHMC_ERR_NOT_CONVERGED):
         _check(status)
     return S, st.as_dict(nrhs, alpha.size, status)
+
+
+def rhmc_pf_force(g: Gauge, m: float, alpha0: float, alpha, beta, phi, force, params=None,
+                  stream=None, allow_not_converged=False):
+    """force = TA(U M) of S = sum_r phi_r^dagger r(A) phi_r; returns statistics."""
+    import torch
+
+    alpha = np.ascontiguousarray(alpha, dtype=np.float64)
+    beta = np.ascontiguousarray(beta, dtype=np.float64)
+    if alpha.shape != beta.shape or alpha.ndim != 1:
+        raise ValueError("alpha and beta must be 1-D of equal length")
+    nrhs = int(phi.shape[0])
+    Lx, Ly, Lz, Lt = g.lattice.L
+    pp = _ptr(phi, torch.complex128, (nrhs, 3, g.lattice.Vh), "phi")
+    pf = _ptr(force, torch.complex128, (Lt, Lz, Ly, Lx, 4, 3, 3), "force")
+    rat = rhmc_rational(float(alpha0), alpha.size, alpha.ctypes.data_as(C.POINTER(C.c_double)),
+                        beta.ctypes.data_as(C.POINTER(C.c_double)))
+    st = _Stats(nrhs, alpha.size)
+    prm = params if params is not None else rhmc_solver_params_default()
+    status = load().rhmc_pf_force(g.handle, float(m), C.byref(rat), nrhs, pp, pf, C.byref(prm),
+                                  C.byref(st.c), _stream(stream))
+    if not (allow_not_converged and status == RHMC_ERR_NOT_CONVERGED):
+        _check(status)
+    return st.as_dict(nrhs, alpha.size, status)
 
 
 def rhmc_tune_dslash(g: Gauge, prec: int, nrhs: int, inp, out, stream=None):

@@ -185,3 +185,122 @@ def test_pf_invalid_arguments(rh):
     with pytest.raises(rh.RhmcError):   # non-finite coefficient
         rh.rhmc_pf_action(g, 0.1, float("nan"), [1.0], [0.5], v)
     g.close()
+
+
+def _gauge_transform(U, G, phi_even):
+    """U^G_mu(n) = G(n) U_mu(n) G(n+mu)^dagger and phi -> G phi (even sites)."""
+    from oracle import lattice
+
+    L = dirac.lattice_of(U)
+    Ug = np.empty_like(U)
+    for mu in range(4):
+        Gf = np.roll(G, -1, axis=lattice.AXIS[mu] - 1)
+        Ug[..., mu, :, :] = G @ U[..., mu, :, :] @ np.swapaxes(Gf.conj(), -1, -2)
+    full = lattice.embed(phi_even, L, 0)
+    phig = lattice.restrict(np.einsum("...ab,...b->...a", G, full), L, 0)
+    return Ug, phig
+
+
+@pytest.mark.parametrize("flags", ["fp64_12", "fp64_18", "hilo"])
+def test_pf_force_matches_oracle(rh, flags):
+    import torch
+
+    from oracle import force
+
+    L = (4, 4, 4, 4)
+    c = synth.CONFIGS[1]
+    m = c["m"]
+    U = synth.gauge_field(L, c["eps"], 5400)
+    lat = rh.rhmc_lattice_create(L, -1)
+    fl = dict(fp64_12=rh.RHMC_LINKS_FP64_12 | rh.RHMC_LINKS_FP32_12,
+              fp64_18=rh.RHMC_LINKS_FP64_18 | rh.RHMC_LINKS_FP32_12,
+              hilo=rh.RHMC_LINKS_HILO_12)[flags]
+    g = rh.rhmc_gauge_create(lat, U, flags=fl)
+    r = rational_for(1, -0.25)
+    rng = np.random.default_rng(25)
+    phi = _gauss(rng, (2, 3, lat.Vh))
+    want = force.force(U, m, r.alpha, r.beta, phi)
+    scale = np.abs(want).max()
+    F = torch.empty(U.shape, dtype=torch.complex128, device="cuda:0")
+    st = rh.rhmc_pf_force(g, m, r.alpha0, r.alpha, r.beta, _dev(phi), F,
+                          rh.solver_params(tol=1e-13, mode=rh.RHMC_MODE_FP64))
+    assert st["max_true_residual"] <= 1e-13
+    # hi + lo links differ from the FP64 ones by ~2^-47 relative
+    tol = 1e-9 if flags != "hilo" else 1e-8
+    assert np.abs(F.cpu().numpy() - want).max() <= tol * scale
+    if flags == "fp64_12":
+        rh.rhmc_pf_force(g, m, r.alpha0, r.alpha, r.beta, _dev(phi), F,
+                         rh.solver_params(tol=1e-10, mode=rh.RHMC_MODE_MIXED))
+        assert np.abs(F.cpu().numpy() - want).max() <= 1e-6 * scale
+    g.close()
+
+
+def test_pf_force_gauge_covariance_16x16x16x4(rh):
+    """F[U^G, G phi] = G F[U, phi] G^dagger, both from the GPU (a property that
+    holds at any size; the tolerance is the solver's)."""
+    import torch
+
+    cfg = 2
+    c = synth.CONFIGS[cfg]
+    m = c["m"]
+    U = np.asarray(workload_gauge(cfg))
+    G = synth.gauge_field(c["L"], 1.0, 5500)[..., 0, :, :]
+    rng = np.random.default_rng(26)
+    lat = rh.rhmc_lattice_create(c["L"], -1)
+    phi = _gauss(rng, (2, 3, lat.Vh))
+    Ug, phig = _gauge_transform(U, G, phi)
+    r = rational_for(cfg, -0.25)
+    prm = rh.solver_params(tol=1e-12, mode=rh.RHMC_MODE_FP64)
+    out = []
+    for UU, pp in ((U, phi), (Ug, phig)):
+        g = rh.rhmc_gauge_create(lat, UU)
+        F = torch.empty(U.shape, dtype=torch.complex128, device="cuda:0")
+        rh.rhmc_pf_force(g, m, r.alpha0, r.alpha, r.beta, _dev(pp), F, prm)
+        out.append(F.cpu().numpy())
+        g.close()
+    F0, Fg = out
+    want = G[..., None, :, :] @ F0 @ np.swapaxes(G.conj(), -1, -2)[..., None, :, :]
+    assert np.abs(Fg - want).max() <= 1e-7 * np.abs(F0).max()
+
+
+def test_pf_force_48x48x48x12_mixed_structure(rh):
+    """Full size, MIXED batched, 4 sources x 20 poles.  The oracle cannot solve
+    at this size, so the checks are properties that hold at any size: F is
+    traceless anti-Hermitian, and a gauge transformation that differs from 1
+    only on a few sites rotates F there (F -> G F G^dagger) within the solver
+    tolerance."""
+    import torch
+
+    cfg = 5
+    c = synth.CONFIGS[cfg]
+    m, tol = c["m"], c["tol"]
+    U = np.asarray(workload_gauge(cfg))
+    lat = rh.rhmc_lattice_create(c["L"], -1)
+    rng = np.random.default_rng(27)
+    phi = _gauss(rng, (4, 3, lat.Vh))
+    r = rational_for(cfg, -0.25)
+    prm = rh.solver_params(tol=tol, mode=rh.RHMC_MODE_MIXED, tune=1)
+    g = rh.rhmc_gauge_create(lat, U)
+    F = torch.empty(U.shape, dtype=torch.complex128, device="cuda:0")
+    st = rh.rhmc_pf_force(g, m, r.alpha0, r.alpha, r.beta, _dev(phi), F, prm)
+    assert st["max_true_residual"] <= tol
+    g.close()
+    Fh = F.cpu().numpy()
+    scale = np.abs(Fh).max()
+    assert np.abs(Fh + np.swapaxes(Fh.conj(), -1, -2)).max() <= 1e-14 * scale
+    assert np.abs(np.trace(Fh, axis1=-2, axis2=-1)).max() <= 1e-14 * scale
+    # a gauge transformation that differs from 1 on a handful of sites
+    G = np.broadcast_to(np.eye(3, dtype=np.complex128), U.shape[:4] + (3, 3)).copy()
+    sites = [(0, 0, 0, 0), (5, 17, 33, 47), (11, 47, 2, 9), (6, 24, 24, 24)]
+    rot = synth.fields.random_su3((len(sites),), np.random.default_rng(28), 1.0)
+    for (t, z, y, x), Gs in zip(sites, rot):
+        G[t, z, y, x] = Gs
+    Ug, phig = _gauge_transform(U, G, phi)
+    g = rh.rhmc_gauge_create(lat, Ug)
+    Fg = torch.empty_like(F)
+    rh.rhmc_pf_force(g, m, r.alpha0, r.alpha, r.beta, _dev(phig), Fg, prm)
+    g.close()
+    Fgh = Fg.cpu().numpy()
+    for (t, z, y, x) in sites:
+        want = G[t, z, y, x] @ Fh[t, z, y, x] @ G[t, z, y, x].conj().T
+        assert np.abs(Fgh[t, z, y, x] - want).max() <= 1e-6 * scale
