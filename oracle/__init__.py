@@ -17,6 +17,14 @@ The oracle follows the paper's statement of the problem:
   dense solves and true residuals used to certify results.
 * ``rational`` -- r(A) b = alpha0 b + sum_i alpha_i (A + beta_i)^-1 b, the
   rational approximation of the rooted system (Sec. 2.1, Eq. system_r).
+* ``pseudofermion``, ``force`` -- the pseudofermion field, action and heat
+  bath of the Phi algorithm, and the derivative of the action with respect
+  to the links (Sec. 2.1).
+* ``gauge`` -- plaquette action and its force, momenta, the exponential link
+  update and reunitarisation (Sec. 2, 2.1, 4.1).
+* ``md`` -- the multi-step second-order minimum-norm integrator, the
+  Hamiltonian, one trajectory with its Metropolis test, and the
+  reversibility estimators (Sec. 2.1, 4.4).
 """
 
-from . import dirac, lattice, rational, solvers  # noqa: F401
+from . import dirac, force, gauge, lattice, md, pseudofermion, rational, solvers  # noqa: F401
