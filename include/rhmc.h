@@ -253,6 +253,131 @@ rhmc_status rhmc_dslash_variant(const rhmc_gauge* g, rhmc_prec prec, int32_t nrh
 rhmc_status rhmc_set_dslash_variant(rhmc_gauge* g, rhmc_prec prec, int32_t nrhs,
                                     int32_t variant);
 
+/* ---------------------------------------------------------------- molecular dynamics
+ * The update of Sec. 2.1 (Phi algorithm): momenta conjugate to the links,
+ * Hamiltonian sum Tr(H^2) + S_g + S_f, a symmetric symplectic integrator and a
+ * Metropolis test.
+ *
+ * Momenta: device double [8][4][2][V/2] = omega^a of link (mu, parity, eo),
+ * H_mu(n) = sum_a omega^a T^a with T^a = lambda^a / 2 (Gell-Mann), so that
+ * sum Tr(H^2) = (1/2) sum omega^2 and omega^a ~ N(0, 1) is the heat bath.
+ * The caller draws them (and every other random number) and owns the array.
+ *
+ * Links evolve in place inside the gauge object: every storage it holds is
+ * rewritten by each link update.  All of these entry points need an FP64
+ * link storage (FP64-12, FP64-18 or hi/lo) and return RHMC_ERR_UNSUPPORTED
+ * without one.  Forces follow one convention: for U_mu(n) -> exp(i eps T)
+ * U_mu(n), dS/deps = i Tr(T F_mu(n)), and a kick of size eps does
+ * omega^a -= eps * i Tr(T^a F) (the flow that conserves the Hamiltonian with
+ * dU/dtau = i H U). */
+
+/* Plaquette (Wilson) action of Sec. 2,
+ *   S_g = beta sum_n sum_{mu<nu} (1 - Re Tr P_{mu nu}(n) / 3),
+ *   P_{mu nu}(n) = U_mu(n) U_nu(n+mu) U_mu(n+nu)^dagger U_nu(n)^dagger,
+ * links periodic in every direction; FP64 sums in a fixed order.  S: host
+ * double.  Blocks until S is on the host. */
+rhmc_status rhmc_gauge_action(const rhmc_gauge* g, double beta, double* S, hipStream_t stream);
+
+/* Gauge-force kick: mom -= eps * (i Tr(T^a F_g)) with
+ *   F_g = -(beta/3) TA(U_mu(n) Sigma_mu(n)),
+ *   Sigma_mu(n) = sum_{nu != mu} U_nu(n+mu) U_mu(n+nu)^dagger U_nu(n)^dagger
+ *                              + U_nu(n+mu-nu)^dagger U_mu(n-nu)^dagger U_nu(n-nu),
+ * the derivative of S_g.  mom: device, layout above, updated in place.
+ * Asynchronous on `stream`. */
+rhmc_status rhmc_gauge_force_kick(const rhmc_gauge* g, double beta, double eps, double* mom,
+                                  hipStream_t stream);
+
+/* Pseudofermion-force kick: mom -= eps * (i Tr(T^a F)) with F the force of
+ * rhmc_pf_force for S = sum_r phi_r^dagger r(A) phi_r (same solves, params and
+ * stats).  phi: device complex128 [npf][3][V/2].  Blocks until done. */
+rhmc_status rhmc_pf_force_kick(const rhmc_gauge* g, double m, const rhmc_rational* rat,
+                               int32_t npf, const void* phi, double eps, double* mom,
+                               const rhmc_solver_params* params, rhmc_solver_stats* stats,
+                               hipStream_t stream);
+
+/* Link update U_mu(n) -> exp(i eps H_mu(n)) U_mu(n), followed by the FP64
+ * reunitarisation of Sec. 4.1 (rows 1-2 Gram-Schmidt orthonormalised, row 3
+ * the complex conjugate of their cross product), written to every storage of
+ * g.  The exponential is the power series of the matrix scaled to norm 1/2,
+ * squared back.  Asynchronous on `stream`. */
+rhmc_status rhmc_update_links(rhmc_gauge* g, double eps, const double* mom, hipStream_t stream);
+
+/* Kinetic term sum Tr(H^2) = (1/2) sum omega^2 (FP64, fixed order).  K: host
+ * double.  Blocks until K is on the host. */
+rhmc_status rhmc_kinetic(const rhmc_gauge* g, const double* mom, double* K, hipStream_t stream);
+
+/* The current FP64 links of g in the layout of rhmc_gauge_create: device
+ * complex128 [Lt][Lz][Ly][Lx][4][3][3] (caller-owned, overwritten; row 3
+ * rebuilt where only rows 1-2 are stored).  Asynchronous on `stream`. */
+rhmc_status rhmc_gauge_links(const rhmc_gauge* g, void* links, hipStream_t stream);
+
+typedef struct {
+    double beta;            /* gauge coupling of S_g */
+    double mass;            /* quark mass m */
+    double tau;             /* trajectory length (default 1) */
+    int32_t n_md;           /* fermion steps per trajectory (default 12) */
+    int32_t gauge_steps;    /* fermion step / gauge step, even >= 2 (default 10) */
+    double lambda;          /* 2MN parameter, 0 <= lambda <= 1/2 (default 0.1931833275037836) */
+    const rhmc_rational* force_rational;  /* r(x) of the fermion force (~x^{-1/4}) */
+    rhmc_solver_params solver;            /* solves of the force (r_md, precision mode) */
+} rhmc_md_params;
+
+typedef struct {
+    int32_t fermion_forces;   /* force evaluations (kicks merged where adjacent) */
+    int32_t gauge_forces;
+    int32_t link_updates;
+    int64_t cg_iterations;    /* shared Krylov iterations summed over the force solves */
+    double max_true_residual; /* worst certified residual of the force solves */
+    double time_ms;
+} rhmc_md_stats;
+
+/* Defaults: beta 5.264, mass 0.01335, tau 1, n_md 12, gauge_steps 10, the
+ * minimum-norm lambda, no rational, the solver defaults. */
+void rhmc_md_params_default(rhmc_md_params* p);
+
+/* Molecular dynamics over tau with the multi-step second-order minimum-norm
+ * (2MN) scheme (Sec. 2.1).  One 2MN step of size h for a kick P and a drift Q:
+ *   P(lambda h) Q(h/2) P((1 - 2 lambda) h) Q(h/2) P(lambda h).
+ * The outer scheme (step delta = tau / n_md) kicks with the pseudofermion
+ * force; each of its two drifts Q(delta/2) is made of gauge_steps/2 inner 2MN
+ * steps of size delta / gauge_steps that kick with the gauge force and update
+ * the links, so a trajectory makes n_md * gauge_steps gauge steps.  Kicks
+ * between two link updates act on the same links and are summed into one
+ * evaluation per force.  phi: device complex128 [npf][3][V/2]; mom: device
+ * momenta (layout above), updated in place; links of g updated in place.
+ * Blocks until done.  A force solve that misses its tolerance makes the call
+ * return RHMC_ERR_NOT_CONVERGED after finishing the trajectory. */
+rhmc_status rhmc_md_integrate(rhmc_gauge* g, const rhmc_md_params* params, int32_t npf,
+                              const void* phi, double* mom, rhmc_md_stats* stats,
+                              hipStream_t stream);
+
+typedef struct {
+    rhmc_md_params md;
+    const rhmc_rational* heatbath_rational;  /* phi = r_hb(A) R (~x^{+1/8}) */
+    const rhmc_rational* action_rational;    /* S_f = sum phi^dagger r_act(A) phi (~x^{-1/4}) */
+    rhmc_solver_params metropolis_solver;    /* heat-bath and action solves (r_metro) */
+} rhmc_hmc_params;
+
+typedef struct {
+    double kinetic[2];       /* before / after the molecular dynamics */
+    double gauge_action[2];
+    double pf_action[2];     /* summed over pseudofermions */
+    double dH;               /* H(after) - H(before), summed part by part */
+    int32_t accepted;
+    rhmc_md_stats md;
+    double time_ms;
+} rhmc_trajectory_stats;
+
+/* One trajectory of the Phi algorithm (Sec. 2.1): phi = r_hb(A) R, H before,
+ * rhmc_md_integrate, H after, and the Metropolis test: accepted iff
+ * u < exp(-dH).  On rejection the links of g are restored to their values at
+ * the start; mom holds the final momenta either way.  R: device complex128
+ * [npf][3][V/2], complex Gaussian (parts N(0, 1/2)); mom: device momenta drawn
+ * N(0, 1) by the caller; u in [0, 1).  Blocks until done; stats required. */
+rhmc_status rhmc_trajectory(rhmc_gauge* g, const rhmc_hmc_params* params, int32_t npf,
+                            const void* R, double* mom, double u, rhmc_trajectory_stats* stats,
+                            hipStream_t stream);
+
 const char* rhmc_status_string(rhmc_status s);
 const char* rhmc_last_error(void);
 

@@ -9,6 +9,8 @@
 #include <vector>
 
 #include "common.h"
+#include "gauge.h"
+#include "md.h"
 #include "solver.h"
 
 namespace rhmc {
@@ -238,6 +240,7 @@ void rhmc_gauge_destroy(rhmc_gauge* g) {
     if (!g) return;
     hipSetDevice(g->device);
     workspace_destroy(g->ws);
+    md_destroy(g->md);
     hipFree(g->u64);
     hipFree(g->u64c);
     hipFree(g->u32);
@@ -394,7 +397,7 @@ rhmc_status rhmc_pf_force(const rhmc_gauge* gc, double m, const rhmc_rational* r
         stats->max_true_residual = 0;
     }
     return pf_force(g, m, rat, nrhs, reinterpret_cast<const double2*>(phi),
-                    reinterpret_cast<double2*>(force), prm, stats, stream);
+                    reinterpret_cast<double2*>(force), nullptr, 0.0, prm, stats, stream);
 }
 
 rhmc_status rhmc_tune_dslash(rhmc_gauge* g, rhmc_prec prec, int32_t nrhs, const void* in,
@@ -426,6 +429,145 @@ rhmc_status rhmc_set_dslash_variant(rhmc_gauge* g, rhmc_prec prec, int32_t nrhs,
     g->hop_variant[prec][cls] = variant;
     g->hop_tuned[prec][cls] = 1;
     return RHMC_OK;
+}
+
+// ------------------------------------------------------------------ molecular dynamics
+static rhmc_status need_fp64_links(const rhmc_gauge* g) {
+    if (!has_fp64_op(g)) {
+        set_error("molecular dynamics needs an FP64 link storage (FP64-12, FP64-18 or hi/lo)");
+        return RHMC_ERR_UNSUPPORTED;
+    }
+    return RHMC_OK;
+}
+
+static rhmc_status check_rational(double m, const rhmc_rational* rat) {
+    if (!rat) return invalid("null rational");
+    if (!std::isfinite(m) || !std::isfinite(rat->alpha0)) return invalid("non-finite coefficient");
+    if (rat->npole < 1 || !rat->alpha) return invalid("rational needs npole >= 1 and alpha");
+    for (int i = 0; i < rat->npole; ++i)
+        if (!std::isfinite(rat->alpha[i])) return invalid("non-finite coefficient");
+    return check_shifts(m, rat->npole, rat->beta);
+}
+
+static rhmc_status check_md(const rhmc_gauge* g, const rhmc_md_params* p, rhmc_md_params* out) {
+    if (!p) return invalid("null md params");
+    *out = *p;
+    if (!std::isfinite(p->beta) || !std::isfinite(p->mass)) return invalid("beta and mass must be finite");
+    if (!std::isfinite(p->tau)) return invalid("tau must be finite");
+    if (p->n_md < 1 || p->n_md > 1000000) return invalid("n_md must be in 1..1e6");
+    if (p->gauge_steps < 2 || p->gauge_steps % 2 || p->gauge_steps > 100000)
+        return invalid("gauge_steps must be even and in 2..1e5");
+    if (!(p->lambda >= 0.0 && p->lambda <= 0.5)) return invalid("lambda must be in [0, 1/2]");
+    RHMC_TRY(check_rational(p->mass, p->force_rational));
+    return check_params(&p->solver, g, &out->solver);
+}
+
+rhmc_status rhmc_gauge_action(const rhmc_gauge* gc, double beta, double* S, hipStream_t stream) {
+    rhmc_gauge* g = const_cast<rhmc_gauge*>(gc);
+    if (!g || !S) return invalid("null argument");
+    if (!std::isfinite(beta)) return invalid("beta must be finite");
+    RHMC_TRY(need_fp64_links(g));
+    RHMC_TRY(use_device(g->device));
+    return gauge_action(g, beta, S, stream);
+}
+
+rhmc_status rhmc_gauge_force_kick(const rhmc_gauge* g, double beta, double eps, double* mom,
+                                  hipStream_t stream) {
+    if (!g || !mom) return invalid("null argument");
+    if (!std::isfinite(beta) || !std::isfinite(eps)) return invalid("beta and eps must be finite");
+    RHMC_TRY(need_fp64_links(g));
+    RHMC_TRY(use_device(g->device));
+    RHMC_HIP_TRY(launch_gauge_force_mom(g, beta, eps, mom, stream));
+    return RHMC_OK;
+}
+
+rhmc_status rhmc_pf_force_kick(const rhmc_gauge* gc, double m, const rhmc_rational* rat,
+                               int32_t npf, const void* phi, double eps, double* mom,
+                               const rhmc_solver_params* params, rhmc_solver_stats* stats,
+                               hipStream_t stream) {
+    rhmc_gauge* g = const_cast<rhmc_gauge*>(gc);
+    if (!g || !phi || !mom) return invalid("null argument");
+    if (npf < 1 || npf > 64) return invalid("npf must be in 1..64");
+    if (!std::isfinite(eps)) return invalid("eps must be finite");
+    RHMC_TRY(need_fp64_links(g));
+    RHMC_TRY(check_rational(m, rat));
+    rhmc_solver_params prm;
+    RHMC_TRY(check_params(params, g, &prm));
+    RHMC_TRY(use_device(g->device));
+    if (stats) {
+        stats->total_iterations = 0;
+        stats->reliable_updates = 0;
+        stats->refine_rounds = 0;
+        stats->time_ms = 0;
+        stats->max_true_residual = 0;
+    }
+    return pf_force(g, m, rat, npf, reinterpret_cast<const double2*>(phi), nullptr, mom, eps, prm,
+                    stats, stream);
+}
+
+rhmc_status rhmc_update_links(rhmc_gauge* g, double eps, const double* mom, hipStream_t stream) {
+    if (!g || !mom) return invalid("null argument");
+    if (!std::isfinite(eps)) return invalid("eps must be finite");
+    RHMC_TRY(need_fp64_links(g));
+    RHMC_TRY(use_device(g->device));
+    RHMC_HIP_TRY(launch_update_links(g, eps, mom, stream));
+    return RHMC_OK;
+}
+
+rhmc_status rhmc_kinetic(const rhmc_gauge* gc, const double* mom, double* K, hipStream_t stream) {
+    rhmc_gauge* g = const_cast<rhmc_gauge*>(gc);
+    if (!g || !mom || !K) return invalid("null argument");
+    RHMC_TRY(use_device(g->device));
+    return kinetic(g, mom, K, stream);
+}
+
+rhmc_status rhmc_gauge_links(const rhmc_gauge* g, void* links, hipStream_t stream) {
+    if (!g || !links) return invalid("null argument");
+    RHMC_TRY(need_fp64_links(g));
+    RHMC_TRY(use_device(g->device));
+    RHMC_HIP_TRY(launch_get_links(g, reinterpret_cast<double2*>(links), stream));
+    return RHMC_OK;
+}
+
+void rhmc_md_params_default(rhmc_md_params* p) {
+    if (!p) return;
+    p->beta = 5.264;
+    p->mass = 0.01335;
+    p->tau = 1.0;
+    p->n_md = 12;
+    p->gauge_steps = 10;
+    p->lambda = 0.1931833275037836;
+    p->force_rational = nullptr;
+    rhmc_solver_params_default(&p->solver);
+}
+
+rhmc_status rhmc_md_integrate(rhmc_gauge* g, const rhmc_md_params* params, int32_t npf,
+                              const void* phi, double* mom, rhmc_md_stats* stats,
+                              hipStream_t stream) {
+    if (!g || !phi || !mom) return invalid("null argument");
+    if (npf < 1 || npf > 64) return invalid("npf must be in 1..64");
+    RHMC_TRY(need_fp64_links(g));
+    rhmc_md_params p;
+    RHMC_TRY(check_md(g, params, &p));
+    RHMC_TRY(use_device(g->device));
+    return md_integrate(g, p, npf, reinterpret_cast<const double2*>(phi), mom, stats, stream);
+}
+
+rhmc_status rhmc_trajectory(rhmc_gauge* g, const rhmc_hmc_params* params, int32_t npf,
+                            const void* R, double* mom, double u, rhmc_trajectory_stats* stats,
+                            hipStream_t stream) {
+    if (!g || !params || !R || !mom || !stats) return invalid("null argument");
+    if (npf < 1 || npf > 64) return invalid("npf must be in 1..64");
+    if (!(u >= 0.0 && u <= 1.0)) return invalid("u must be in [0, 1]");
+    RHMC_TRY(need_fp64_links(g));
+    rhmc_hmc_params p = *params;
+    RHMC_TRY(check_md(g, &params->md, &p.md));
+    RHMC_TRY(check_rational(p.md.mass, p.heatbath_rational));
+    RHMC_TRY(check_rational(p.md.mass, p.action_rational));
+    RHMC_TRY(check_params(&params->metropolis_solver, g, &p.metropolis_solver));
+    RHMC_TRY(use_device(g->device));
+    *stats = rhmc_trajectory_stats{};
+    return trajectory(g, p, npf, reinterpret_cast<const double2*>(R), mom, u, stats, stream);
 }
 
 const char* rhmc_status_string(rhmc_status s) {

@@ -76,4 +76,13 @@ struct DotArgs {
 };
 hipError_t launch_dot(const DotArgs& a, int nsys, hipStream_t s);
 
+// Re <a_j, b_j> of FP32 vectors (FP64 sums), same partial layout as DotArgs
+struct Dot32Args {
+    size_t n;
+    const float2* a[kMaxSys];
+    const float2* b[kMaxSys];
+    double* partial;
+};
+hipError_t launch_dot32(const Dot32Args& a, int nsys, hipStream_t s);
+
 }  // namespace rhmc

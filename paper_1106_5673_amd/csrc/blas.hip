@@ -109,12 +109,13 @@ __global__ __launch_bounds__(kBlock) void k_rupdate(VecArgs<VT> a) {
     const bool live = !st->sys[j].done;
     double r2 = 0.0;
     if (live) {
-        // alpha = rr / <p, A p>; every block adds the A-kernel partials itself,
-        // in the same fixed order, so all blocks use the same alpha bits
+        // alpha = rr / <p, A p> (<r, p> / <p, A p> right after a residual
+        // replacement); every block adds the A-kernel partials itself, in the
+        // same fixed order, so all blocks use the same alpha bits
         block_sum_rows(a.part2 + (size_t)j * a.nblk2, 1, a.nblk2, sums);
         const double pap = sums[0];
         if (blockIdx.x == 0 && threadIdx.x == 0) st->sys[j].pap = pap;
-        const double alpha = st->sys[j].rr[a.q & 1] / pap;
+        const double alpha = step_alpha_num(st->sys[j], a.q) / pap;
         const VT* __restrict__ x = a.x[j];
         const VT* __restrict__ y = a.y[j];
         VT* __restrict__ z = a.z[j];
@@ -354,6 +355,22 @@ __global__ __launch_bounds__(kBlock) void k_dot(DotArgs a) {
     reduce_store(d, 0.0, j, -1, a.partial);
 }
 
+// Re <a_j, b_j> of FP32 vectors with FP64 accumulation (the alpha numerator
+// after a residual replacement).
+__global__ __launch_bounds__(kBlock) void k_dot32(Dot32Args a) {
+    const int j = blockIdx.y;
+    double d = 0.0;
+    for (size_t i = ((size_t)blockIdx.x * kBlock + threadIdx.x) * 2; i < a.n;
+         i += (size_t)gridDim.x * kBlock * 2) {
+        Pair<float2> u, v;
+        u.load(a.a[j], i);
+        v.load(a.b[j], i);
+        for (int k = 0; k < 2; ++k)
+            d += (double)u.re[k] * (double)v.re[k] + (double)u.im[k] * (double)v.im[k];
+    }
+    reduce_store(d, 0.0, j, -1, a.partial);
+}
+
 // ------------------------------------------------------------------ axpy
 // y += x (FP64), for folding a correction into a solution
 __global__ __launch_bounds__(kBlock) void k_add(AddArgs a) {
@@ -435,6 +452,10 @@ hipError_t launch_combine(const CombineArgs& a, int nsys, hipStream_t s) {
 }
 hipError_t launch_dot(const DotArgs& a, int nsys, hipStream_t s) {
     hipLaunchKernelGGL(k_dot, red_grid(a.n, nsys), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+hipError_t launch_dot32(const Dot32Args& a, int nsys, hipStream_t s) {
+    hipLaunchKernelGGL(k_dot32, red_grid(a.n, nsys), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 hipError_t launch_add(const AddArgs& a, int nsys, hipStream_t s) {

@@ -150,6 +150,7 @@ struct rhmc_lattice {
 namespace rhmc {
 struct Workspace;  // solver workspace, defined in solver.hip
 void workspace_destroy(Workspace* w);
+void md_destroy(void* md);  // md.hip
 }  // namespace rhmc
 
 struct rhmc_gauge {
@@ -166,6 +167,7 @@ struct rhmc_gauge {
     rhmc::Workspace* ws;     // solver workspace (lazily created)
     int hop_variant[2][4];   // launch variant per [RHMC_PREC_*][rhs class]
     int hop_tuned[2][4];     // 1 once the autotuner has timed that case
+    void* md;                // molecular-dynamics buffers (md.hip, lazily created)
 };
 
 namespace rhmc {

@@ -8,7 +8,7 @@
 // time-boundary sign of the hop n -> n+mu, TA the traceless anti-Hermitian part.
 #include "force.h"
 
-#include "dslash_kernel.h"
+#include "algebra.h"
 
 namespace rhmc {
 
@@ -74,6 +74,24 @@ __global__ __launch_bounds__(kBlock) void k_force(const LT* __restrict__ links, 
             xr[i][j] = sr;
             xi[i][j] = si;
         }
+    if (a.mom) {
+        // momentum kick: the coefficients of F = TA(X) in the algebra
+        Mat3 Xm;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                Xm.re[i][j] = xr[i][j];
+                Xm.im[i][j] = xi[i][j];
+            }
+        double cf[8];
+        algebra_coef(Xm, 1.0, cf);
+        const int nl = 8 * g.Vh;
+        const int k = (2 * mu + par) * g.Vh + eo;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) a.mom[(size_t)i * nl + k] -= a.eps * cf[i];
+        return;
+    }
     // F = (X - X^dagger)/2 - Tr(X - X^dagger)/6
     const double tr = (xi[0][0] + xi[1][1] + xi[2][2]) / 3.0;   // imaginary part of the trace / 3
     const int lex = x + g.Lx * (y + g.Ly * (z + g.Lz * t));

@@ -20,9 +20,10 @@ rhmc_status pf_action(rhmc_gauge* g, double m, const rhmc_rational* rat, int nrh
                       const double2* phi, double* S, const rhmc_solver_params& prm,
                       rhmc_solver_stats* stats, hipStream_t s);
 
-// force[lex][mu] = TA(U M) of S = sum_r phi[r]^dagger r(A) phi[r] (force.hip)
+// force[lex][mu] = TA(U M) of S = sum_r phi[r]^dagger r(A) phi[r] (force.hip); with
+// mom non-null, mom^a -= eps * i Tr(T^a F) instead and force is not written
 rhmc_status pf_force(rhmc_gauge* g, double m, const rhmc_rational* rat, int nrhs,
-                     const double2* phi, double2* force, const rhmc_solver_params& prm,
-                     rhmc_solver_stats* stats, hipStream_t s);
+                     const double2* phi, double2* force, double* mom, double eps,
+                     const rhmc_solver_params& prm, rhmc_solver_stats* stats, hipStream_t s);
 
 }  // namespace rhmc

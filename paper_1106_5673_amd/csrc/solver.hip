@@ -298,6 +298,18 @@ static rhmc_status enqueue_block(const rhmc_gauge* g, Workspace* w, const Proble
         RHMC_HIP_TRY(launch_fp64_op(g, d64, kModeD, s));
         RHMC_HIP_TRY(launch_fp64_op(g, r64, kModeResid, s));
         RHMC_HIP_TRY(launch_finalize(kFinReliable, w->st, w->partial, dgrid, ns, nullptr, s));
+        if (f32) {
+            // <r, p> with the replaced r: alpha of the next step (state.h)
+            Dot32Args dp{};
+            dp.n = n;
+            dp.partial = w->partial + kMaxSys * w->part_stride;
+            for (int j = 0; j < ns; ++j) {
+                dp.a[j] = reinterpret_cast<const float2*>(vec<VT>(w->ring, n, j));
+                dp.b[j] = reinterpret_cast<const float2*>(vec<VT>(w->p, n, j));
+            }
+            RHMC_HIP_TRY(launch_dot32(dp, ns, s));
+            RHMC_HIP_TRY(launch_finalize(kFinReliableDot, w->st, dp.partial, vgrid, ns, nullptr, s));
+        }
     }
     return RHMC_OK;
 }
@@ -746,8 +758,8 @@ rhmc_status pf_action(rhmc_gauge* g, double m, const rhmc_rational* rat, int nrh
 }
 
 rhmc_status pf_force(rhmc_gauge* g, double m, const rhmc_rational* rat, int nrhs,
-                     const double2* phi, double2* force, const rhmc_solver_params& prm,
-                     rhmc_solver_stats* stats, hipStream_t s) {
+                     const double2* phi, double2* force, double* mom, double eps,
+                     const rhmc_solver_params& prm, rhmc_solver_stats* stats, hipStream_t s) {
     const size_t n = (size_t)3 * g->lat.Vh;
     const int np = rat->npole;
     const int grp = std::min(nrhs, kMaxSys);
@@ -802,6 +814,8 @@ rhmc_status pf_force(rhmc_gauge* g, double m, const rhmc_rational* rat, int nrhs
         for (int i = 0; i < np; ++i) f.alpha[i] = rat->alpha[i];
         f.out = force;
         f.accumulate = r0 > 0;
+        f.mom = mom;
+        f.eps = eps;
         RHMC_HIP_TRY(launch_force(g, f, s));
     }
     RHMC_HIP_TRY(hipStreamSynchronize(s));

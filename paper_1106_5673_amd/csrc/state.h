@@ -22,7 +22,19 @@ struct SysScalars {
     int iters;          // iterations completed by this system
     int base;           // index of the shift with offset 0
     int blk_steps;      // iterations this system completed in the current block
+    // After a residual replacement r is no longer the residual p was built
+    // from, so <r, p> != <r, r>: the first step then takes the exact line
+    // search alpha = <r, p> / <p, A p> (replaced = 1, alpha_num = <r, p>).
+    // Any alpha keeps the three-term residual recurrence, so the shifted
+    // systems stay collinear with the base one.
+    double alpha_num;
+    int replaced;
 };
+
+// Numerator of alpha for step q of the current block.
+__host__ __device__ inline double step_alpha_num(const SysScalars& s, int q) {
+    return s.replaced ? s.alpha_num : s.rr[q & 1];
+}
 
 // Shifted solutions are not touched every iteration.  Inside a block of
 // iterations starting at k0 the recurrences of shift i,
@@ -69,7 +81,8 @@ enum FinalizeKind {
     kFinNone = 0,
     kFinInit = 1,      // after the start kernel: ||b||, rr
     kFinReliable = 4,  // after r = b - A x in FP64: rr
-    kFinNorms = 5      // plain per-rhs sums into an output array
+    kFinNorms = 5,     // plain per-rhs sums into an output array
+    kFinReliableDot = 6  // after the replacement: <r, p>, the next step's alpha numerator
 };
 
 #if defined(__HIPCC__)
@@ -165,6 +178,13 @@ __device__ inline void solver_finalize(int kind, void* vstate, const double* par
         }
         return;
     }
+    if (kind == kFinReliableDot) {
+        if (tid < nsys && !st->sys[tid].done) {
+            st->sys[tid].alpha_num = sums[tid];
+            st->sys[tid].replaced = 1;
+        }
+        return;
+    }
     // kFinReliable: the residual was replaced at a block boundary (slot 0)
     if (tid < nsys && !st->sys[tid].done) st->sys[tid].rr[0] = sums[tid];
     if (tid == 0) st->reliable_count += 1;
@@ -195,7 +215,7 @@ __device__ inline void iteration_update(SolverState* st, const double* partR, in
         ShiftScalars& h = st->sh[j][i];
         if (s.done || !h.active) continue;
         const double rr = s.rr[cur];
-        const double alpha = rr / pap_s[j];
+        const double alpha = step_alpha_num(s, q_step) / pap_s[j];
         const double beta = rrn_s[j] / rr;
         const double zeta = h.zeta, zeta_prev = h.zeta_prev;
         const double zn = zeta * zeta_prev * s.alpha_prev /
@@ -225,8 +245,9 @@ __device__ inline void iteration_update(SolverState* st, const double* partR, in
         SysScalars& s = st->sys[tid];
         if (!s.done) {
             const double rr = s.rr[cur];
-            s.alpha_prev = rr / pap_s[tid];
+            s.alpha_prev = step_alpha_num(s, q_step) / pap_s[tid];
             s.beta_prev = rrn_s[tid] / rr;
+            s.replaced = 0;
             s.rr[nxt] = rrn_s[tid];
             s.iters += 1;
             s.blk_steps += 1;

@@ -40,7 +40,9 @@ EXPORTED = (
     "rhmc_debug_neighbors", "rhmc_gauge_create", "rhmc_gauge_destroy", "rhmc_dslash_eo",
     "rhmc_apply_mdagm", "rhmc_multishift_cg", "rhmc_rational_apply", "rhmc_tune_dslash",
     "rhmc_dslash_variant", "rhmc_set_dslash_variant", "rhmc_pf_phi", "rhmc_pf_action",
-    "rhmc_pf_force",
+    "rhmc_pf_force", "rhmc_gauge_action", "rhmc_gauge_force_kick", "rhmc_pf_force_kick",
+    "rhmc_update_links", "rhmc_kinetic", "rhmc_gauge_links", "rhmc_md_params_default",
+    "rhmc_md_integrate", "rhmc_trajectory",
     "rhmc_status_string", "rhmc_last_error",
 )
 
@@ -67,6 +69,30 @@ class rhmc_solver_stats(C.Structure):
 class rhmc_rational(C.Structure):
     _fields_ = [("alpha0", C.c_double), ("npole", C.c_int32),
                 ("alpha", C.POINTER(C.c_double)), ("beta", C.POINTER(C.c_double))]
+
+
+class rhmc_md_params(C.Structure):
+    _fields_ = [("beta", C.c_double), ("mass", C.c_double), ("tau", C.c_double),
+                ("n_md", C.c_int32), ("gauge_steps", C.c_int32), ("lambda_", C.c_double),
+                ("force_rational", C.POINTER(rhmc_rational)), ("solver", rhmc_solver_params)]
+
+
+class rhmc_md_stats(C.Structure):
+    _fields_ = [("fermion_forces", C.c_int32), ("gauge_forces", C.c_int32),
+                ("link_updates", C.c_int32), ("cg_iterations", C.c_int64),
+                ("max_true_residual", C.c_double), ("time_ms", C.c_double)]
+
+
+class rhmc_hmc_params(C.Structure):
+    _fields_ = [("md", rhmc_md_params), ("heatbath_rational", C.POINTER(rhmc_rational)),
+                ("action_rational", C.POINTER(rhmc_rational)),
+                ("metropolis_solver", rhmc_solver_params)]
+
+
+class rhmc_trajectory_stats(C.Structure):
+    _fields_ = [("kinetic", C.c_double * 2), ("gauge_action", C.c_double * 2),
+                ("pf_action", C.c_double * 2), ("dH", C.c_double), ("accepted", C.c_int32),
+                ("md", rhmc_md_stats), ("time_ms", C.c_double)]
 
 
 _lib = None
@@ -102,6 +128,18 @@ def load():
                                  C.POINTER(rhmc_solver_params), C.POINTER(rhmc_solver_stats), vp]),
         "rhmc_dslash_variant": (i32, [vp, i32, i32, C.POINTER(C.c_int32)]),
         "rhmc_set_dslash_variant": (i32, [vp, i32, i32, i32]),
+        "rhmc_gauge_action": (i32, [vp, f64, C.POINTER(C.c_double), vp]),
+        "rhmc_gauge_force_kick": (i32, [vp, f64, f64, vp, vp]),
+        "rhmc_pf_force_kick": (i32, [vp, f64, C.POINTER(rhmc_rational), i32, vp, f64, vp,
+                                     C.POINTER(rhmc_solver_params), C.POINTER(rhmc_solver_stats), vp]),
+        "rhmc_update_links": (i32, [vp, f64, vp, vp]),
+        "rhmc_kinetic": (i32, [vp, vp, C.POINTER(C.c_double), vp]),
+        "rhmc_gauge_links": (i32, [vp, vp, vp]),
+        "rhmc_md_params_default": (None, [C.POINTER(rhmc_md_params)]),
+        "rhmc_md_integrate": (i32, [vp, C.POINTER(rhmc_md_params), i32, vp, vp,
+                                    C.POINTER(rhmc_md_stats), vp]),
+        "rhmc_trajectory": (i32, [vp, C.POINTER(rhmc_hmc_params), i32, vp, vp, f64,
+                                  C.POINTER(rhmc_trajectory_stats), vp]),
         "rhmc_status_string": (C.c_char_p, [i32]),
         "rhmc_last_error": (C.c_char_p, []),
     }
@@ -389,6 +427,164 @@ def rhmc_dslash_variant(g: Gauge, prec: int, nrhs: int) -> int:
 def rhmc_set_dslash_variant(g: Gauge, prec: int, nrhs: int, variant: int):
     """Pin the hopping kernel's launch variant for (prec, nrhs)."""
     _check(load().rhmc_set_dslash_variant(g.handle, int(prec), int(nrhs), int(variant)))
+
+
+# ------------------------------------------------------------------ molecular dynamics
+class Rational:
+    """An rhmc_rational together with the host arrays it points into."""
+
+    def __init__(self, alpha0, alpha, beta):
+        self.alpha = np.ascontiguousarray(alpha, dtype=np.float64)
+        self.beta = np.ascontiguousarray(beta, dtype=np.float64)
+        if self.alpha.shape != self.beta.shape or self.alpha.ndim != 1:
+            raise ValueError("alpha and beta must be 1-D of equal length")
+        self.c = rhmc_rational(float(alpha0), self.alpha.size,
+                               self.alpha.ctypes.data_as(C.POINTER(C.c_double)),
+                               self.beta.ctypes.data_as(C.POINTER(C.c_double)))
+
+    @classmethod
+    def of(cls, r):
+        """From any object with alpha0, alpha, beta attributes."""
+        return r if isinstance(r, cls) else cls(r.alpha0, r.alpha, r.beta)
+
+
+def _mom_shape(g: Gauge):
+    return (8, 4, 2, g.lattice.Vh)
+
+
+def rhmc_gauge_action(g: Gauge, beta: float, stream=None) -> float:
+    S = C.c_double()
+    _check(load().rhmc_gauge_action(g.handle, float(beta), C.byref(S), _stream(stream)))
+    return S.value
+
+
+def rhmc_gauge_force_kick(g: Gauge, beta: float, eps: float, mom, stream=None):
+    """mom -= eps * (algebra coefficients of the plaquette-action force)."""
+    import torch
+
+    _check(load().rhmc_gauge_force_kick(g.handle, float(beta), float(eps),
+                                        _ptr(mom, torch.float64, _mom_shape(g), "mom"),
+                                        _stream(stream)))
+
+
+def rhmc_pf_force_kick(g: Gauge, m: float, rational, phi, eps: float, mom, params=None,
+                       stream=None, allow_not_converged=False):
+    """mom -= eps * (algebra coefficients of the pseudofermion force); returns statistics."""
+    import torch
+
+    rat = Rational.of(rational)
+    npf = int(phi.shape[0])
+    pp = _ptr(phi, torch.complex128, (npf, 3, g.lattice.Vh), "phi")
+    pm = _ptr(mom, torch.float64, _mom_shape(g), "mom")
+    st = _Stats(npf, rat.alpha.size)
+    prm = params if params is not None else rhmc_solver_params_default()
+    status = load().rhmc_pf_force_kick(g.handle, float(m), C.byref(rat.c), npf, pp, float(eps), pm,
+                                       C.byref(prm), C.byref(st.c), _stream(stream))
+    if not (allow_not_converged and status == RHMC_ERR_NOT_CONVERGED):
+        _check(status)
+    return st.as_dict(npf, rat.alpha.size, status)
+
+
+def rhmc_update_links(g: Gauge, eps: float, mom, stream=None):
+    """U -> reunitarised exp(i eps H) U in every link storage of g."""
+    import torch
+
+    _check(load().rhmc_update_links(g.handle, float(eps),
+                                    _ptr(mom, torch.float64, _mom_shape(g), "mom"), _stream(stream)))
+
+
+def rhmc_kinetic(g: Gauge, mom, stream=None) -> float:
+    import torch
+
+    K = C.c_double()
+    _check(load().rhmc_kinetic(g.handle, _ptr(mom, torch.float64, _mom_shape(g), "mom"),
+                               C.byref(K), _stream(stream)))
+    return K.value
+
+
+def rhmc_gauge_links(g: Gauge, out, stream=None):
+    """out (device complex128 [Lt][Lz][Ly][Lx][4][3][3]) = the current FP64 links."""
+    import torch
+
+    Lx, Ly, Lz, Lt = g.lattice.L
+    _check(load().rhmc_gauge_links(g.handle, _ptr(out, torch.complex128, (Lt, Lz, Ly, Lx, 4, 3, 3),
+                                                  "links"), _stream(stream)))
+
+
+class MDParams:
+    """rhmc_md_params with its rational kept alive; keyword names as in the C
+    struct (lambda_ for lambda), force_rational any object with alpha0, alpha,
+    beta, solver an rhmc_solver_params."""
+
+    def __init__(self, force_rational, **kw):
+        self.c = rhmc_md_params()
+        load().rhmc_md_params_default(C.byref(self.c))
+        self.rational = Rational.of(force_rational)
+        self.c.force_rational = C.pointer(self.rational.c)
+        for k, v in kw.items():
+            if k == "lambda":
+                k = "lambda_"
+            if not hasattr(self.c, k):
+                raise KeyError(k)
+            setattr(self.c, k, v)
+
+
+def _md_stats_dict(s: rhmc_md_stats):
+    return dict(fermion_forces=s.fermion_forces, gauge_forces=s.gauge_forces,
+                link_updates=s.link_updates, cg_iterations=int(s.cg_iterations),
+                max_true_residual=s.max_true_residual, time_ms=s.time_ms)
+
+
+def rhmc_md_integrate(g: Gauge, params: MDParams, phi, mom, stream=None,
+                      allow_not_converged=False):
+    """Multi-step 2MN molecular dynamics over params.tau; links and mom in place."""
+    import torch
+
+    npf = int(phi.shape[0])
+    pp = _ptr(phi, torch.complex128, (npf, 3, g.lattice.Vh), "phi")
+    pm = _ptr(mom, torch.float64, _mom_shape(g), "mom")
+    st = rhmc_md_stats()
+    status = load().rhmc_md_integrate(g.handle, C.byref(params.c), npf, pp, pm, C.byref(st),
+                                      _stream(stream))
+    if not (allow_not_converged and status == RHMC_ERR_NOT_CONVERGED):
+        _check(status)
+    d = _md_stats_dict(st)
+    d["status"] = status
+    return d
+
+
+class HMCParams:
+    """rhmc_hmc_params: MD parameters, the heat-bath and action rationals and
+    the solver parameters of the Metropolis solves."""
+
+    def __init__(self, md: MDParams, heatbath_rational, action_rational, metropolis_solver=None):
+        self.md = md
+        self.hb = Rational.of(heatbath_rational)
+        self.act = Rational.of(action_rational)
+        self.c = rhmc_hmc_params()
+        self.c.md = md.c
+        self.c.heatbath_rational = C.pointer(self.hb.c)
+        self.c.action_rational = C.pointer(self.act.c)
+        self.c.metropolis_solver = (metropolis_solver if metropolis_solver is not None
+                                    else rhmc_solver_params_default())
+
+
+def rhmc_trajectory(g: Gauge, params: HMCParams, R, mom, u: float, stream=None,
+                    allow_not_converged=False):
+    """One trajectory (heat bath, MD, Metropolis); returns its statistics."""
+    import torch
+
+    npf = int(R.shape[0])
+    pr = _ptr(R, torch.complex128, (npf, 3, g.lattice.Vh), "R")
+    pm = _ptr(mom, torch.float64, _mom_shape(g), "mom")
+    st = rhmc_trajectory_stats()
+    status = load().rhmc_trajectory(g.handle, C.byref(params.c), npf, pr, pm, float(u),
+                                    C.byref(st), _stream(stream))
+    if not (allow_not_converged and status == RHMC_ERR_NOT_CONVERGED):
+        _check(status)
+    return dict(status=status, kinetic=tuple(st.kinetic), gauge_action=tuple(st.gauge_action),
+                pf_action=tuple(st.pf_action), dH=st.dH, accepted=bool(st.accepted),
+                md=_md_stats_dict(st.md), time_ms=st.time_ms)
 
 
 def rhmc_status_string(status: int) -> str:

@@ -11,6 +11,7 @@ from .fields import (  # noqa: F401
     CONFIGS,
     even_volume,
     gauge_field,
+    momenta,
     random_su3,
     source,
     unit_gauge,

@@ -183,6 +183,15 @@ def source(L, seed: int, nrhs: int = 1) -> np.ndarray:
     return out
 
 
+def momenta(L, seed: int) -> np.ndarray:
+    """Gaussian momenta omega^a ~ N(0, 1) (the heat bath of Sec. 2.1), float64
+    [8][4][2][V/2]: algebra component a, direction mu, parity, eo; drawn in
+    that order."""
+    _check_dims(L)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.standard_normal((8, 4, 2, even_volume(L)))
+
+
 def config_inputs(cfg: int):
     """(U, b, params) for one of the five named workloads."""
     c = CONFIGS[cfg]

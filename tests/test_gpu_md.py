@@ -1,0 +1,332 @@
+"""GPU parity of the molecular-dynamics entry points (Sec. 2.1, 4.1, 4.4).
+
+Against the oracle, element by element, on lattices of one to several
+256-site blocks with ragged tails, for every FP64 link storage:
+
+* rhmc_gauge_links returns the stored links; rhmc_kinetic is (1/2) sum omega^2;
+* rhmc_gauge_action equals the plaquette action (1e-13 relative);
+* rhmc_gauge_force_kick equals omega - eps * c(F_g) (1e-11 absolute);
+* rhmc_update_links equals reunitarize(exp(i eps H) U) for step sizes that
+  need zero to several squarings (1e-13), keeps the links in SU(3), and
+  rewrites the FP32 copy the mixed operator reads;
+* rhmc_pf_force_kick equals omega - eps * c(F) of the oracle's dense force,
+  and the kick of rhmc_pf_force's own F;
+* rhmc_md_integrate and rhmc_trajectory against the oracle's multi-step 2MN
+  integrator and trajectory on 4^4 and 6x4x4x6 (FP64 and MIXED solves), with
+  the force, gauge-force and link-update counts of the merged kicks;
+* the Metropolis test restores the initial links bit for bit on rejection.
+
+Properties that hold at any size: reversibility (Delta C, Delta M of Sec. 4.4)
+and the second-order energy error at 16^3x4; at 48^3x12 gauge invariance of
+the action, gauge covariance of the force and sampled link updates against
+the oracle.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from fieldcache import workload_gauge
+from oracle import force, gauge, md
+from synth.make_rational import rational_for
+
+pytestmark = pytest.mark.gpu
+
+T = gauge.generators()
+
+
+@pytest.fixture(scope="module")
+def rh():
+    import torch
+
+    from paper_1106_5673_amd import rhmc
+
+    rhmc.load()
+    assert torch.cuda.is_available()
+    return rhmc
+
+
+def _dev(x):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
+
+
+def _gauss(rng, shape):
+    return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) * np.sqrt(0.5)
+
+
+def _flags(rh, storage):
+    return {"fp64_12": 0, "fp64_18": rh.RHMC_LINKS_FP64_18 | rh.RHMC_LINKS_FP32_12,
+            "hilo": rh.RHMC_LINKS_HILO_12}[storage]
+
+
+def _links(rh, g):
+    import torch
+
+    Lx, Ly, Lz, Lt = g.lattice.L
+    out = torch.empty((Lt, Lz, Ly, Lx, 4, 3, 3), dtype=torch.complex128, device="cuda:0")
+    rh.rhmc_gauge_links(g, out)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def _setup(rh, L, storage, seed, eps=0.5):
+    U = synth.gauge_field(L, eps, seed)
+    lat = rh.rhmc_lattice_create(L, -1)
+    g = rh.rhmc_gauge_create(lat, U, _flags(rh, storage))
+    return U, lat, g
+
+
+LATS = [(4, 4, 4, 4), (6, 4, 4, 6), (8, 6, 4, 10)]
+STORAGES = ["fp64_12", "fp64_18", "hilo"]
+# hi + lo carries ~48 bits of each entry: its results differ from exact FP64 at ~1e-14
+LINK_TOL = {"fp64_12": 1e-15, "fp64_18": 0.0, "hilo": 2e-14}
+
+
+@pytest.mark.parametrize("storage", STORAGES)
+@pytest.mark.parametrize("L", LATS)
+def test_links_action_kinetic(rh, L, storage):
+    U, lat, g = _setup(rh, L, storage, 7000 + sum(L))
+    got = _links(rh, g)
+    assert np.abs(got - U).max() <= LINK_TOL[storage] + 4e-16
+    beta = 5.3
+    S = rh.rhmc_gauge_action(g, beta)
+    want = gauge.gauge_action(U, beta)
+    assert abs(S - want) <= (5e-13 if storage == "hilo" else 1e-13) * abs(want)
+    w = synth.momenta(L, 7100)
+    K = rh.rhmc_kinetic(g, _dev(w))
+    assert abs(K - 0.5 * np.sum(w ** 2)) <= 1e-13 * K
+    g.close()
+
+
+@pytest.mark.parametrize("storage", STORAGES)
+@pytest.mark.parametrize("L", LATS)
+def test_gauge_force_kick(rh, L, storage):
+    U, lat, g = _setup(rh, L, storage, 7200 + sum(L), eps=0.7)
+    beta, eps = 5.3, 0.37
+    w = synth.momenta(L, 7300)
+    mom = _dev(w)
+    rh.rhmc_gauge_force_kick(g, beta, eps, mom)
+    full = gauge.mom_from_abi(w, L) - eps * gauge.algebra_coefficients(gauge.gauge_force(U, beta))
+    want = gauge.mom_to_abi(full)
+    assert np.abs(mom.cpu().numpy() - want).max() <= 1e-11
+    g.close()
+
+
+@pytest.mark.parametrize("eps", [0.05, 0.7, 3.0])
+@pytest.mark.parametrize("storage", STORAGES)
+@pytest.mark.parametrize("L", LATS[:2])
+def test_update_links(rh, L, storage, eps):
+    import torch
+
+    U, lat, g = _setup(rh, L, storage, 7400 + sum(L))
+    w = synth.momenta(L, 7500)
+    rh.rhmc_update_links(g, eps, _dev(w))
+    got = _links(rh, g)
+    want = gauge.update_links(U, gauge.mom_from_abi(w, L), eps)
+    assert np.abs(got - want).max() <= 1e-13
+    uu = np.einsum("...ij,...kj->...ik", got, got.conj())
+    assert np.abs(uu - np.eye(3)).max() <= 1e-14
+    assert np.abs(np.linalg.det(got) - 1).max() <= 1e-14
+    # the FP32 copy of the mixed operator follows the update
+    from oracle import dirac
+
+    v = _gauss(np.random.default_rng(3), (1, 3, lat.Vh))
+    out = torch.empty((1, 3, lat.Vh), dtype=torch.complex64, device="cuda:0")
+    rh.rhmc_dslash_eo(g, 1, rh.RHMC_PREC_FP32, 1, _dev(v.astype(np.complex64)), out)
+    ref = dirac.dslash(want, v, 1)
+    assert np.abs(out.cpu().numpy() - ref).max() <= 3e-6 * np.abs(ref).max()
+    g.close()
+
+
+def test_pf_force_kick(rh):
+    import torch
+
+    L = (4, 4, 4, 4)
+    m = 0.1
+    U, lat, g = _setup(rh, L, "fp64_12", 7600)
+    r = rational_for(1, -0.25)
+    phi = _gauss(np.random.default_rng(4), (2, 3, lat.Vh))
+    w = synth.momenta(L, 7700)
+    eps = 0.3
+    mom = _dev(w)
+    prm = rh.solver_params(tol=1e-12, mode=rh.RHMC_MODE_FP64)
+    rh.rhmc_pf_force_kick(g, m, r, _dev(phi), eps, mom, prm)
+    F = force.force(U, m, r.alpha, r.beta, phi)
+    want = gauge.mom_to_abi(gauge.mom_from_abi(w, L) - eps * gauge.algebra_coefficients(F))
+    got = mom.cpu().numpy()
+    assert np.abs(got - want).max() <= 1e-9 * max(1.0, np.abs(want - w).max())
+    # the same as the kick of the force rhmc_pf_force writes out
+    Fg = torch.empty((4, 4, 4, 4, 4, 3, 3), dtype=torch.complex128, device="cuda:0")
+    rh.rhmc_pf_force(g, m, r.alpha0, r.alpha, r.beta, _dev(phi), Fg, prm)
+    want2 = gauge.mom_to_abi(gauge.mom_from_abi(w, L)
+                             - eps * gauge.algebra_coefficients(Fg.cpu().numpy()))
+    assert np.abs(got - want2).max() <= 1e-13 * max(1.0, np.abs(want2).max())
+    g.close()
+
+
+def _md_case(L, seed):
+    m, beta = 0.2, 5.3
+    U = synth.gauge_field(L, 0.4, seed)
+    rng = np.random.default_rng(seed + 1)
+    Vh = synth.even_volume(L)
+    phi = _gauss(rng, (2, 3, Vh))
+    w = synth.momenta(L, seed + 2)
+    return m, beta, U, phi, w
+
+
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+@pytest.mark.parametrize("L", [(4, 4, 4, 4), (6, 4, 4, 6)])
+def test_md_integrate_matches_oracle(rh, L, mode):
+    m, beta, U, phi, w = _md_case(L, 7800 + sum(L))
+    r = rational_for(1, -0.25)
+    tau, n_md, gs = 0.5, 2, 4
+    lat = rh.rhmc_lattice_create(L, -1)
+    g = rh.rhmc_gauge_create(lat, U)
+    solver = rh.solver_params(tol=1e-12 if mode == "fp64" else 1e-11,
+                              mode=rh.RHMC_MODE_FP64 if mode == "fp64" else rh.RHMC_MODE_MIXED)
+    p = rh.MDParams(r, beta=beta, mass=m, tau=tau, n_md=n_md, gauge_steps=gs, solver=solver)
+    mom = _dev(w)
+    st = rh.rhmc_md_integrate(g, p, _dev(phi), mom)
+    assert (st["fermion_forces"], st["gauge_forces"], st["link_updates"]) == (
+        2 * n_md + 1, 2 * gs * n_md + 1, 2 * gs * n_md)
+    ref = md.LatticeMD(U, gauge.mom_from_abi(w, L), phi, beta, m, r)
+    ref.integrate(tau, n_md, gs)
+    assert np.abs(_links(rh, g) - ref.U).max() <= 1e-9
+    assert np.abs(mom.cpu().numpy() - gauge.mom_to_abi(ref.omega)).max() <= 1e-8
+    g.close()
+
+
+def test_trajectory_matches_oracle(rh):
+    L = (4, 4, 4, 4)
+    m, beta, U, _, w = _md_case(L, 7900)
+    R = _gauss(np.random.default_rng(7901), (2, 3, synth.even_volume(L)))
+    r_hb, r_act = rational_for(1, 0.125), rational_for(1, -0.25)
+    tau, n_md, gs = 0.5, 2, 4
+    ref = md.trajectory(U, gauge.mom_from_abi(w, L), R, 0.0, beta, m, r_hb, r_act, r_act,
+                        tau, n_md, gs)
+    lat = rh.rhmc_lattice_create(L, -1)
+    g = rh.rhmc_gauge_create(lat, U)
+    solver = rh.solver_params(tol=1e-12, mode=rh.RHMC_MODE_FP64)
+    p = rh.HMCParams(rh.MDParams(r_act, beta=beta, mass=m, tau=tau, n_md=n_md, gauge_steps=gs,
+                                 solver=solver), r_hb, r_act, solver)
+    mom = _dev(w)
+    st = rh.rhmc_trajectory(g, p, _dev(R), mom, 0.0)
+    assert st["accepted"]
+    for key, i in (("kinetic", 0), ("gauge_action", 1), ("pf_action", 2)):
+        for side, h in ((0, ref["h0"]), (1, ref["h1"])):
+            assert abs(st[key][side] - h[i]) <= 1e-10 * max(1.0, abs(h[i])), (key, side)
+    assert abs(st["dH"] - ref["dH"]) <= 1e-8
+    assert np.abs(_links(rh, g) - ref["U"]).max() <= 1e-9
+    assert np.abs(mom.cpu().numpy() - gauge.mom_to_abi(ref["omega"])).max() <= 1e-8
+    # rejection: u above exp(-dH) restores the links exactly
+    before = _links(rh, g)
+    p2 = rh.HMCParams(rh.MDParams(r_act, beta=beta, mass=m, tau=2.0, n_md=1, gauge_steps=2,
+                                  solver=solver), r_hb, r_act, solver)
+    st2 = rh.rhmc_trajectory(g, p2, _dev(R), _dev(w), 1.0)
+    assert not st2["accepted"] and st2["dH"] > -np.log(1.0)
+    assert np.array_equal(_links(rh, g), before)
+    g.close()
+
+
+def _hmc_start(rh, L, m, seed, npf=2):
+    import torch
+
+    U = synth.gauge_field(L, 0.5, seed)
+    lat = rh.rhmc_lattice_create(L, -1)
+    g = rh.rhmc_gauge_create(lat, U)
+    R = _gauss(np.random.default_rng(seed + 1), (npf, 3, lat.Vh))
+    phi = torch.empty((npf, 3, lat.Vh), dtype=torch.complex128, device="cuda:0")
+    r_hb = rational_for(2, 0.125)
+    rh.rhmc_rational_apply(g, m, r_hb.alpha0, r_hb.alpha, r_hb.beta, _dev(R), phi,
+                           rh.solver_params(tol=1e-12))
+    return U, lat, g, phi
+
+
+@pytest.mark.parametrize("mode,tol,bound", [("fp64", 1e-12, 1e-10), ("mixed", 1e-7, 1e-5)])
+def test_md_reversible_16x16x16x4(rh, mode, tol, bound):
+    L = (16, 16, 16, 4)
+    m, beta = 0.05, 5.3
+    U, lat, g, phi = _hmc_start(rh, L, m, 8000)
+    r = rational_for(2, -0.25)
+    solver = rh.solver_params(tol=tol, mode=rh.RHMC_MODE_FP64 if mode == "fp64" else rh.RHMC_MODE_MIXED)
+    p = rh.MDParams(r, beta=beta, mass=m, tau=0.5, n_md=4, gauge_steps=6, solver=solver)
+    w = synth.momenta(L, 8002)
+    mom = _dev(w)
+    rh.rhmc_md_integrate(g, p, phi, mom)
+    mom.neg_()
+    rh.rhmc_md_integrate(g, p, phi, mom)
+    dC, dM = md.reversibility(U, _links(rh, g), gauge.mom_from_abi(w, L),
+                              gauge.mom_from_abi(mom.cpu().numpy(), L))
+    print(f"reversibility {mode} tol {tol}: dC {dC:.3e} dM {dM:.3e}")
+    assert dC < bound and dM < bound
+    g.close()
+
+
+def test_md_energy_second_order_16x16x16x4(rh):
+    L = (16, 16, 16, 4)
+    m, beta = 0.1, 5.3
+    r = rational_for(2, -0.25)
+    solver = rh.solver_params(tol=1e-12)
+    dH = []
+    for n_md in (4, 8):
+        U, lat, g, phi = _hmc_start(rh, L, m, 8100)
+        w = synth.momenta(L, 8102)
+        mom = _dev(w)
+
+        def H():
+            S, _ = rh.rhmc_pf_action(g, m, r.alpha0, r.alpha, r.beta, phi, solver)
+            return rh.rhmc_kinetic(g, mom) + rh.rhmc_gauge_action(g, beta) + float(S.sum())
+
+        h0 = H()
+        p = rh.MDParams(r, beta=beta, mass=m, tau=0.5, n_md=n_md, gauge_steps=4, solver=solver)
+        rh.rhmc_md_integrate(g, p, phi, mom)
+        dH.append(H() - h0)
+        g.close()
+    print(f"dH(n_md=4) {dH[0]:.4e}  dH(n_md=8) {dH[1]:.4e}")
+    assert abs(dH[0]) < 50.0
+    assert 3.3 < dH[0] / dH[1] < 4.7
+
+
+def test_gauge_sector_48x48x48x12(rh):
+    import torch
+
+    L = synth.CONFIGS[5]["L"]
+    U = np.asarray(workload_gauge(5))
+    lat = rh.rhmc_lattice_create(L, -1)
+    g = rh.rhmc_gauge_create(lat, U)
+    beta = 5.264
+    S = rh.rhmc_gauge_action(g, beta)
+    rng = np.random.default_rng(8200)
+    # sampled plaquette sum is not a closed form; gauge invariance is
+    G = synth.random_su3(U.shape[:4], rng, 2.0)
+    UG = np.empty_like(U)
+    for mu in range(4):
+        UG[..., mu, :, :] = G @ U[..., mu, :, :] @ gauge.dagger(gauge.shift(G, mu, 1))
+    gG = rh.rhmc_gauge_create(lat, UG)
+    SG = rh.rhmc_gauge_action(gG, beta)
+    assert abs(S - SG) <= 1e-12 * abs(S)
+    # the force transforms as F -> G F G^dagger; F = -2i sum_a c^a T^a
+    eps = 1.0
+    m0 = torch.zeros((8, 4, 2, lat.Vh), dtype=torch.float64, device="cuda:0")
+    m1 = torch.zeros_like(m0)
+    rh.rhmc_gauge_force_kick(g, beta, eps, m0)
+    rh.rhmc_gauge_force_kick(gG, beta, eps, m1)
+    c0 = gauge.mom_from_abi(-m0.cpu().numpy(), L)
+    c1 = gauge.mom_from_abi(-m1.cpu().numpy(), L)
+    idx = tuple(rng.integers(0, n, 4096) for n in U.shape[:4])
+    mu = rng.integers(0, 4, 4096)
+    F0 = -2j * np.einsum("sa,aij->sij", c0[idx + (mu,)], T)
+    F1 = -2j * np.einsum("sa,aij->sij", c1[idx + (mu,)], T)
+    Gs = G[idx]
+    assert np.abs(F1 - Gs @ F0 @ gauge.dagger(Gs)).max() <= 1e-11 * np.abs(F0).max()
+    # sampled link updates against the oracle
+    w = synth.momenta(L, 8201)
+    rh.rhmc_update_links(g, 0.1, _dev(w))
+    got = _links(rh, g)[idx + (mu,)]
+    wf = gauge.mom_from_abi(w, L)[idx + (mu,)]
+    want = gauge.update_links(U[idx + (mu,)], wf, 0.1)
+    assert np.abs(got - want).max() <= 1e-13
+    g.close()
+    gG.close()
