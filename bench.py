@@ -15,6 +15,11 @@ Printed JSON line:
   ms_per_step  wall time of one mixed + batched solve;
   time_to_solution_s  the same solve in MIXED + batched and in plain FP64;
   roofline     the hopping kernel against the 8 TB/s HBM peak;
+  md_kernels   the gauge-force kick and link update on the same lattice;
+  md_trajectory_16x16x16x4  seconds per trajectory of the molecular-dynamics
+               workload of the algorithm tests (4 x 16^3, beta 5.264,
+               am 0.01335, 2 pseudofermions, n_md 12, dtau_f/dtau_g 10), with
+               mixed MD solves and FP64 Metropolis solves, and all FP64;
   cpu_baseline the FP64 numpy oracle timed on a bounded sample.
 """
 
@@ -118,6 +123,91 @@ def cpu_baseline(U, b, m, rat, gpu_iters):
     }
 
 
+# Molecular-dynamics kernels, per link (FP64-12 links, FP64 momenta of 8 reals):
+# the gauge-force kick reads every link once and the momenta once and writes
+# the momenta; the link update reads link and momenta and writes the FP64-12
+# and FP32-12 copies.  Flops of the kick: 13 complex 3x3 products (198 each),
+# 19 third-row rebuilds (42 each), the staple sums and the momentum update.
+GF_BYTES_PER_LINK = 96 + 64 + 64
+GF_FLOPS_PER_LINK = 13 * 198 + 19 * 42 + 6 * 18 + 40
+UP_BYTES_PER_LINK = 96 + 64 + 96 + 48
+FP64_VECTOR_PEAK_GFLOPS = 78600.0
+
+
+def kernel_entry(t, t_min, nbytes, nflops):
+    e = {"us_median": round(t * 1e6, 2), "us_min": round(t_min * 1e6, 2),
+         "GBps": round(nbytes / t / 1e9, 1), "hbm_frac": round(nbytes / t / 1e9 / HBM_PEAK_GBPS, 4)}
+    if nflops is not None:
+        e["gflops"] = round(nflops / t / 1e9, 1)
+        e["fp64_frac"] = round(nflops / t / 1e9 / FP64_VECTOR_PEAK_GFLOPS, 4)
+    return e
+
+
+def run_md_workload(rhmc, torch, dev, ntraj):
+    """Trajectories of the molecular-dynamics workload (Sec. 4.4 settings) in
+    two precision settings: MD solves MIXED at r_md = 1e-3 with FP64
+    Metropolis solves at r_metro = 1e-9 (the paper's MP_1), and everything
+    FP64 at 1e-9 (D_1).  One untimed trajectory, then `ntraj` timed ones."""
+    import numpy as np
+
+    import synth
+    from synth.make_rational import md_rationals
+
+    w = synth.MD_WORKLOAD
+    L = w["L"]
+    r_hb, r_act, r_md = md_rationals()
+    U = synth.gauge_field(L, w["eps"], w["seed"])
+    out = {"lattice": list(L), "beta": w["beta"], "mass": w["m"], "npf": w["npf"],
+           "n_md": w["n_md"], "gauge_steps": w["gauge_steps"], "tau": w["tau"],
+           "poles_md": len(r_md.beta), "poles_metropolis": len(r_act.beta),
+           "gauge_field": "synthetic, not thermalised"}
+    settings = {
+        "MP1_mixed_md_1e-3_fp64_metropolis_1e-9": (rhmc.RHMC_MODE_MIXED, 1e-3),
+        "D1_fp64_1e-9": (rhmc.RHMC_MODE_FP64, 1e-9),
+    }
+    for name, (mode, md_tol) in settings.items():
+        lat = rhmc.rhmc_lattice_create(L, -1)
+        g = rhmc.rhmc_gauge_create(lat, U)
+        metro = rhmc.solver_params(tol=1e-9, mode=rhmc.RHMC_MODE_FP64)
+        mdp = rhmc.MDParams(r_md, beta=w["beta"], mass=w["m"], tau=w["tau"], n_md=w["n_md"],
+                            gauge_steps=w["gauge_steps"],
+                            solver=rhmc.solver_params(tol=md_tol, mode=mode))
+        hp = rhmc.HMCParams(mdp, r_hb, r_act, metro)
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(w["seed"] + 7)
+        rng = np.random.default_rng(w["seed"] + 8)
+        times, stats = [], []
+        for k in range(ntraj + 1):
+            R = torch.complex(torch.randn((w["npf"], 3, lat.Vh), dtype=torch.float64, device=dev, generator=gen),
+                              torch.randn((w["npf"], 3, lat.Vh), dtype=torch.float64, device=dev, generator=gen))
+            R *= 0.5 ** 0.5
+            mom = torch.from_numpy(synth.momenta(L, w["seed"] + 100 + k)).to(dev)
+            u = float(rng.uniform())
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            st = rhmc.rhmc_trajectory(g, hp, R, mom, u, allow_not_converged=True)
+            torch.cuda.synchronize()
+            if k > 0:
+                times.append(time.perf_counter() - t1)
+                stats.append(st)
+        g.close()
+        out[name] = {
+            "s_per_trajectory": round(float(np.mean(times)), 4),
+            "runs_s": [round(t, 4) for t in times],
+            "dH": [round(s["dH"], 5) for s in stats],
+            "accepted": [s["accepted"] for s in stats],
+            "fermion_forces": stats[-1]["md"]["fermion_forces"],
+            "gauge_forces": stats[-1]["md"]["gauge_forces"],
+            "link_updates": stats[-1]["md"]["link_updates"],
+            "md_cg_iterations": stats[-1]["md"]["cg_iterations"],
+            "md_s": round(stats[-1]["md"]["time_ms"] / 1e3, 4),
+        }
+        log(f"trajectory {name}: {out[name]['s_per_trajectory']:.3f} s, dH {out[name]['dH']}, "
+            f"MD {out[name]['md_s']:.3f} s, {out[name]['md_cg_iterations']} CG iterations in "
+            f"{out[name]['fermion_forces']} force solves")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -131,6 +221,10 @@ def main():
                     help="also time MIXED and FP64 at this looser tolerance (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-pf", action="store_true", help="skip the pseudofermion heat bath + action")
+    ap.add_argument("--no-md", action="store_true",
+                    help="skip the molecular-dynamics kernels and the 4x16^3 trajectories")
+    ap.add_argument("--md-trajectories", type=int, default=2,
+                    help="timed trajectories per setting of the 4x16^3 workload (after one untimed)")
     ap.add_argument("--only-dslash", action="store_true",
                     help="only the hopping-kernel timing and a copy of known size (counter runs)")
     args = ap.parse_args()
@@ -165,6 +259,29 @@ def main():
     y = torch.empty_like(bd)
     torch.cuda.synchronize()
     log("gauge packed on the device")
+
+    def time_call(fn, reps, warm=3):
+        """Median and min duration of fn's launches, each bracketed by HIP events."""
+        for _ in range(warm):
+            fn()
+        s = torch.cuda.current_stream()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for e0, e1 in ev:
+            e0.record(s)
+            fn()
+            e1.record(s)
+        ev[-1][1].synchronize()
+        ts = sorted(e0.elapsed_time(e1) / 1e3 for e0, e1 in ev)
+        return ts[len(ts) // 2], ts[0]
+
+    def wall_call(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t1) / reps
 
     # ---------------------------------------------------------------- hopping kernel
     def time_dslash(prec, k, reps, gauge=None, vh=None, warm=20):
@@ -298,9 +415,37 @@ def main():
             f"force {t_force * 1e3:.0f} ms, "
             f"max |S/RR - 1| = {pf['max_abs_S_over_RR_minus_1']:.2e}")
 
+    # molecular-dynamics kernels on this lattice (one lane per link or site)
+    md_kernels = None
+    if not args.no_md:
+        mom = torch.from_numpy(synth.momenta(L, 4000 + cfg)).to(dev)
+        beta_g, eps_g = synth.MD_WORKLOAD["beta"], 0.004   # about half a gauge step of the MD workload
+        t_gf, t_gf_min = time_call(lambda: rhmc.rhmc_gauge_force_kick(g, beta_g, 1e-9, mom), 50)
+        t_up, t_up_min = time_call(lambda: rhmc.rhmc_update_links(g, eps_g, mom), 50)
+        t_pl = wall_call(lambda: rhmc.rhmc_gauge_action(g, beta_g), 20)
+        t_kin = wall_call(lambda: rhmc.rhmc_kinetic(g, mom), 20)
+        nl = 4 * lat.V
+        md_kernels = {
+            "gauge_force_kick": kernel_entry(t_gf, t_gf_min, GF_BYTES_PER_LINK * nl, GF_FLOPS_PER_LINK * nl),
+            "link_update": kernel_entry(t_up, t_up_min, UP_BYTES_PER_LINK * nl, None),
+            "plaquette_action_call_ms": round(t_pl * 1e3, 3),
+            "kinetic_call_ms": round(t_kin * 1e3, 3),
+            "note": "HIP events around each launch; GB/s counts each FP64-12 link, momentum "
+                    "and written storage once (neighbour links re-read from cache are not counted); "
+                    "the action and kinetic calls include the read-back of one scalar",
+        }
+        log(f"gauge force kick {t_gf * 1e6:.0f} us ({md_kernels['gauge_force_kick']['GBps']} GB/s, "
+            f"{md_kernels['gauge_force_kick']['gflops']} GFLOP/s), link update {t_up * 1e6:.0f} us "
+            f"({md_kernels['link_update']['GBps']} GB/s), action {t_pl * 1e3:.2f} ms, kinetic {t_kin * 1e3:.2f} ms")
+        del mom
+
     tag = f"dslash_fp32_{nrhs}rhs_{'x'.join(str(v) for v in L)}"
     traffic = traffic_from_profile(tag, var32)
     g.close()
+
+    trajectories = None
+    if not args.no_md:
+        trajectories = run_md_workload(rhmc, torch, dev, args.md_trajectories)
 
     # FP64 operator from hi/lo links (Sec. 4.2 split) and from FP64-18 links, same lattice
     ghl = rhmc.rhmc_gauge_create(lat, U, flags=rhmc.RHMC_LINKS_HILO_12)
@@ -402,6 +547,8 @@ def main():
         "max_true_residual": {"mixed_batched": st["max_true_residual"],
                               "fp64": None if st64 is None else st64["max_true_residual"]},
         "pseudofermion": pf,
+        "md_kernels": md_kernels,
+        "md_trajectory_16x16x16x4": trajectories,
         "reliable_updates": st["reliable_updates"],
         "refine_rounds": st["refine_rounds"],
         "refine_iterations": int(st["refine_iterations"].sum()),

@@ -161,14 +161,19 @@ __device__ __forceinline__ void store_link(const Mat3& U, int k, int nlinks, dou
 }
 
 // ------------------------------------------------------------------ kernels
-// One lane per link (eo, blockIdx.y = mu, blockIdx.z = parity): the six
-// staples, X = U Sigma, and mom^a -= eps * scale * i Tr(T^a TA(X)).
+// One lane per link: the six staples, X = U Sigma, and
+// mom^a -= eps * scale * i Tr(T^a TA(X)).  The 8 (mu, parity) link classes
+// of one range of sites are consecutive blocks, and each XCD takes a
+// contiguous run of blocks, so the 18 neighbour links a lane reads were
+// mostly just read by a nearby lane of the same XCD (its L2).
 template <typename LT>
 __global__ __launch_bounds__(kBlock) void k_gauge_force(const LT* links, int nlinks, Geom g,
                                                         double scale, double eps,
                                                         double* __restrict__ mom) {
-    const int eo = blockIdx.x * kBlock + threadIdx.x;
-    const int mu = blockIdx.y, par = blockIdx.z;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int cls = blk & 7;
+    const int mu = cls >> 1, par = cls & 1;
+    const int eo = (blk >> 3) * kBlock + threadIdx.x;
     if (eo >= g.Vh) return;
     int n[4];
     site_coords(g, eo, par, n[0], n[1], n[2], n[3]);
@@ -315,7 +320,8 @@ static dim3 link_grid(const rhmc_gauge* g) {
 
 hipError_t launch_gauge_force_mom(const rhmc_gauge* g, double beta, double eps, double* mom,
                                   hipStream_t s) {
-    RHMC_GAUGE_DISPATCH(k_gauge_force, link_grid(g), g->lat.geom, -beta / 3.0, eps, mom);
+    const dim3 grid((unsigned)(8 * ((g->lat.Vh + kBlock - 1) / kBlock)));
+    RHMC_GAUGE_DISPATCH(k_gauge_force, grid, g->lat.geom, -beta / 3.0, eps, mom);
     return hipGetLastError();
 }
 

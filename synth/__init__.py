@@ -9,6 +9,7 @@ it produces, and neither imports the other.
 
 from .fields import (  # noqa: F401
     CONFIGS,
+    MD_WORKLOAD,
     even_volume,
     gauge_field,
     momenta,

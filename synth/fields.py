@@ -49,6 +49,16 @@ CONFIGS = {
 }
 
 
+# The molecular-dynamics workload of the algorithm tests of Sec. 4.4: a 4 x 16^3
+# lattice at beta 5.264 and am 0.01335, two pseudofermions, rational
+# approximations with 8 poles in the molecular dynamics and 15 in the
+# Metropolis step (x^{-1/4}) and the heat bath (x^{+1/8}), n_md = 12 fermion
+# steps with dtau_f / dtau_g = 10, trajectory length 1.  The gauge field is
+# synthetic (link roughness 0.5 gives a plaquette near 0.5), not thermalised.
+MD_WORKLOAD = dict(L=(16, 16, 16, 4), eps=0.5, beta=5.264, m=0.01335, npf=2, md_npole=8,
+                   metro_npole=15, n_md=12, gauge_steps=10, tau=1.0, seed=1100)
+
+
 def seed_gauge(cfg: int) -> int:
     return 1000 + cfg
 

@@ -1,11 +1,12 @@
-"""Write the cached rational coefficients for the five named workloads.
+"""Write the cached rational coefficients for the five named workloads and
+the molecular-dynamics workload.
 
 Run as ``python -m synth.make_rational``; each file in ``synth/data`` holds
 alpha0, alpha_i, beta_i and the levelled relative error delta for x^p with
 ``npole`` poles on the interval [m^2, 16 + m^2].
 """
 
-from .fields import CONFIGS
+from .fields import CONFIGS, MD_WORKLOAD
 from .remez import rational_coefficients
 
 
@@ -17,6 +18,12 @@ def workload_rationals():
             key = (p, c["npole"], lo, 16.0 + lo)
             if key not in seen:
                 seen.append(key)
+    lo = MD_WORKLOAD["m"] ** 2
+    for p, n in ((0.125, MD_WORKLOAD["metro_npole"]), (-0.25, MD_WORKLOAD["metro_npole"]),
+                 (-0.25, MD_WORKLOAD["md_npole"])):
+        key = (p, n, lo, 16.0 + lo)
+        if key not in seen:
+            seen.append(key)
     return seen
 
 
@@ -24,6 +31,16 @@ def rational_for(cfg: int, p: float = -0.25):
     c = CONFIGS[cfg]
     lo = c["m"] ** 2
     return rational_coefficients(p, c["npole"], lo, 16.0 + lo)
+
+
+def md_rationals():
+    """(heat bath x^{1/8}, Metropolis action x^{-1/4}, molecular-dynamics force
+    x^{-1/4}) of the molecular-dynamics workload."""
+    w = MD_WORKLOAD
+    lo = w["m"] ** 2
+    return (rational_coefficients(0.125, w["metro_npole"], lo, 16.0 + lo),
+            rational_coefficients(-0.25, w["metro_npole"], lo, 16.0 + lo),
+            rational_coefficients(-0.25, w["md_npole"], lo, 16.0 + lo))
 
 
 if __name__ == "__main__":
