@@ -223,6 +223,8 @@ def main():
     ap.add_argument("--no-pf", action="store_true", help="skip the pseudofermion heat bath + action")
     ap.add_argument("--no-md", action="store_true",
                     help="skip the molecular-dynamics kernels and the 4x16^3 trajectories")
+    ap.add_argument("--only-md", action="store_true",
+                    help="only the molecular-dynamics kernels and trajectories (profiler runs)")
     ap.add_argument("--md-trajectories", type=int, default=2,
                     help="timed trajectories per setting of the 4x16^3 workload (after one untimed)")
     ap.add_argument("--only-dslash", action="store_true",
@@ -282,6 +284,35 @@ def main():
             fn()
         torch.cuda.synchronize()
         return (time.perf_counter() - t1) / reps
+
+    def md_kernel_timings():
+        mom = torch.from_numpy(synth.momenta(L, 4000 + cfg)).to(dev)
+        beta_g, eps_g = synth.MD_WORKLOAD["beta"], 0.004   # about half a gauge step of the MD workload
+        t_gf, t_gf_min = time_call(lambda: rhmc.rhmc_gauge_force_kick(g, beta_g, 1e-9, mom), 50)
+        t_up, t_up_min = time_call(lambda: rhmc.rhmc_update_links(g, eps_g, mom), 50)
+        t_pl = wall_call(lambda: rhmc.rhmc_gauge_action(g, beta_g), 20)
+        t_kin = wall_call(lambda: rhmc.rhmc_kinetic(g, mom), 20)
+        nl = 4 * lat.V
+        res = {
+            "gauge_force_kick": kernel_entry(t_gf, t_gf_min, GF_BYTES_PER_LINK * nl, GF_FLOPS_PER_LINK * nl),
+            "link_update": kernel_entry(t_up, t_up_min, UP_BYTES_PER_LINK * nl, None),
+            "plaquette_action_call_ms": round(t_pl * 1e3, 3),
+            "kinetic_call_ms": round(t_kin * 1e3, 3),
+            "note": "HIP events around each launch; GB/s counts each FP64-12 link, momentum "
+                    "and written storage once (neighbour links re-read from cache are not counted); "
+                    "the action and kinetic calls include the read-back of one scalar",
+        }
+        log(f"gauge force kick {t_gf * 1e6:.0f} us ({res['gauge_force_kick']['GBps']} GB/s, "
+            f"{res['gauge_force_kick']['gflops']} GFLOP/s), link update {t_up * 1e6:.0f} us "
+            f"({res['link_update']['GBps']} GB/s), action {t_pl * 1e3:.2f} ms, kinetic {t_kin * 1e3:.2f} ms")
+        return res
+
+    if args.only_md:
+        res = {"md_kernels": md_kernel_timings()}
+        g.close()
+        res["md_trajectory_16x16x16x4"] = run_md_workload(rhmc, torch, dev, args.md_trajectories)
+        print(json.dumps(res), flush=True)
+        return
 
     # ---------------------------------------------------------------- hopping kernel
     def time_dslash(prec, k, reps, gauge=None, vh=None, warm=20):
@@ -416,28 +447,7 @@ def main():
             f"max |S/RR - 1| = {pf['max_abs_S_over_RR_minus_1']:.2e}")
 
     # molecular-dynamics kernels on this lattice (one lane per link or site)
-    md_kernels = None
-    if not args.no_md:
-        mom = torch.from_numpy(synth.momenta(L, 4000 + cfg)).to(dev)
-        beta_g, eps_g = synth.MD_WORKLOAD["beta"], 0.004   # about half a gauge step of the MD workload
-        t_gf, t_gf_min = time_call(lambda: rhmc.rhmc_gauge_force_kick(g, beta_g, 1e-9, mom), 50)
-        t_up, t_up_min = time_call(lambda: rhmc.rhmc_update_links(g, eps_g, mom), 50)
-        t_pl = wall_call(lambda: rhmc.rhmc_gauge_action(g, beta_g), 20)
-        t_kin = wall_call(lambda: rhmc.rhmc_kinetic(g, mom), 20)
-        nl = 4 * lat.V
-        md_kernels = {
-            "gauge_force_kick": kernel_entry(t_gf, t_gf_min, GF_BYTES_PER_LINK * nl, GF_FLOPS_PER_LINK * nl),
-            "link_update": kernel_entry(t_up, t_up_min, UP_BYTES_PER_LINK * nl, None),
-            "plaquette_action_call_ms": round(t_pl * 1e3, 3),
-            "kinetic_call_ms": round(t_kin * 1e3, 3),
-            "note": "HIP events around each launch; GB/s counts each FP64-12 link, momentum "
-                    "and written storage once (neighbour links re-read from cache are not counted); "
-                    "the action and kinetic calls include the read-back of one scalar",
-        }
-        log(f"gauge force kick {t_gf * 1e6:.0f} us ({md_kernels['gauge_force_kick']['GBps']} GB/s, "
-            f"{md_kernels['gauge_force_kick']['gflops']} GFLOP/s), link update {t_up * 1e6:.0f} us "
-            f"({md_kernels['link_update']['GBps']} GB/s), action {t_pl * 1e3:.2f} ms, kinetic {t_kin * 1e3:.2f} ms")
-        del mom
+    md_kernels = md_kernel_timings() if not args.no_md else None
 
     tag = f"dslash_fp32_{nrhs}rhs_{'x'.join(str(v) for v in L)}"
     traffic = traffic_from_profile(tag, var32)
