@@ -101,7 +101,7 @@ def test_links_action_kinetic(rh, L, storage):
 
 
 @pytest.mark.parametrize("storage", STORAGES)
-@pytest.mark.parametrize("L", LATS)
+@pytest.mark.parametrize("L", LATS + [(4, 6, 6, 4)])   # Lz % 4 != 0: the other site order
 def test_gauge_force_kick(rh, L, storage):
     U, lat, g = _setup(rh, L, storage, 7200 + sum(L), eps=0.7)
     beta, eps = 5.3, 0.37
@@ -330,3 +330,44 @@ def test_gauge_sector_48x48x48x12(rh):
     assert np.abs(got - want).max() <= 1e-13
     g.close()
     gG.close()
+
+
+def test_trajectory_48x48x48x12(rh):
+    """One short trajectory at the full workload size, in the precision
+    setting of the benchmark (MIXED MD solves, FP64-12 Metropolis solves):
+    the heat bath makes the initial fermion action R^dagger R, the energy
+    error is small and falls by ~4 when the step is halved, and a rejection
+    restores the links."""
+    import torch
+
+    c = synth.CONFIGS[5]
+    L, m = c["L"], c["m"]
+    U = np.asarray(workload_gauge(5))
+    lat = rh.rhmc_lattice_create(L, -1)
+    g = rh.rhmc_gauge_create(lat, U)
+    r_hb, r_act = rational_for(5, 0.125), rational_for(5, -0.25)
+    R = _gauss(np.random.default_rng(8300), (2, 3, lat.Vh))
+    w = synth.momenta(L, 8301)
+    metro = rh.solver_params(tol=1e-10, mode=rh.RHMC_MODE_FP64)
+    dH = []
+    for n_md in (1, 2):
+        p = rh.HMCParams(rh.MDParams(r_act, beta=5.264, mass=m, tau=0.04, n_md=n_md, gauge_steps=2,
+                                     solver=rh.solver_params(tol=1e-9, mode=rh.RHMC_MODE_MIXED)),
+                         r_hb, r_act, metro)
+        before = _links(rh, g)
+        st = rh.rhmc_trajectory(g, p, _dev(R), _dev(w), 1.0)
+        print(f"48^3x12 n_md {n_md}: dH {st['dH']:.4e} parts K {st['kinetic'][1] - st['kinetic'][0]:.4e} "
+              f"S_g {st['gauge_action'][1] - st['gauge_action'][0]:.4e} "
+              f"S_f {st['pf_action'][1] - st['pf_action'][0]:.4e} time {st['time_ms'] / 1e3:.1f} s")
+        RR = float(np.sum(np.abs(R) ** 2))
+        assert abs(st["pf_action"][0] / RR - 1) < 1e-8
+        if not st["accepted"]:
+            assert np.array_equal(_links(rh, g), before)
+        else:
+            assert st["dH"] <= 0.0
+            g.close()
+            g = rh.rhmc_gauge_create(lat, U)
+        dH.append(st["dH"])
+    assert abs(dH[0]) < 1e3
+    assert 3.0 < dH[0] / dH[1] < 5.0, dH
+    g.close()
