@@ -99,6 +99,10 @@ typedef struct {
     int32_t use_graph;      /* nonzero: replay each block of iterations as a hipGraph (default 1) */
     int32_t poll_every;     /* blocks launched between convergence polls (0 = automatic) */
     int32_t tune;           /* nonzero: time the Dslash launch shapes once and keep the best */
+    int32_t per_shift;      /* nonzero: no shared Krylov space; every shifted system gets its
+                               own CG from a zero start (batched up to 8 systems per launch,
+                               sorted by shift, with reliable updates in MIXED mode), the
+                               ordinary-solver alternative at the end of Sec. 4.3 (default 0) */
 } rhmc_solver_params;
 
 typedef struct {

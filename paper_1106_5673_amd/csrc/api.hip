@@ -112,6 +112,7 @@ void rhmc_solver_params_default(rhmc_solver_params* p) {
     p->use_graph = 1;
     p->poll_every = 0;
     p->tune = 0;
+    p->per_shift = 0;
 }
 
 rhmc_status rhmc_lattice_create(const int32_t L[4], int32_t t_bc, rhmc_lattice** out) {

@@ -502,36 +502,64 @@ static rhmc_status solve_impl(rhmc_gauge* g, Problem pb, const rhmc_solver_param
                               rhmc_solver_stats* stats, hipStream_t s) {
     const auto t0 = std::chrono::steady_clock::now();
     int iters = 0, rel = 0;
-    if (pb.mode == RHMC_MODE_MIXED)
-        RHMC_TRY(run_krylov<float2>(g, pb, s, &iters, &rel));
-    else
-        RHMC_TRY(run_krylov<double2>(g, pb, s, &iters, &rel));
-    Workspace* w = g->ws;
-    const SolverState hs = *w->hst;
+    const bool per_shift = prm.per_shift != 0;
     const int total = pb.nsys * pb.nshift;
     std::vector<int> conv(total), refine_it(total, 0);
-    for (int j = 0; j < pb.nsys; ++j)
-        for (int i = 0; i < pb.nshift; ++i) {
-            const ShiftScalars& q = hs.sh[j][i];
-            conv[j * pb.nshift + i] = q.active ? hs.sys[j].iters : q.conv_iter;
-        }
     double bnorm[kMaxSys];
-    for (int j = 0; j < pb.nsys; ++j) bnorm[j] = hs.sys[j].bnorm;
-
-    std::vector<int> all(total);
-    for (int p = 0; p < total; ++p) all[p] = p;
-    std::vector<double> res2(total);
-    RHMC_TRY(true_residuals(g, pb, all, res2.data(), nullptr, s));
-    std::vector<double> res(total);
-    auto relres = [&](int p) {
-        const int j = p / pb.nshift;
-        return bnorm[j] > 0 ? std::sqrt(res2[p]) / bnorm[j] : 0.0;
-    };
-    for (int p = 0; p < total; ++p) res[p] = relres(p);
+    std::vector<double> res(total), res2(total);
+    if (!per_shift) {
+        if (pb.mode == RHMC_MODE_MIXED)
+            RHMC_TRY(run_krylov<float2>(g, pb, s, &iters, &rel));
+        else
+            RHMC_TRY(run_krylov<double2>(g, pb, s, &iters, &rel));
+        const SolverState hs = *g->ws->hst;
+        for (int j = 0; j < pb.nsys; ++j)
+            for (int i = 0; i < pb.nshift; ++i) {
+                const ShiftScalars& q = hs.sh[j][i];
+                conv[j * pb.nshift + i] = q.active ? hs.sys[j].iters : q.conv_iter;
+            }
+        for (int j = 0; j < pb.nsys; ++j) bnorm[j] = hs.sys[j].bnorm;
+        std::vector<int> all(total);
+        for (int p = 0; p < total; ++p) all[p] = p;
+        RHMC_TRY(true_residuals(g, pb, all, res2.data(), nullptr, s));
+        for (int p = 0; p < total; ++p) {
+            const int j = p / pb.nshift;
+            res[p] = bnorm[j] > 0 ? std::sqrt(res2[p]) / bnorm[j] : 0.0;
+        }
+    } else {
+        // every shifted system from a zero start: the residual is b, and the
+        // batched per-shift CG below (the refinement loop) solves each system
+        RHMC_TRY(ensure_workspace(g, pb.nsys, pb.nshift, pb.K));
+        Workspace* ws = g->ws;
+        DotArgs d{};
+        d.n = ws->n;
+        d.partial = ws->partial;
+        for (int j = 0; j < pb.nsys; ++j) d.a[j] = d.b[j] = pb.b[j];
+        RHMC_HIP_TRY(launch_dot(d, pb.nsys, s));
+        RHMC_HIP_TRY(launch_finalize(kFinNorms, nullptr, ws->partial, vec_blocks(ws->n), pb.nsys,
+                                     ws->sums, s));
+        RHMC_HIP_TRY(hipMemcpyAsync(ws->sums_host, ws->sums, sizeof(double) * pb.nsys,
+                                    hipMemcpyDeviceToHost, s));
+        for (int j = 0; j < pb.nsys; ++j)
+            for (int i = 0; i < pb.nshift; ++i)
+                RHMC_HIP_TRY(hipMemsetAsync(pb.X + j * pb.x_sys + i * pb.x_shift, 0,
+                                            ws->n * sizeof(double2), s));
+        RHMC_HIP_TRY(hipStreamSynchronize(s));
+        for (int j = 0; j < pb.nsys; ++j) {
+            bnorm[j] = std::sqrt(ws->sums_host[j]);
+            if (!std::isfinite(bnorm[j])) {
+                set_error("source holds NaN or Inf");
+                return RHMC_ERR_NONFINITE;
+            }
+        }
+        for (int p = 0; p < total; ++p) res[p] = bnorm[p / pb.nshift] > 0 ? 1.0 : 0.0;
+    }
+    Workspace* w = g->ws;
 
     int rounds = 0;
     const double tol = prm.tol;
-    while (prm.refine && rounds < 4) {
+    const int max_rounds = prm.refine ? 4 : (per_shift ? 1 : 0);
+    while (rounds < max_rounds) {
         std::vector<int> bad;
         for (int p = 0; p < total; ++p)
             if (!(res[p] <= tol)) bad.push_back(p);
@@ -595,6 +623,13 @@ static rhmc_status solve_impl(rhmc_gauge* g, Problem pb, const rhmc_solver_param
     for (int p = 0; p < total; ++p) {
         worst = std::max(worst, res[p]);
         if (!(res[p] <= tol)) ok = false;
+    }
+    if (per_shift) {
+        // each system's own iterations; the shared count is the largest
+        for (int p = 0; p < total; ++p) {
+            conv[p] = refine_it[p];
+            iters = std::max(iters, refine_it[p]);
+        }
     }
     if (stats) {
         for (int p = 0; p < total; ++p) {
