@@ -374,8 +374,9 @@ typedef struct {
 
 /* One trajectory of the Phi algorithm (Sec. 2.1): phi = r_hb(A) R, H before,
  * rhmc_md_integrate, H after, and the Metropolis test: accepted iff
- * u < exp(-dH).  On rejection the links of g are restored to their values at
- * the start; mom holds the final momenta either way.  R: device complex128
+ * u < exp(-dH).  On rejection, and on an error after the molecular dynamics
+ * has started, the links of g are restored to their values at the start; mom
+ * holds the final momenta either way.  R: device complex128
  * [npf][3][V/2], complex Gaussian (parts N(0, 1/2)); mom: device momenta drawn
  * N(0, 1) by the caller; u in [0, 1).  Blocks until done; stats required. */
 rhmc_status rhmc_trajectory(rhmc_gauge* g, const rhmc_hmc_params* params, int32_t npf,

@@ -239,11 +239,17 @@ rhmc_status trajectory(rhmc_gauge* g, const rhmc_hmc_params& p, int npf, const d
     RHMC_TRY(gauge_action(g, p.md.beta, &stats->gauge_action[0], s));
     RHMC_TRY(fermion_action(&stats->pf_action[0]));
     RHMC_TRY(copy_links(g, w, true, s));
+    // from here on a failure leaves the links as they were at the start
+    auto fail = [&](rhmc_status q) -> rhmc_status {
+        copy_links(g, w, false, s);
+        hipStreamSynchronize(s);
+        return q;
+    };
     r = md_integrate(g, p.md, npf, w->phi, mom, &stats->md, s);
-    if (!keep(r)) return r;
-    RHMC_TRY(kinetic(g, mom, &stats->kinetic[1], s));
-    RHMC_TRY(gauge_action(g, p.md.beta, &stats->gauge_action[1], s));
-    RHMC_TRY(fermion_action(&stats->pf_action[1]));
+    if (!keep(r)) return fail(r);
+    if ((r = kinetic(g, mom, &stats->kinetic[1], s)) != RHMC_OK) return fail(r);
+    if ((r = gauge_action(g, p.md.beta, &stats->gauge_action[1], s)) != RHMC_OK) return fail(r);
+    if ((r = fermion_action(&stats->pf_action[1])) != RHMC_OK) return fail(r);
     stats->dH = (stats->kinetic[1] - stats->kinetic[0]) +
                 (stats->gauge_action[1] - stats->gauge_action[0]) +
                 (stats->pf_action[1] - stats->pf_action[0]);
