@@ -102,7 +102,9 @@ typedef struct {
     int32_t per_shift;      /* nonzero: no shared Krylov space; every shifted system gets its
                                own CG from a zero start (batched up to 8 systems per launch,
                                sorted by shift, with reliable updates in MIXED mode), the
-                               ordinary-solver alternative at the end of Sec. 4.3 (default 0) */
+                               ordinary-solver alternative at the end of Sec. 4.3; stats then
+                               give each system's own iterations, total_iterations is the
+                               largest of them, refine_rounds counts this pass (default 0) */
 } rhmc_solver_params;
 
 typedef struct {

@@ -371,3 +371,45 @@ def test_trajectory_48x48x48x12(rh):
     assert abs(dH[0]) < 1e3
     assert 3.0 < dH[0] / dH[1] < 5.0, dH
     g.close()
+
+
+def test_md_invalid_arguments(rh):
+    import torch
+
+    L = (4, 4, 4, 4)
+    U = synth.gauge_field(L, 0.5, 8400)
+    lat = rh.rhmc_lattice_create(L, -1)
+    g = rh.rhmc_gauge_create(lat, U)
+    r = rational_for(1, -0.25)
+    phi = _dev(_gauss(np.random.default_rng(1), (2, 3, lat.Vh)))
+    mom = _dev(synth.momenta(L, 8401))
+    before = mom.clone()
+    for kw in (dict(n_md=0), dict(gauge_steps=3), dict(gauge_steps=0), dict(lambda_=0.7),
+               dict(lambda_=-0.1), dict(tau=float("nan")), dict(beta=float("inf"))):
+        p = rh.MDParams(r, **{**dict(beta=5.3, mass=0.1, tau=0.1, n_md=1, gauge_steps=2), **kw})
+        with pytest.raises(rh.RhmcError) as e:
+            rh.rhmc_md_integrate(g, p, phi, mom)
+        assert e.value.status == rh.RHMC_ERR_INVALID_ARG, kw
+    assert torch.equal(mom, before)   # rejected calls leave the momenta alone
+    bad = rh.Rational(1.0, [0.5], [-1.0])   # negative pole
+    with pytest.raises(rh.RhmcError):
+        rh.rhmc_pf_force_kick(g, 0.1, bad, phi, 0.1, mom)
+    with pytest.raises(rh.RhmcError):
+        rh.rhmc_gauge_force_kick(g, float("nan"), 0.1, mom)
+    with pytest.raises(rh.RhmcError):
+        rh.rhmc_update_links(g, float("inf"), mom)
+    with pytest.raises(ValueError):
+        rh.rhmc_kinetic(g, mom[:, :, :, :10].contiguous())     # wrong shape stops in the binding
+    hp = rh.HMCParams(rh.MDParams(r, beta=5.3, mass=0.1, tau=0.1, n_md=1, gauge_steps=2), r, r)
+    with pytest.raises(rh.RhmcError):
+        rh.rhmc_trajectory(g, hp, phi, mom, 1.5)                # u outside [0, 1]
+    g.close()
+    # links stored only in FP32: no molecular dynamics
+    g32 = rh.rhmc_gauge_create(lat, U, rh.RHMC_LINKS_FP32_12)
+    with pytest.raises(rh.RhmcError) as e:
+        rh.rhmc_update_links(g32, 0.1, mom)
+    assert e.value.status == rh.RHMC_ERR_UNSUPPORTED
+    with pytest.raises(rh.RhmcError) as e:
+        rh.rhmc_gauge_action(g32, 5.3)
+    assert e.value.status == rh.RHMC_ERR_UNSUPPORTED
+    g32.close()
