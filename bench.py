@@ -120,7 +120,24 @@ def cpu_baseline(U, b, m, rat, gpu_iters):
         "time_to_solution_s_extrapolated": t_it * gpu_iters * nrhs,
         "wall_seconds": wall_total,
         "cpu_seconds": cpu_total,
+        "host": host_description(),
     }
+
+
+def host_description():
+    """CPU model, logical CPUs and the thread settings numpy's kernels see."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    threads = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")
+               if os.environ.get(k) is not None}
+    return {"cpu_model": model, "nproc": os.cpu_count(), "threads_env": threads}
 
 
 # Molecular-dynamics kernels, per link (FP64-12 links, FP64 momenta of 8 reals):
@@ -261,6 +278,8 @@ def main():
     y = torch.empty_like(bd)
     torch.cuda.synchronize()
     log("gauge packed on the device")
+    # average plaquette Re Tr P / 3 of the field (roughness descriptor): S_g at beta = 1 is sum (1 - Re Tr P / 3)
+    plaquette = 1.0 - rhmc.rhmc_gauge_action(g, 1.0) / (6.0 * lat.V)
 
     def time_call(fn, reps, warm=3):
         """Median and min duration of fn's launches, each bracketed by HIP events."""
@@ -315,9 +334,12 @@ def main():
         return
 
     # ---------------------------------------------------------------- hopping kernel
-    def time_dslash(prec, k, reps, gauge=None, vh=None, warm=20):
+    def time_dslash(prec, k, reps, gauge=None, vh=None, warm=20, flush=None):
         """Median and min launch time of D_oe over `reps` launches, each
-        bracketed by its own pair of HIP events on the launching stream."""
+        bracketed by its own pair of HIP events on the launching stream;
+        with `flush` (a device buffer), the buffer is streamed through a
+        reduction between launches, outside the events, so no cache holds the
+        operands (reading, not writing, leaves no dirty lines to write back)."""
         gg = gauge if gauge is not None else g
         n = vh if vh is not None else Vh
         dt = torch.complex64 if prec == "fp32" else torch.complex128
@@ -329,7 +351,9 @@ def main():
             rhmc.rhmc_dslash_eo(gg, 1, pr, k, vin, vout)
         s = torch.cuda.current_stream()
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
-        for e0, e1 in ev:
+        for i, (e0, e1) in enumerate(ev):
+            if flush is not None:
+                flush.max()
             e0.record(s)
             rhmc.rhmc_dslash_eo(gg, 1, pr, k, vin, vout)
             e1.record(s)
@@ -344,6 +368,15 @@ def main():
     var64 = rhmc.rhmc_dslash_variant(g, rhmc.RHMC_PREC_FP64, 1)
     log(f"hopping launch variants: fp32 x{nrhs} {var32}, fp64 x1 {var64}")
     avg, avg_min, byts = time_dslash("fp32", nrhs, args.dslash_reps)
+    # the same launches with a 1 GiB buffer read between them: no link or
+    # vector can be served from the 256 MB Infinity Cache
+    # (not in the counter runs, which average every launch of the kernel)
+    avg_cold = avg_cold_min = float("nan")
+    if not args.only_dslash:
+        junk = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        avg_cold, avg_cold_min, _ = time_dslash("fp32", nrhs, args.dslash_reps, flush=junk)
+        del junk
+        log(f"hopping fp32-12 x{nrhs} cold cache: {avg_cold * 1e6:.1f} us ({byts / avg_cold / 1e9:.0f} GB/s)")
     avg64, avg64_min, _ = time_dslash("fp64", 1, args.dslash_reps)
     byts64 = dslash_bytes_per_site("fp64c", 1) * Vh   # default storage: FP64-12 links
     avg1, avg1_min, byts1 = time_dslash("fp32", 1, args.dslash_reps)
@@ -508,6 +541,7 @@ def main():
             "npole": len(rat.beta),
             "mass": m,
             "tol": c["tol"],
+            "plaquette": round(plaquette, 6),
         },
         "roofline": {
             "bound": "hbm",
@@ -519,6 +553,9 @@ def main():
             "kernel": f"hopping FP32 12-real, {nrhs} rhs, launch variant {var32}, "
                       f"{avg * 1e6:.2f} us per launch (median of {args.dslash_reps}; min "
                       f"{avg_min * 1e6:.2f}), {byts / 1e6:.1f} MB algorithmic per launch",
+            "cold_cache": {"us_median": round(avg_cold * 1e6, 2), "us_min": round(avg_cold_min * 1e6, 2),
+                           "GBps": round(byts / avg_cold / 1e9, 1),
+                           "note": "a 1 GiB buffer read between launches (outside the events)"},
             "gflops": round(FLOPS_PER_SITE * Vh * nrhs / avg / 1e9, 1),
         },
         "dslash": {
