@@ -158,3 +158,35 @@ def exp_i(eps, H):
 def update_links(U, omega, eps):
     """U -> reunitarize(exp(i eps H) U)."""
     return reunitarize(exp_i(eps, mom_matrix(omega)) @ U)
+
+
+def gauge_force_links(U, beta, t, z, y, x, mu):
+    """F_g of the links (t[k], z[k], y[k], x[k], mu[k]) only, from the same
+    definition with the neighbours indexed explicitly (periodic): for large
+    lattices, where only a sample of links is checked."""
+    Lt, Lz, Ly, Lx = U.shape[:4]
+    ext = (Lx, Ly, Lz, Lt)
+    t, z, y, x, mu = (np.asarray(a, dtype=np.int64) for a in (t, z, y, x, mu))
+
+    def link(c, d):   # U_d at coordinates c = [x, y, z, t] (arrays)
+        return U[c[3] % Lt, c[2] % Lz, c[1] % Ly, c[0] % Lx, d]
+
+    def step(c, d, s):
+        c = [a.copy() for a in c]
+        c[d] = c[d] + s
+        return c
+
+    n = [x, y, z, t]
+    S = np.zeros((x.size, 3, 3), dtype=np.complex128)
+    for k in range(x.size):
+        m = int(mu[k])
+        nk = [a[k:k + 1] for a in n]
+        for nu in range(4):
+            if nu == m:
+                continue
+            up = link(step(nk, m, 1), nu) @ dagger(link(step(nk, nu, 1), m)) @ dagger(link(nk, nu))
+            lo_site = step(nk, nu, -1)
+            lo = dagger(link(step(lo_site, m, 1), nu)) @ dagger(link(lo_site, m)) @ link(lo_site, nu)
+            S[k] += (up + lo)[0]
+    Ul = U[t, z, y, x, mu]
+    return -(beta / 3.0) * traceless_antihermitian(Ul @ S)

@@ -18,8 +18,9 @@ Against the oracle, element by element, on lattices of one to several
 
 Properties that hold at any size: reversibility (Delta C, Delta M of Sec. 4.4)
 and the second-order energy error at 16^3x4; at 48^3x12 gauge invariance of
-the action, gauge covariance of the force and sampled link updates against
-the oracle.
+the action, gauge covariance of the force, the gauge force and link updates
+of 4096 sampled links against the oracle, and a short trajectory (heat-bath
+action, second-order energy error, restore on rejection).
 """
 
 import numpy as np
@@ -321,6 +322,9 @@ def test_gauge_sector_48x48x48x12(rh):
     F1 = -2j * np.einsum("sa,aij->sij", c1[idx + (mu,)], T)
     Gs = G[idx]
     assert np.abs(F1 - Gs @ F0 @ gauge.dagger(Gs)).max() <= 1e-11 * np.abs(F0).max()
+    # and the sampled links against the oracle's force at those links
+    Fo = gauge.gauge_force_links(U, beta, *idx, mu)
+    assert np.abs(c0[idx + (mu,)] - gauge.algebra_coefficients(Fo)).max() <= 1e-11 * np.abs(c0).max()
     # sampled link updates against the oracle
     w = synth.momenta(L, 8201)
     rh.rhmc_update_links(g, 0.1, _dev(w))

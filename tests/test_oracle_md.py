@@ -360,3 +360,15 @@ def test_trajectory_metropolis(md_setup):
     if u is not None:
         b = md.trajectory(U, omega, R, u, beta, m, r_hb, r_md, r_md, 0.5, 2, 4)
         assert not b["accepted"] and np.array_equal(b["U"], U)
+
+
+def test_gauge_force_at_sampled_links_matches_whole_lattice():
+    L = (4, 6, 4, 2)
+    U = synth.gauge_field(L, 0.7, 71)
+    F = gauge.gauge_force(U, 5.1)
+    rng = np.random.default_rng(72)
+    k = 60
+    t, z, y, x = (rng.integers(0, n, k) for n in U.shape[:4])
+    mu = rng.integers(0, 4, k)
+    Fs = gauge.gauge_force_links(U, 5.1, t, z, y, x, mu)
+    assert np.abs(Fs - F[t, z, y, x, mu]).max() < 1e-14
