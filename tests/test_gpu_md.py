@@ -417,3 +417,40 @@ def test_md_invalid_arguments(rh):
         rh.rhmc_gauge_action(g32, 5.3)
     assert e.value.status == rh.RHMC_ERR_UNSUPPORTED
     g32.close()
+
+
+@pytest.mark.parametrize("storage,t_bc", [("fp64_18", -1), ("hilo", -1), ("fp64_12", 1)])
+def test_md_integrate_storages_and_boundary(rh, storage, t_bc):
+    """The integrator on FP64-18 and hi/lo-only link storages (every update
+    rewrites them) and with a periodic time boundary, against the oracle."""
+    L = (4, 4, 4, 6)
+    m, beta, U, phi, w = _md_case(L, 8500 + t_bc)
+    r = rational_for(1, -0.25)
+    lat = rh.rhmc_lattice_create(L, t_bc)
+    g = rh.rhmc_gauge_create(lat, U, _flags(rh, storage))
+    p = rh.MDParams(r, beta=beta, mass=m, tau=0.3, n_md=2, gauge_steps=2,
+                    solver=rh.solver_params(tol=1e-12))
+    mom = _dev(w)
+    rh.rhmc_md_integrate(g, p, _dev(phi), mom)
+    ref = md.LatticeMD(U, gauge.mom_from_abi(w, L), phi, beta, m, r, t_bc=t_bc)
+    ref.integrate(0.3, 2, 2)
+    tol_u = 2e-9 if storage == "hilo" else 1e-9
+    assert np.abs(_links(rh, g) - ref.U).max() <= tol_u
+    assert np.abs(mom.cpu().numpy() - gauge.mom_to_abi(ref.omega)).max() <= 1e-8
+    g.close()
+
+
+def test_pf_force_kick_many_pseudofermions(rh):
+    """Nine pseudofermions: the kick is applied group by group (8 per solve)."""
+    L = (4, 4, 4, 4)
+    m = 0.15
+    U, lat, g = _setup(rh, L, "fp64_12", 8600)
+    r = rational_for(1, -0.25)
+    phi = _gauss(np.random.default_rng(8601), (9, 3, lat.Vh))
+    w = synth.momenta(L, 8602)
+    mom = _dev(w)
+    rh.rhmc_pf_force_kick(g, m, r, _dev(phi), 0.2, mom, rh.solver_params(tol=1e-12))
+    F = force.force(U, m, r.alpha, r.beta, phi)
+    want = gauge.mom_to_abi(gauge.mom_from_abi(w, L) - 0.2 * gauge.algebra_coefficients(F))
+    assert np.abs(mom.cpu().numpy() - want).max() <= 1e-9 * max(1.0, np.abs(want - w).max())
+    g.close()
