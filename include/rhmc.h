@@ -270,9 +270,9 @@ rhmc_status rhmc_set_dslash_variant(rhmc_gauge* g, rhmc_prec prec, int32_t nrhs,
  * The caller draws them (and every other random number) and owns the array.
  *
  * Links evolve in place inside the gauge object: every storage it holds is
- * rewritten by each link update.  All of these entry points need an FP64
- * link storage (FP64-12, FP64-18 or hi/lo) and return RHMC_ERR_UNSUPPORTED
- * without one.  Forces follow one convention: for U_mu(n) -> exp(i eps T)
+ * rewritten by each link update.  All of these entry points but
+ * rhmc_kinetic need an FP64 link storage (FP64-12, FP64-18 or hi/lo) and
+ * return RHMC_ERR_UNSUPPORTED without one.  Forces follow one convention: for U_mu(n) -> exp(i eps T)
  * U_mu(n), dS/deps = i Tr(T F_mu(n)), and a kick of size eps does
  * omega^a -= eps * i Tr(T^a F) (the flow that conserves the Hamiltonian with
  * dU/dtau = i H U). */
