@@ -225,6 +225,51 @@ def run_md_workload(rhmc, torch, dev, ntraj):
     return out
 
 
+def run_md_chain(rhmc, torch, ntraj):
+    """A Markov chain of `ntraj` trajectories of the molecular-dynamics
+    workload from its synthetic start: momenta, pseudofermion sources and the
+    Metropolis numbers drawn on the host (numpy PCG64, seed 123).  Over the
+    second half, <exp(-dH)> must be 1 (the equality that holds at equilibrium
+    for a reversible, area-preserving integrator with an exact Metropolis
+    test)."""
+    import numpy as np
+
+    import synth
+    from synth.make_rational import md_rationals
+
+    w = synth.MD_WORKLOAD
+    L = w["L"]
+    r_hb, r_act, r_md = md_rationals()
+    lat = rhmc.rhmc_lattice_create(L, -1)
+    g = rhmc.rhmc_gauge_create(lat, synth.gauge_field(L, w["eps"], w["seed"]))
+    mdp = rhmc.MDParams(r_md, beta=w["beta"], mass=w["m"], tau=w["tau"], n_md=w["n_md"],
+                        gauge_steps=w["gauge_steps"],
+                        solver=rhmc.solver_params(tol=1e-7, mode=rhmc.RHMC_MODE_MIXED))
+    hp = rhmc.HMCParams(mdp, r_hb, r_act, rhmc.solver_params(tol=1e-10))
+    rng = np.random.default_rng(123)
+    rows = []
+    t0 = time.perf_counter()
+    for k in range(ntraj):
+        R = torch.from_numpy((rng.standard_normal((w["npf"], 3, lat.Vh)) +
+                              1j * rng.standard_normal((w["npf"], 3, lat.Vh))) * np.sqrt(0.5)).cuda()
+        mom = torch.from_numpy(rng.standard_normal((8, 4, 2, lat.Vh))).cuda()
+        st = rhmc.rhmc_trajectory(g, hp, R, mom, float(rng.uniform()), allow_not_converged=True)
+        plaq = 1.0 - rhmc.rhmc_gauge_action(g, 1.0) / (6.0 * lat.V)
+        rows.append((st["dH"], float(st["accepted"]), plaq))
+        if k % 20 == 19:
+            log(f"chain trajectory {k + 1}: plaquette {plaq:.5f}, dH {st['dH']:.4f}")
+    g.close()
+    a = np.array(rows)
+    half = a[len(a) // 2:]
+    e = np.exp(-half[:, 0])
+    return {"trajectories": ntraj, "measured": len(half),
+            "exp_minus_dH_mean": float(e.mean()), "exp_minus_dH_err": float(e.std() / np.sqrt(len(e))),
+            "acceptance": float(half[:, 1].mean()), "plaquette": float(half[:, 2].mean()),
+            "plaquette_err": float(half[:, 2].std() / np.sqrt(len(half))),
+            "seconds": round(time.perf_counter() - t0, 1),
+            "setting": "MIXED MD solves at 1e-7, FP64 Metropolis solves at 1e-10"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -242,6 +287,10 @@ def main():
                     help="skip the molecular-dynamics kernels and the 4x16^3 trajectories")
     ap.add_argument("--only-md", action="store_true",
                     help="only the molecular-dynamics kernels and trajectories (profiler runs)")
+    ap.add_argument("--md-chain", type=int, default=0,
+                    help="run a Markov chain of this many trajectories of the 4x16^3 workload "
+                         "(MIXED MD solves at 1e-7, FP64 Metropolis at 1e-10) and report "
+                         "<exp(-dH)>, acceptance and plaquette over its second half")
     ap.add_argument("--md-trajectories", type=int, default=2,
                     help="timed trajectories per setting of the 4x16^3 workload (after one untimed)")
     ap.add_argument("--only-dslash", action="store_true",
@@ -330,6 +379,8 @@ def main():
         res = {"md_kernels": md_kernel_timings()}
         g.close()
         res["md_trajectory_16x16x16x4"] = run_md_workload(rhmc, torch, dev, args.md_trajectories)
+        if args.md_chain > 0:
+            res["md_chain_16x16x16x4"] = run_md_chain(rhmc, torch, args.md_chain)
         print(json.dumps(res), flush=True)
         return
 
