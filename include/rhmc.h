@@ -380,7 +380,10 @@ typedef struct {
  * has started, the links of g are restored to their values at the start; mom
  * holds the final momenta either way.  R: device complex128
  * [npf][3][V/2], complex Gaussian (parts N(0, 1/2)); mom: device momenta drawn
- * N(0, 1) by the caller; u in [0, 1).  Blocks until done; stats required. */
+ * N(0, 1) by the caller; u in [0, 1).  Blocks until done; stats required.  A
+ * solve that misses its tolerance (heat bath, actions or forces) makes the
+ * call return RHMC_ERR_NOT_CONVERGED after the trajectory is complete, with
+ * the Metropolis decision taken on the values it produced. */
 rhmc_status rhmc_trajectory(rhmc_gauge* g, const rhmc_hmc_params* params, int32_t npf,
                             const void* R, double* mom, double u, rhmc_trajectory_stats* stats,
                             hipStream_t stream);
