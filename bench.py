@@ -56,6 +56,8 @@ def dslash_bytes_per_site(prec: str, nrhs: int) -> int:
     read once, the input vector read once and the output written once."""
     if prec == "fp32":
         return 8 * 48 + nrhs * (24 + 24)
+    if prec == "fp32f":   # FP32-18 links: 72 B per link
+        return 8 * 72 + nrhs * (24 + 24)
     if prec in ("fp64hl", "fp64c"):   # hi/lo FP32-12 planes or FP64-12 links: 96 B per link
         return 8 * 96 + nrhs * (48 + 48)
     return 8 * 144 + nrhs * (48 + 48)
@@ -551,6 +553,14 @@ def main():
     g18.close()
     log(f"hopping fp64 hi/lo x1: {thl * 1e6:.1f} us ({byts_hl / thl / 1e9:.0f} GB/s); "
         f"fp64-18 x1: {t18 * 1e6:.1f} us ({byts18 / t18 / 1e9:.0f} GB/s)")
+    # FP32 operator from FP32-18 links (no reconstruction)
+    gf = rhmc.rhmc_gauge_create(lat, U, flags=rhmc.RHMC_LINKS_FP32_18 | rhmc.RHMC_LINKS_FP64_12)
+    tf1, tf1_min, _ = time_dslash("fp32", 1, args.dslash_reps, gauge=gf)
+    tf4, tf4_min, _ = time_dslash("fp32", nrhs, args.dslash_reps, gauge=gf)
+    gf.close()
+    bf1, bf4 = dslash_bytes_per_site("fp32f", 1) * Vh, dslash_bytes_per_site("fp32f", nrhs) * Vh
+    log(f"hopping fp32-18 x1: {tf1 * 1e6:.1f} us ({bf1 / tf1 / 1e9:.0f} GB/s); "
+        f"x{nrhs}: {tf4 * 1e6:.1f} us ({bf4 / tf4 / 1e9:.0f} GB/s)")
 
     # 16^3x4 (cache resident: 9.4 MB of FP64 links): 1000 standalone FP64 D_oe
     c2 = synth.CONFIGS[2]
@@ -622,6 +632,12 @@ def main():
             "fp64_18_1rhs": {"us_median": round(t18 * 1e6, 2), "us_min": round(t18_min * 1e6, 2),
                              "GBps": round(byts18 / t18 / 1e9, 1),
                              "gflops": round(FLOPS_PER_SITE * Vh / t18 / 1e9, 1)},
+            "fp32_18_1rhs": {"us_median": round(tf1 * 1e6, 2), "us_min": round(tf1_min * 1e6, 2),
+                             "GBps": round(bf1 / tf1 / 1e9, 1),
+                             "gflops": round(FLOPS_PER_SITE * Vh / tf1 / 1e9, 1)},
+            f"fp32_18_{nrhs}rhs": {"us_median": round(tf4 * 1e6, 2), "us_min": round(tf4_min * 1e6, 2),
+                                   "GBps": round(bf4 / tf4 / 1e9, 1),
+                                   "gflops": round(FLOPS_PER_SITE * Vh * nrhs / tf4 / 1e9, 1)},
             "fp64_hilo12_1rhs": {"us_median": round(thl * 1e6, 2), "us_min": round(thl_min * 1e6, 2),
                                  "GBps": round(byts_hl / thl / 1e9, 1),
                                  "gflops": round(FLOPS_PER_SITE * Vh / thl / 1e9, 1)},

@@ -78,6 +78,9 @@ typedef enum { RHMC_PREC_FP64 = 0, RHMC_PREC_FP32 = 1 } rhmc_prec;
  * conj(row1 x row2): the storage of Sec. 4.2 in double precision.  The FP64
  * operator of choice when present (needs the links SU(3) to 1e-12). */
 #define RHMC_LINKS_FP64_12 8u
+/* All 18 reals in FP32 (72 B per link), no reconstruction: an FP32 operator
+ * for links that are not SU(3).  Used when RHMC_LINKS_FP32_12 is absent. */
+#define RHMC_LINKS_FP32_18 16u
 
 typedef enum {
     RHMC_MODE_FP64 = 0,  /* every operator application and vector in FP64 */
@@ -145,9 +148,10 @@ rhmc_status rhmc_debug_neighbors(const rhmc_lattice* lat, int32_t parity, int32_
 /* Upload and pack one gauge field (Sec. 4.2 storage: structure of arrays so that
  * consecutive sites read consecutive memory).  links: host array described
  * above, 4*V*9 complex128.  flags: any of RHMC_LINKS_*; 0 means FP32_12 plus
- * FP64_12, or plus FP64_18 if row 3 of some link differs from conj(row1 x row2)
- * by more than 1e-12.  The FP64 operator uses FP64_12 if stored, else FP64_18,
- * else hi + lo.  12-real storage needs SU(3) links: INVALID_ARG if row 3 is
+ * FP64_12, with FP64_18 instead of FP64_12 if row 3 of some link differs from
+ * conj(row1 x row2) by more than 1e-12 and FP32_18 instead of FP32_12 if by
+ * more than 1e-6.  The FP64 operator uses FP64_12 if stored, else FP64_18,
+ * else hi + lo; the FP32 operator FP32_12 if stored, else FP32_18.  12-real storage needs SU(3) links: INVALID_ARG if row 3 is
  * off by more than 1e-12 (FP64_12) or 1e-6 (FP32_12), or links hold NaN/Inf.
  * The links are copied; the host array may be freed on return. */
 rhmc_status rhmc_gauge_create(const rhmc_lattice* lat, const double* links, uint32_t flags,

@@ -46,7 +46,6 @@ template <typename VT>
 static rhmc_status hop(rhmc_gauge* g, int out_par, rhmc_prec prec, int nrhs, const void* in,
                        void* out, int mode, const void* self, double c, hipStream_t s) {
     const size_t n = (size_t)3 * g->lat.Vh;
-    const int nlinks = (int)(4 * g->lat.V);
     double* partial = g->partial;   // kModeA partial sums nobody reads
     for (int r0 = 0; r0 < nrhs; r0 += kMaxSys) {
         const int cnt = nrhs - r0 < kMaxSys ? nrhs - r0 : kMaxSys;
@@ -65,7 +64,7 @@ static rhmc_status hop(rhmc_gauge* g, int out_par, rhmc_prec prec, int nrhs, con
         if constexpr (std::is_same<VT, double2>::value) {
             RHMC_HIP_TRY(launch_fp64_op(g, a, mode, s));
         } else {
-            RHMC_HIP_TRY(launch_dslash32(g->u32, nlinks, a, mode, s));
+            RHMC_HIP_TRY(launch_fp32_op(g, a, mode, s));
         }
     }
     (void)prec;
@@ -75,7 +74,7 @@ static rhmc_status hop(rhmc_gauge* g, int out_par, rhmc_prec prec, int nrhs, con
 static rhmc_status check_prec(const rhmc_gauge* g, rhmc_prec prec) {
     if (prec == RHMC_PREC_FP64 && !has_fp64_op(g))
         return invalid("gauge object has no FP64 operator (FP64-18 or hi/lo links)");
-    if (prec == RHMC_PREC_FP32 && !g->u32) return invalid("gauge object has no FP32-12 links");
+    if (prec == RHMC_PREC_FP32 && !has_fp32_op(g)) return invalid("gauge object has no FP32 links");
     if (prec != RHMC_PREC_FP64 && prec != RHMC_PREC_FP32) return invalid("unknown precision");
     return RHMC_OK;
 }
@@ -91,7 +90,7 @@ static rhmc_status check_params(const rhmc_solver_params* p, const rhmc_gauge* g
     if (out->reliable_every < 1) return invalid("reliable_every must be >= 1");
     if (!has_fp64_op(g))
         return invalid("solvers need an FP64 operator (FP64-18 or hi/lo links): true residuals are FP64");
-    if (out->mode == RHMC_MODE_MIXED && !g->u32) return invalid("MIXED mode needs the FP32-12 links");
+    if (out->mode == RHMC_MODE_MIXED && !has_fp32_op(g)) return invalid("MIXED mode needs FP32 links");
     return RHMC_OK;
 }
 
@@ -193,13 +192,14 @@ rhmc_status rhmc_gauge_create(const rhmc_lattice* lat, const double* links, uint
     if (!lat || !links || !out) return invalid("null argument");
     *out = nullptr;
     const uint32_t known = RHMC_LINKS_FP64_18 | RHMC_LINKS_FP32_12 | RHMC_LINKS_HILO_12 |
-                           RHMC_LINKS_FP64_12;
+                           RHMC_LINKS_FP64_12 | RHMC_LINKS_FP32_18;
     if (flags & ~known) return invalid("unknown link flags");
     // 12-real storage rebuilds row 3 as conj(row1 x row2), which needs det U = 1
     const double defect = su3_defect(links, (size_t)4 * lat->V);
     if (!std::isfinite(defect)) return invalid("links hold NaN or Inf");
     if (flags == 0) {
-        flags = RHMC_LINKS_FP32_12 | (defect <= kFp64x12Defect ? RHMC_LINKS_FP64_12 : RHMC_LINKS_FP64_18);
+        flags = (defect <= kFp32x12Defect ? RHMC_LINKS_FP32_12 : RHMC_LINKS_FP32_18) |
+                (defect <= kFp64x12Defect ? RHMC_LINKS_FP64_12 : RHMC_LINKS_FP64_18);
     }
     if ((flags & RHMC_LINKS_FP64_12) && defect > kFp64x12Defect)
         return invalid("FP64-12 links need SU(3) input to FP64 accuracy (row 3 = conj(row1 x row2))");
@@ -220,6 +220,8 @@ rhmc_status rhmc_gauge_create(const rhmc_lattice* lat, const double* links, uint
         e = hipMalloc(&g->u64c, nlinks * 6 * sizeof(double2));
     if (e == hipSuccess && (flags & RHMC_LINKS_FP32_12))
         e = hipMalloc(&g->u32, nlinks * (g->hilo ? 6 : 3) * sizeof(float4));
+    if (e == hipSuccess && (flags & RHMC_LINKS_FP32_18))
+        e = hipMalloc(&g->u32f, nlinks * 9 * sizeof(float2));
     if (e == hipSuccess)
         e = hipMalloc(&g->partial, sizeof(double) * kMaxSys * (size_t)dslash_grid((int)lat->Vh));
     if (e == hipSuccess) e = hipMalloc(&canon, nlinks * 9 * sizeof(double2));
@@ -245,6 +247,7 @@ void rhmc_gauge_destroy(rhmc_gauge* g) {
     hipFree(g->u64);
     hipFree(g->u64c);
     hipFree(g->u32);
+    hipFree(g->u32f);
     hipFree(g->tmp_odd);
     hipFree(g->partial);
     delete g;

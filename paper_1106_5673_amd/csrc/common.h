@@ -160,6 +160,7 @@ struct rhmc_gauge {
     double2* u64;  // FP64-18: [9][8*Vh] entry-major, link k = (2*mu + parity)*Vh + eo
     float4* u32;   // FP32-12: [3][8*Vh], rows 1-2 as three float4 per link; with
                    // hilo, [6][8*Vh]: planes 3-5 hold the FP32 remainders (lo)
+    float2* u32f;  // FP32-18: [9][8*Vh] entry-major (no reconstruction)
     int hilo;      // FP64 operator available from hi + lo (no u64 needed)
     void* tmp_odd;           // odd-parity temporary for rhmc_apply_mdagm
     size_t tmp_odd_bytes;
@@ -228,6 +229,10 @@ struct HiLoLink {
 struct Fp64x12Link {
     double2 v;
 };
+// FP32 links with all 18 reals stored.
+struct Fp32x18Link {
+    float2 v;
+};
 hipError_t launch_dslash64c(const Fp64x12Link* u, int nlinks, const DslashArgs<double2>& a,
                             int mode, hipStream_t s);
 hipError_t launch_dslash64hl(const HiLoLink* u, int nlinks, const DslashArgs<double2>& a,
@@ -236,6 +241,17 @@ hipError_t launch_dslash64(const double2* u64, int nlinks, const DslashArgs<doub
                            int mode, hipStream_t s);
 hipError_t launch_dslash32(const float4* u32, int nlinks, const DslashArgs<float2>& a,
                            int mode, hipStream_t s);
+hipError_t launch_dslash32f(const Fp32x18Link* u, int nlinks, const DslashArgs<float2>& a,
+                            int mode, hipStream_t s);
+
+// The FP32 operator of a gauge object: FP32-12 links if stored, else FP32-18.
+inline hipError_t launch_fp32_op(const rhmc_gauge* g, const DslashArgs<float2>& a, int mode,
+                                 hipStream_t s) {
+    const int nlinks = (int)(4 * g->lat.V);
+    if (g->u32) return launch_dslash32(g->u32, nlinks, a, mode, s);
+    return launch_dslash32f(reinterpret_cast<const Fp32x18Link*>(g->u32f), nlinks, a, mode, s);
+}
+inline bool has_fp32_op(const rhmc_gauge* g) { return g->u32 || g->u32f; }
 hipError_t launch_neighbors(const Geom& g, int par, int* nb, int* sign, hipStream_t s);
 
 // The FP64 operator of a gauge object: FP64-12 links if stored, else FP64-18,

@@ -9,7 +9,8 @@ namespace rhmc {
 __global__ __launch_bounds__(kBlock) void k_pack_links(const double2* __restrict__ canon, Geom g,
                                                         double2* __restrict__ u64,
                                                         float4* __restrict__ u32, int hilo,
-                                                        double2* __restrict__ u64c, int nlinks) {
+                                                        double2* __restrict__ u64c,
+                                                        float2* __restrict__ u32f, int nlinks) {
     const int id = blockIdx.x * blockDim.x + threadIdx.x;  // lex * 4 + mu
     const int V = 2 * g.Vh;
     if (id >= 4 * V) return;
@@ -33,6 +34,12 @@ __global__ __launch_bounds__(kBlock) void k_pack_links(const double2* __restrict
     if (u64c) {
 #pragma unroll
         for (int i = 0; i < 6; ++i) u64c[(size_t)i * nlinks + k] = e[i];
+    }
+    if (u32f) {
+        // all 18 reals rounded to nearest FP32
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            u32f[(size_t)i * nlinks + k] = make_float2((float)e[i].x, (float)e[i].y);
     }
     if (u32) {
         // rows 1-2 rounded to nearest FP32; row 3 is rebuilt in the kernel
@@ -60,7 +67,7 @@ hipError_t launch_pack_links(const rhmc_gauge* g, const double2* canon, hipStrea
     const int nlinks = 4 * V;
     const int grid = (4 * V + kBlock - 1) / kBlock;
     hipLaunchKernelGGL(k_pack_links, dim3(grid), dim3(kBlock), 0, s, canon, g->lat.geom, g->u64,
-                       g->u32, g->hilo, g->u64c, nlinks);
+                       g->u32, g->hilo, g->u64c, g->u32f, nlinks);
     return hipGetLastError();
 }
 

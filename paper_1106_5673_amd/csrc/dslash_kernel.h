@@ -32,6 +32,18 @@ __device__ __forceinline__ double2 ldg(const double2* p) {
     }
 }
 
+typedef float f2v __attribute__((ext_vector_type(2)));
+
+template <bool NT>
+__device__ __forceinline__ float2 ldg(const float2* p) {
+    if constexpr (NT) {
+        const f2v v = __builtin_nontemporal_load(reinterpret_cast<const f2v*>(p));
+        return make_float2(v.x, v.y);
+    } else {
+        return *p;
+    }
+}
+
 template <bool NT>
 __device__ __forceinline__ float4 ldg(const float4* p) {
     if constexpr (NT) {
@@ -111,6 +123,19 @@ __device__ __forceinline__ void load_link(const HiLoLink* __restrict__ uh, int n
         L.im[e / 3][e % 3] = w[2 * e + 1];
     }
     rebuild_row3(L);
+}
+
+// FP32 link from 18 stored floats (no reconstruction: any complex 3x3 matrix).
+template <bool NT>
+__device__ __forceinline__ void load_link(const Fp32x18Link* __restrict__ uf, int nlinks, int k,
+                                          Link<float>& L) {
+    const float2* u = reinterpret_cast<const float2*>(uf);
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+        const float2 v = ldg<NT>(u + (size_t)e * nlinks + k);
+        L.re[e / 3][e % 3] = v.x;
+        L.im[e / 3][e % 3] = v.y;
+    }
 }
 
 // FP64 link from 12 stored doubles (rows 1-2), row 3 rebuilt in FP64.

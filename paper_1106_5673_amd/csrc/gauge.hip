@@ -124,7 +124,13 @@ __device__ __forceinline__ void reunitarize(Mat3& U) {
 // the link pack: FP64-18 entry planes, FP64-12 rows 1-2, FP32-12 rows 1-2 and
 // their FP32 remainders for hi + lo).
 __device__ __forceinline__ void store_link(const Mat3& U, int k, int nlinks, double2* u64,
-                                           double2* u64c, float4* u32, int hilo) {
+                                           double2* u64c, float4* u32, int hilo, float2* u32f) {
+    if (u32f) {
+#pragma unroll
+        for (int e = 0; e < 9; ++e)
+            u32f[(size_t)e * nlinks + k] =
+                make_float2((float)U.re[e / 3][e % 3], (float)U.im[e / 3][e % 3]);
+    }
     if (u64) {
 #pragma unroll
         for (int e = 0; e < 9; ++e)
@@ -221,7 +227,7 @@ template <typename LT>
 __global__ __launch_bounds__(kBlock) void k_update_links(const LT* links, int nlinks, double eps,
                                                          const double* __restrict__ mom,
                                                          double2* u64, double2* u64c, float4* u32,
-                                                         int hilo) {
+                                                         int hilo, float2* u32f) {
     const int k = blockIdx.x * kBlock + threadIdx.x;
     if (k >= nlinks) return;
     Mat3 U, H, E, N;
@@ -233,7 +239,7 @@ __global__ __launch_bounds__(kBlock) void k_update_links(const LT* links, int nl
     exp_i(H, E);
     mat_mul<false, false>(E, U, N);
     reunitarize(N);
-    store_link(N, k, nlinks, u64, u64c, u32, hilo);
+    store_link(N, k, nlinks, u64, u64c, u32, hilo, u32f);
 }
 
 // Sum over the sites of this lane of sum_{mu<nu} (1 - Re Tr P / 3); one
@@ -327,7 +333,7 @@ hipError_t launch_gauge_force_mom(const rhmc_gauge* g, double beta, double eps, 
 
 hipError_t launch_update_links(rhmc_gauge* g, double eps, const double* mom, hipStream_t s) {
     const dim3 grid((unsigned)((4 * g->lat.V + kBlock - 1) / kBlock));
-    RHMC_GAUGE_DISPATCH(k_update_links, grid, eps, mom, g->u64, g->u64c, g->u32, g->hilo);
+    RHMC_GAUGE_DISPATCH(k_update_links, grid, eps, mom, g->u64, g->u64c, g->u32, g->hilo, g->u32f);
     return hipGetLastError();
 }
 

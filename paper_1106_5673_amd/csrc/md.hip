@@ -61,8 +61,8 @@ rhmc_status ensure(void** buf, size_t* cap, size_t need) {
 
 // (pointer, bytes) of each link storage of g
 struct Storage {
-    void* p[3];
-    size_t bytes[3];
+    void* p[4];
+    size_t bytes[4];
 };
 Storage storages(const rhmc_gauge* g) {
     const size_t nl = (size_t)4 * g->lat.V;
@@ -73,15 +73,17 @@ Storage storages(const rhmc_gauge* g) {
     st.bytes[1] = g->u64c ? nl * 6 * sizeof(double2) : 0;
     st.p[2] = g->u32;
     st.bytes[2] = g->u32 ? nl * (g->hilo ? 6 : 3) * sizeof(float4) : 0;
+    st.p[3] = g->u32f;
+    st.bytes[3] = g->u32f ? nl * 9 * sizeof(float2) : 0;
     return st;
 }
 
 rhmc_status copy_links(rhmc_gauge* g, MdWork* w, bool save, hipStream_t s) {
     const Storage st = storages(g);
-    size_t total = st.bytes[0] + st.bytes[1] + st.bytes[2];
+    size_t total = st.bytes[0] + st.bytes[1] + st.bytes[2] + st.bytes[3];
     if (save) RHMC_TRY(ensure((void**)&w->backup, &w->backup_bytes, total));
     size_t off = 0;
-    for (int i = 0; i < 3; ++i) {
+    for (int i = 0; i < 4; ++i) {
         if (!st.bytes[i]) continue;
         if (save)
             RHMC_HIP_TRY(hipMemcpyAsync(w->backup + off, st.p[i], st.bytes[i],

@@ -197,7 +197,6 @@ static rhmc_status enqueue_block(const rhmc_gauge* g, Workspace* w, const Proble
                                  bool reliable, hipStream_t s) {
     const size_t n = w->n;
     const int ns = pb.nsys;
-    const int nlinks = (int)(4 * g->lat.V);
     const bool f32 = std::is_same<VT, float2>::value;
 
     DslashArgs<VT> d{};
@@ -224,8 +223,8 @@ static rhmc_status enqueue_block(const rhmc_gauge* g, Workspace* w, const Proble
     set_variant(a, g);
     for (int q = 0; q < pb.K; ++q) {
         if constexpr (std::is_same<VT, float2>::value) {
-            RHMC_HIP_TRY(launch_dslash32(g->u32, nlinks, d, kModeD, s));
-            RHMC_HIP_TRY(launch_dslash32(g->u32, nlinks, a, kModeA, s));
+            RHMC_HIP_TRY(launch_fp32_op(g, d, kModeD, s));
+            RHMC_HIP_TRY(launch_fp32_op(g, a, kModeA, s));
         } else {
             RHMC_HIP_TRY(launch_fp64_op(g, d, kModeD, s));
             RHMC_HIP_TRY(launch_fp64_op(g, a, kModeA, s));

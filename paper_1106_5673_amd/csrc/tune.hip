@@ -29,7 +29,6 @@ void default_hop_variants(int (&v)[2][4]) {
 rhmc_status tune_hop(rhmc_gauge* g, rhmc_prec prec, int nrhs, const void* in, void* out,
                      hipStream_t s) {
     const int cls = nr_class(nrhs);
-    const int nlinks = (int)(4 * g->lat.V);
     const size_t n = (size_t)3 * g->lat.Vh;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     RHMC_HIP_TRY(hipEventCreate(&e0));
@@ -60,7 +59,7 @@ rhmc_status tune_hop(rhmc_gauge* g, rhmc_prec prec, int nrhs, const void* in, vo
                     a.in[r] = reinterpret_cast<const float2*>(in) + r * n;
                     a.out[r] = reinterpret_cast<float2*>(out) + r * n;
                 }
-                err = launch_dslash32(g->u32, nlinks, a, kModeD, s);
+                err = launch_fp32_op(g, a, kModeD, s);
             }
         };
         for (int w = 0; w < 2 && err == hipSuccess; ++w) launch();

@@ -31,6 +31,7 @@ RHMC_LINKS_FP64_18 = 1
 RHMC_LINKS_FP32_12 = 2
 RHMC_LINKS_HILO_12 = 4
 RHMC_LINKS_FP64_12 = 8
+RHMC_LINKS_FP32_18 = 16
 RHMC_MODE_FP64 = 0
 RHMC_MODE_MIXED = 1
 

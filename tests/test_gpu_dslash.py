@@ -291,7 +291,7 @@ def test_fp64_12_links_and_su3_check(rh):
     """FP64-12 storage (rows 1-2, row 3 rebuilt in FP64) gives the FP64-18
     operator to rounding; links that are not SU(3) to 1e-12 are refused for
     it (and default storage falls back to FP64-18), and links far from SU(3)
-    are refused for the 12-real FP32 copy."""
+    are refused for the 12-real FP32 copy (default storage: FP32-18)."""
     import torch
 
     L = (6, 4, 4, 8)
@@ -325,12 +325,20 @@ def test_fp64_12_links_and_su3_check(rh):
     wantb = dirac.dslash(Ub, v, 1, -1)
     assert np.abs(out.cpu().numpy() - wantb).max() <= 1e-13 * np.abs(wantb).max()
     gb.close()
-    # far from SU(3): refused for 12-real FP32 storage, accepted as FP64-18 only
+    # far from SU(3): refused for 12-real FP32 storage; the default storage is
+    # then FP32-18 + FP64-18
     Uc = np.array(U)
     Uc[..., 2, :] *= 1.01
     with pytest.raises(rh.RhmcError):
-        rh.rhmc_gauge_create(lat, Uc)
+        rh.rhmc_gauge_create(lat, Uc, flags=rh.RHMC_LINKS_FP32_12 | rh.RHMC_LINKS_FP64_18)
     rh.rhmc_gauge_create(lat, Uc, flags=rh.RHMC_LINKS_FP64_18).close()
+    gc = rh.rhmc_gauge_create(lat, Uc)
+    v32 = vin[:1].to(torch.complex64).contiguous()
+    o32 = torch.empty_like(v32)
+    rh.rhmc_dslash_eo(gc, 1, rh.RHMC_PREC_FP32, 1, v32, o32)
+    wantc = dirac.dslash(Uc, v32.cpu().numpy().astype(np.complex128), 1, -1)
+    assert np.abs(o32.cpu().numpy() - wantc).max() <= 1e-5 * np.abs(wantc).max()
+    gc.close()
 
 
 def test_max_rhs_and_direct_tuning(rh):
@@ -359,4 +367,60 @@ def test_max_rhs_and_direct_tuning(rh):
     assert 0 <= var < 128
     rh.rhmc_dslash_eo(g, 1, rh.RHMC_PREC_FP32, 4, v32, b)
     assert torch.equal(a, b)
+    g.close()
+
+
+def _non_su3_links(L, seed):
+    """Links that are not SU(3) (an SU(3) field plus 0.3 x complex noise): the
+    staggered D stays anti-Hermitian for any links, so A stays Hermitian."""
+    U = synth.gauge_field(L, 0.6, seed)
+    rng = np.random.default_rng(seed + 1)
+    return U + 0.3 * (rng.standard_normal(U.shape) + 1j * rng.standard_normal(U.shape))
+
+
+@pytest.mark.parametrize("su3", [True, False])
+@pytest.mark.parametrize("nrhs", [1, 4])
+def test_fp32_18_links(rh, su3, nrhs):
+    """FP32-18 storage: the FP32 operator from all 18 reals (no reconstruction),
+    within the FP32 rounding bound of the oracle for SU(3) links and for links
+    that are not SU(3) (which 12-real storage refuses); the default flags
+    choose FP32-18 and FP64-18 for the latter; launch variants give the same bits."""
+    import torch
+
+    L = (6, 4, 4, 8)
+    U = synth.gauge_field(L, 0.7, 4100) if su3 else _non_su3_links(L, 4100)
+    lat = rh.rhmc_lattice_create(L, -1)
+    flags = rh.RHMC_LINKS_FP32_18 | rh.RHMC_LINKS_FP64_18 if su3 else 0
+    g = rh.rhmc_gauge_create(lat, U, flags)
+    if not su3:
+        with pytest.raises(rh.RhmcError):
+            rh.rhmc_gauge_create(lat, U, rh.RHMC_LINKS_FP32_12 | rh.RHMC_LINKS_FP64_18)
+    rng = np.random.default_rng(12)
+    for out_par in (0, 1):
+        v32 = _rand_vec(rng, nrhs, lat.Vh).astype(np.complex64)
+        v = v32.astype(np.complex128)
+        ref = dirac.dslash(U, v, out_par, -1)
+        vin = _to(v32)
+        vout = torch.empty_like(vin)
+        rh.rhmc_dslash_eo(g, out_par, rh.RHMC_PREC_FP32, nrhs, vin, vout)
+        torch.cuda.synchronize()
+        got = vout.cpu().numpy().astype(np.complex128)
+        scale = _abs_scale(U, v, out_par)
+        err = np.abs(got - ref)
+        assert np.all(err.real <= 32 * 2.0 ** -24 * scale + 1e-30)
+        # the FP64 operator on the same gauge object
+        vin64 = _to(v)
+        vout64 = torch.empty_like(vin64)
+        rh.rhmc_dslash_eo(g, out_par, rh.RHMC_PREC_FP64, nrhs, vin64, vout64)
+        torch.cuda.synchronize()
+        assert np.abs(vout64.cpu().numpy() - ref).max() <= 1e-13 * np.abs(ref).max()
+    # every launch variant computes the same bits
+    outs = []
+    for var in (0, 14, 46, 83, 127):
+        rh.rhmc_set_dslash_variant(g, rh.RHMC_PREC_FP32, nrhs, var)
+        vout = torch.empty_like(vin)
+        rh.rhmc_dslash_eo(g, 1, rh.RHMC_PREC_FP32, nrhs, vin, vout)
+        torch.cuda.synchronize()
+        outs.append(vout.cpu().numpy())
+    assert all(np.array_equal(outs[0], o) for o in outs[1:])
     g.close()

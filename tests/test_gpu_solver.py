@@ -282,3 +282,23 @@ def test_per_shift_solver(rh, mode, L, nrhs, shifts):
     it = st1["iterations"]
     assert (it > 0).all() and (it[:, -1] <= it[:, 0]).all()
     g.close()
+
+
+def test_mixed_solve_with_non_su3_links(rh):
+    """Links that are not SU(3): the default storage is FP32-18 + FP64-18 and
+    the MIXED multi-shift solve still meets the oracle's FP64 true residual."""
+    L = (6, 4, 4, 8)
+    U0 = synth.gauge_field(L, 0.6, 9300)
+    rng = np.random.default_rng(9301)
+    U = U0 + 0.3 * (rng.standard_normal(U0.shape) + 1j * rng.standard_normal(U0.shape))
+    b = synth.source(L, 9302, 2)
+    lat = rh.rhmc_lattice_create(L, -1)
+    g = rh.rhmc_gauge_create(lat, U)
+    m = 0.1
+    shifts = [0.0, 0.01, 0.3, 2.0]
+    x, st = _solve(rh, g, lat, m, shifts, b, tol=1e-10, mode=rh.RHMC_MODE_MIXED)
+    A = lambda v: dirac.mdagm(U, m, v)  # noqa: E731
+    for r in range(2):
+        for i, s in enumerate(shifts):
+            assert solvers.true_residual(A, b[r], x[r, i], s) <= 1e-10
+    g.close()
