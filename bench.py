@@ -284,6 +284,8 @@ def main():
     ap.add_argument("--md-tol", type=float, default=1e-7,
                     help="also time MIXED and FP64 at this looser tolerance (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-head-runs", type=int, default=1,
+                    help="timed MIXED solves with no FP64 phase (fp64_head < 0), for comparison")
     ap.add_argument("--no-pf", action="store_true", help="skip the pseudofermion heat bath + action")
     ap.add_argument("--no-md", action="store_true",
                     help="skip the molecular-dynamics kernels and the 4x16^3 trajectories")
@@ -482,6 +484,28 @@ def main():
         t_fp64 = sorted(fp64_times)[len(fp64_times) // 2]
     mixed_times = sorted(s_['time_ms'] / 1e3 for s_ in stats)
 
+    # the same MIXED solve in FP32 from the first iteration (no FP64 phase):
+    # the shifted systems then carry the FP32 rounding of the early steps and
+    # need refinement
+    no_head = None
+    if args.no_head_runs > 0:
+        prm_nh = rhmc.solver_params(tol=c["tol"], mode=rhmc.RHMC_MODE_MIXED, tune=1, fp64_head=-1.0)
+        nh_times = []
+        for k in range(args.no_head_runs):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            st_nh = step(prm_nh)
+            torch.cuda.synchronize()
+            nh_times.append(time.perf_counter() - t1)
+        no_head = {"s": round(sorted(nh_times)[len(nh_times) // 2], 4),
+                   "runs_s": [round(v, 4) for v in nh_times],
+                   "iterations": st_nh["total_iterations"],
+                   "refine_iterations": int(st_nh["refine_iterations"].sum()),
+                   "shifts_refined": int((st_nh["refine_iterations"] > 0).sum()),
+                   "max_true_residual": st_nh["max_true_residual"]}
+        log(f"mixed without the FP64 phase: {no_head['s'] * 1e3:.0f} ms, "
+            f"{no_head['refine_iterations']} refinement iterations")
+
     # the same rational apply at a molecular-dynamics tolerance, where the
     # FP32 operator's shifted-residual gap needs little or no refinement
     md = None
@@ -496,6 +520,7 @@ def main():
             md[name] = round(time.perf_counter() - t1, 4)
             md[name + "_iterations"] = st_md["total_iterations"]
             md[name + "_refine_iterations"] = int(st_md["refine_iterations"].sum())
+            md[name + "_fp64_head_iterations"] = st_md["fp64_head_iterations"]
         log(f"tol {args.md_tol:g}: mixed {md['mixed_batched'] * 1e3:.0f} ms, fp64 {md['fp64'] * 1e3:.0f} ms")
 
     # pseudofermion heat bath phi = r_h(A) R (x^{+1/8}) and action phi^dagger r(A) phi
@@ -667,6 +692,8 @@ def main():
         "refine_rounds": st["refine_rounds"],
         "refine_iterations": int(st["refine_iterations"].sum()),
         "shifts_refined": int((st["refine_iterations"] > 0).sum()),
+        "fp64_head_iterations": st["fp64_head_iterations"],
+        "mixed_batched_without_fp64_phase": no_head,
     }
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")

@@ -108,6 +108,13 @@ typedef struct {
                                ordinary-solver alternative at the end of Sec. 4.3; stats then
                                give each system's own iterations, total_iterations is the
                                largest of them, refine_rounds counts this pass (default 0) */
+    double fp64_head;       /* MIXED shared solve: iterate in FP64 until every right-hand side
+                               has ||r|| <= fp64_head ||b||, then in FP32 with reliable updates.
+                               A shifted solution cannot be restarted (Sec. 4.2), so FP32
+                               rounding made while ||r|| is large stays in it; past the switch
+                               it is scaled down by ||r||/||b||.  0 (default): min(1,
+                               1e3 sqrt(tol)), i.e. 1e-2 at tol 1e-10 and no FP64 phase for
+                               tol >= 1e-6; negative or >= 1: no FP64 phase; NaN is rejected */
 } rhmc_solver_params;
 
 typedef struct {
@@ -121,6 +128,7 @@ typedef struct {
     int32_t refine_rounds;
     double time_ms;             /* host wall time of the call */
     double max_true_residual;
+    int32_t fp64_head_iterations; /* MIXED: iterations of the shared solve run in FP64 */
 } rhmc_solver_stats;
 
 typedef struct {

@@ -88,6 +88,7 @@ static rhmc_status check_params(const rhmc_solver_params* p, const rhmc_gauge* g
     if (out->mode != RHMC_MODE_FP64 && out->mode != RHMC_MODE_MIXED) return invalid("unknown mode");
     if (out->block < 1 || out->block > kMaxBlockLen) return invalid("block must be in 1..32");
     if (out->reliable_every < 1) return invalid("reliable_every must be >= 1");
+    if (std::isnan(out->fp64_head)) return invalid("fp64_head is NaN");
     if (!has_fp64_op(g))
         return invalid("solvers need an FP64 operator (FP64-18 or hi/lo links): true residuals are FP64");
     if (out->mode == RHMC_MODE_MIXED && !has_fp32_op(g)) return invalid("MIXED mode needs FP32 links");
@@ -112,6 +113,7 @@ void rhmc_solver_params_default(rhmc_solver_params* p) {
     p->poll_every = 0;
     p->tune = 0;
     p->per_shift = 0;
+    p->fp64_head = 0.0;
 }
 
 rhmc_status rhmc_lattice_create(const int32_t L[4], int32_t t_bc, rhmc_lattice** out) {

@@ -54,6 +54,14 @@ struct AddArgs {
     double2* y[kMaxSys];
 };
 
+// FP64 -> FP32 copy of up to kMaxSys vectors of n complex numbers (x and y
+// must not overlap)
+struct NarrowArgs {
+    size_t n;
+    const double2* x[kMaxSys];
+    float2* y[kMaxSys];
+};
+
 template <typename VT> hipError_t launch_start(const VecArgs<VT>& a, int nsys, hipStream_t s);
 template <typename VT> hipError_t launch_rupdate(const VecArgs<VT>& a, int nsys, hipStream_t s);
 template <typename VT> hipError_t launch_pupdate(const VecArgs<VT>& a, int nsys, hipStream_t s);
@@ -66,6 +74,7 @@ int vec_blocks(size_t n);
 hipError_t launch_finalize(int kind, void* state, const double* partial, int nblk, int nrhs,
                            double* out_sums, hipStream_t s);
 hipError_t launch_add(const AddArgs& a, int nsys, hipStream_t s);
+hipError_t launch_narrow(const NarrowArgs& a, int nsys, hipStream_t s);
 
 // Re <a_j, b_j> per system, as block partials [nsys][vec_blocks(n)]
 struct DotArgs {

@@ -387,6 +387,16 @@ __global__ __launch_bounds__(kBlock) void k_add(AddArgs a) {
     y.store(a.y[j], i);
 }
 
+// ------------------------------------------------------------------ narrow
+// y = x rounded to FP32 (round to nearest even), one complex number per thread
+__global__ __launch_bounds__(kBlock) void k_narrow(NarrowArgs a) {
+    const int j = blockIdx.y;
+    const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= a.n) return;
+    const double2 v = a.x[j][i];
+    a.y[j][i] = make_float2((float)v.x, (float)v.y);
+}
+
 // ------------------------------------------------------------------ launchers
 static dim3 vec_grid(size_t n, int nsys) {
     return dim3((unsigned)((n / 2 + kBlock - 1) / kBlock), (unsigned)nsys);
@@ -460,6 +470,11 @@ hipError_t launch_dot32(const Dot32Args& a, int nsys, hipStream_t s) {
 }
 hipError_t launch_add(const AddArgs& a, int nsys, hipStream_t s) {
     hipLaunchKernelGGL(k_add, vec_grid(a.n, nsys), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+hipError_t launch_narrow(const NarrowArgs& a, int nsys, hipStream_t s) {
+    const dim3 g((unsigned)((a.n + kBlock - 1) / kBlock), (unsigned)nsys);
+    hipLaunchKernelGGL(k_narrow, g, dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 

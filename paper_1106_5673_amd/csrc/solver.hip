@@ -9,9 +9,10 @@
 // kernels, so the host only polls one flag.  The shifted solutions x_i and
 // directions p_i are updated once per block of K iterations from the stored
 // base residuals (state.h); a block is captured once as a hipGraph and
-// replayed.  MIXED mode iterates in FP32 with 12-real links and every
-// `reliable_every` iterations replaces r by b - (A + sigma_0) x_0 computed in
-// FP64.  At the end every shift's true residual is recomputed in FP64, and a
+// replayed.  MIXED mode iterates in FP64 until every residual is below
+// fp64_head ||b||, then in FP32 with 12-real links, and every
+// `reliable_every` FP32 iterations replaces r by b - (A + sigma_0) x_0
+// computed in FP64.  At the end every shift's true residual is recomputed in FP64, and a
 // shift above tolerance gets a warm-started CG on its own system.
 #include <hip/hip_runtime.h>
 
@@ -66,7 +67,7 @@ struct Workspace {
     SolverState* st = nullptr;     // device
     BlockCoef* coef = nullptr;     // device [kMaxSys][kMaxShift]
     SolverState* hst = nullptr;    // pinned host mirror
-    int* flags_host = nullptr;     // pinned [2]
+    int* flags_host = nullptr;     // pinned [2][2]: all_done, head_done per poll slot
     double* sums_host = nullptr;   // pinned [kMaxSys]
     hipStream_t cap = nullptr;     // capture stream
     hipEvent_t ev[2] = {nullptr, nullptr};
@@ -147,7 +148,7 @@ static rhmc_status ensure_workspace(rhmc_gauge* g, int nsys, int nshift, int K) 
         RHMC_TRY(alloc((void**)&w->st, sizeof(SolverState)));
         RHMC_TRY(alloc((void**)&w->coef, sizeof(BlockCoef) * kMaxSys * kMaxShift));
         RHMC_HIP_TRY(hipHostMalloc((void**)&w->hst, sizeof(SolverState), hipHostMallocDefault));
-        RHMC_HIP_TRY(hipHostMalloc((void**)&w->flags_host, sizeof(int) * 2, hipHostMallocDefault));
+        RHMC_HIP_TRY(hipHostMalloc((void**)&w->flags_host, sizeof(int) * 4, hipHostMallocDefault));
         RHMC_HIP_TRY(hipHostMalloc((void**)&w->sums_host, sizeof(double) * kMaxSys, hipHostMallocDefault));
         RHMC_HIP_TRY(hipStreamCreateWithFlags(&w->cap, hipStreamNonBlocking));
         RHMC_HIP_TRY(hipEventCreateWithFlags(&w->ev[0], hipEventDisableTiming));
@@ -181,6 +182,7 @@ struct Problem {
     double2* X;                   // FP64 solutions
     size_t x_sys, x_shift;        // element strides
     int mode, K, reliable_blocks, maxiter;
+    double head_rel;              // MIXED: FP64 iterations until ||r|| <= head_rel ||b|| (0: none)
     bool use_graph;
     bool tune;
     int poll_every;
@@ -358,10 +360,10 @@ static rhmc_status get_graph(rhmc_gauge* g, Workspace* w, const Problem& pb, boo
     return RHMC_OK;
 }
 
-// Core shared Krylov solve; X receives every shifted solution.
+// Scalar state and r = p = b for a new shared solve whose first blocks
+// iterate in VT.
 template <typename VT>
-static rhmc_status run_krylov(rhmc_gauge* g, const Problem& pb, hipStream_t s, int* iters_out,
-                              int* reliable_out) {
+static rhmc_status krylov_init(rhmc_gauge* g, const Problem& pb, hipStream_t s) {
     RHMC_TRY(ensure_workspace(g, pb.nsys, pb.nshift, pb.K));
     Workspace* w = g->ws;
     const size_t n = w->n;
@@ -374,6 +376,7 @@ static rhmc_status run_krylov(rhmc_gauge* g, const Problem& pb, hipStream_t s, i
     h->coef = w->coef;
     for (int j = 0; j < pb.nsys; ++j) {
         h->sys[j].tolb = pb.tol[j];
+        h->sys[j].head_rr = pb.head_rel;
         h->sys[j].base = pb.base[j];
         for (int i = 0; i < pb.nshift; ++i) {
             ShiftScalars& q = h->sh[j][i];
@@ -407,7 +410,17 @@ static rhmc_status run_krylov(rhmc_gauge* g, const Problem& pb, hipStream_t s, i
                 RHMC_HIP_TRY(hipMemsetAsync(pb.X + j * pb.x_sys + i * pb.x_shift, 0,
                                             n * sizeof(double2), s));
     }
+    return RHMC_OK;
+}
 
+// Replay blocks of K iterations in VT until every system is done or, with
+// `head`, until every system is done or below its head threshold; at most
+// enough blocks for the iterations maxiter leaves.  The host mirror holds the
+// final state on return.
+template <typename VT>
+static rhmc_status krylov_loop(rhmc_gauge* g, const Problem& pb, bool head, hipStream_t s) {
+    Workspace* w = g->ws;
+    SolverState* h = w->hst;
     if (pb.tune) {
         const rhmc_prec pr = std::is_same<VT, float2>::value ? RHMC_PREC_FP32 : RHMC_PREC_FP64;
         if (!g->hop_tuned[pr][nr_class(pb.nsys)])
@@ -418,10 +431,11 @@ static rhmc_status run_krylov(rhmc_gauge* g, const Problem& pb, hipStream_t s, i
         RHMC_TRY(get_graph<VT>(g, w, pb, false, &gb));
         if (pb.mode == RHMC_MODE_MIXED) RHMC_TRY(get_graph<VT>(g, w, pb, true, &gr));
     }
-    const int max_blocks = (pb.maxiter + pb.K - 1) / pb.K + 1;
+    const int left = std::max(0, pb.maxiter - h->iter);
+    const int max_blocks = (left + pb.K - 1) / pb.K + 1;
     int launched = 0;
-    bool done = h->all_done != 0;
-    int pending = -1;  // block index whose flag copy is in flight
+    bool done = h->all_done != 0 || (head && h->head_done != 0);
+    int pending = -1;  // poll slot whose flag copy is in flight
     while (!done && launched < max_blocks) {
         const bool rel = pb.mode == RHMC_MODE_MIXED && ((launched + 1) % pb.reliable_blocks == 0);
         if (pb.use_graph) {
@@ -431,19 +445,83 @@ static rhmc_status run_krylov(rhmc_gauge* g, const Problem& pb, hipStream_t s, i
         }
         ++launched;
         if (launched % pb.poll_every == 0 || launched == max_blocks) {
+            // all_done and head_done are adjacent in SolverState
             const int slot = (launched / pb.poll_every) & 1;
-            RHMC_HIP_TRY(hipMemcpyAsync(&w->flags_host[slot], &w->st->all_done, sizeof(int),
-                                        hipMemcpyDeviceToHost, s));
+            RHMC_HIP_TRY(hipMemcpyAsync(&w->flags_host[2 * slot], &w->st->all_done,
+                                        2 * sizeof(int), hipMemcpyDeviceToHost, s));
             RHMC_HIP_TRY(hipEventRecord(w->ev[slot], s));
             if (pending >= 0) {
                 RHMC_HIP_TRY(hipEventSynchronize(w->ev[pending]));
-                done = w->flags_host[pending] != 0;
+                done = w->flags_host[2 * pending] != 0 ||
+                       (head && w->flags_host[2 * pending + 1] != 0);
             }
             pending = slot;
         }
     }
     RHMC_HIP_TRY(hipMemcpyAsync(h, w->st, sizeof(SolverState), hipMemcpyDeviceToHost, s));
     RHMC_HIP_TRY(hipStreamSynchronize(s));
+    return RHMC_OK;
+}
+
+// Shared Krylov solve in one precision; X receives every shifted solution.
+template <typename VT>
+static rhmc_status run_krylov(rhmc_gauge* g, const Problem& pb, hipStream_t s, int* iters_out,
+                              int* reliable_out) {
+    RHMC_TRY(krylov_init<VT>(g, pb, s));
+    RHMC_TRY(krylov_loop<VT>(g, pb, false, s));
+    *iters_out = g->ws->hst->iter;
+    *reliable_out = g->ws->hst->reliable_count;
+    return RHMC_OK;
+}
+
+// MIXED shared solve.  A shifted solution is never restarted, so the FP32
+// rounding of the operator and of r made while ||r|| is still large stays in
+// it (the reliable updates repair only the base system): with head_rel > 0
+// the solve iterates in FP64 until every system has ||r|| <= head_rel ||b||,
+// then rounds r and p to FP32 at that block boundary and goes on in FP32 with
+// reliable updates from the same scalar state.  The first FP32 step takes the
+// exact line search, as after a residual replacement.
+static rhmc_status run_mixed(rhmc_gauge* g, const Problem& pb, hipStream_t s, int* iters_out,
+                             int* reliable_out, int* head_out) {
+    *head_out = 0;
+    if (!(pb.head_rel > 0.0)) return run_krylov<float2>(g, pb, s, iters_out, reliable_out);
+    Problem ph = pb;
+    ph.mode = RHMC_MODE_FP64;
+    RHMC_TRY(krylov_init<double2>(g, ph, s));
+    RHMC_TRY(krylov_loop<double2>(g, ph, true, s));
+    Workspace* w = g->ws;
+    const SolverState* h = w->hst;
+    *head_out = h->iter;
+    if (!h->all_done) {
+        // r (ring slot j) and p to FP32, through the Ap and t buffers
+        const size_t n = w->n;
+        const int ns = pb.nsys;
+        NarrowArgs nr{}, np{};
+        nr.n = np.n = n;
+        for (int j = 0; j < ns; ++j) {
+            nr.x[j] = vec<double2>(w->ring, n, j);
+            nr.y[j] = vec<float2>(w->Ap, n, j);
+            np.x[j] = vec<double2>(w->p, n, j);
+            np.y[j] = vec<float2>(w->t, n, j);
+        }
+        RHMC_HIP_TRY(launch_narrow(nr, ns, s));
+        RHMC_HIP_TRY(launch_narrow(np, ns, s));
+        RHMC_HIP_TRY(hipMemcpyAsync(w->ring, w->Ap, ns * n * sizeof(float2),
+                                    hipMemcpyDeviceToDevice, s));
+        RHMC_HIP_TRY(hipMemcpyAsync(w->p, w->t, ns * n * sizeof(float2),
+                                    hipMemcpyDeviceToDevice, s));
+        Dot32Args dp{};
+        dp.n = n;
+        dp.partial = w->partial + kMaxSys * w->part_stride;
+        for (int j = 0; j < ns; ++j) {
+            dp.a[j] = vec<float2>(w->ring, n, j);
+            dp.b[j] = vec<float2>(w->p, n, j);
+        }
+        RHMC_HIP_TRY(launch_dot32(dp, ns, s));
+        RHMC_HIP_TRY(launch_finalize(kFinReliableDot, w->st, dp.partial, vec_blocks(n), ns,
+                                     nullptr, s));
+        RHMC_TRY(krylov_loop<float2>(g, pb, false, s));
+    }
     *iters_out = h->iter;
     *reliable_out = h->reliable_count;
     return RHMC_OK;
@@ -497,10 +575,21 @@ static rhmc_status true_residuals(rhmc_gauge* g, const Problem& pb, const std::v
 constexpr double kKrylovMargin = 0.9;
 constexpr double kRefineMargin = 0.8;
 
+// Relative residual at which a MIXED shared solve leaves FP64 (0: no FP64
+// phase).  Automatic: min(1, 1e3 sqrt(tol)), i.e. 1e-2 for tol 1e-10, where
+// the FP32 rounding made after the switch keeps every shift within tol
+// without refinement on rough fields at small mass; no FP64 phase for
+// tol >= 1e-6.
+static double mixed_head(const rhmc_solver_params& prm) {
+    if (prm.mode != RHMC_MODE_MIXED || prm.per_shift) return 0.0;
+    const double h = prm.fp64_head == 0.0 ? std::min(1.0, 1e3 * std::sqrt(prm.tol)) : prm.fp64_head;
+    return (h > 0.0 && h < 1.0) ? h : 0.0;
+}
+
 static rhmc_status solve_impl(rhmc_gauge* g, Problem pb, const rhmc_solver_params& prm,
                               rhmc_solver_stats* stats, hipStream_t s) {
     const auto t0 = std::chrono::steady_clock::now();
-    int iters = 0, rel = 0;
+    int iters = 0, rel = 0, head = 0;
     const bool per_shift = prm.per_shift != 0;
     const int total = pb.nsys * pb.nshift;
     std::vector<int> conv(total), refine_it(total, 0);
@@ -508,7 +597,7 @@ static rhmc_status solve_impl(rhmc_gauge* g, Problem pb, const rhmc_solver_param
     std::vector<double> res(total), res2(total);
     if (!per_shift) {
         if (pb.mode == RHMC_MODE_MIXED)
-            RHMC_TRY(run_krylov<float2>(g, pb, s, &iters, &rel));
+            RHMC_TRY(run_mixed(g, pb, s, &iters, &rel, &head));
         else
             RHMC_TRY(run_krylov<double2>(g, pb, s, &iters, &rel));
         const SolverState hs = *g->ws->hst;
@@ -580,6 +669,7 @@ static rhmc_status solve_impl(rhmc_gauge* g, Problem pb, const rhmc_solver_param
             rp.X = w->rx;
             rp.x_sys = w->n;
             rp.x_shift = 0;
+            rp.head_rel = 0.0;   // one system per shift: reliable updates suffice
             for (int k = 0; k < cnt; ++k) {
                 const int p = chunk[k];
                 const int j = p / pb.nshift, i = p % pb.nshift;
@@ -639,6 +729,7 @@ static rhmc_status solve_impl(rhmc_gauge* g, Problem pb, const rhmc_solver_param
         stats->total_iterations = iters;
         stats->reliable_updates = rel;
         stats->refine_rounds = rounds;
+        stats->fp64_head_iterations = head;
         stats->time_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
         stats->max_true_residual = worst;
     }
@@ -688,6 +779,7 @@ rhmc_status multishift(rhmc_gauge* g, double m, int nshift, const double* shifts
         pb.K = K;
         pb.reliable_blocks = std::max(1, (prm.reliable_every + K - 1) / K);
         pb.maxiter = prm.maxiter;
+        pb.head_rel = mixed_head(prm);
         pb.use_graph = prm.use_graph != 0;
         pb.tune = prm.tune != 0;
         pb.poll_every = prm.poll_every > 0 ? prm.poll_every : 1;
@@ -702,12 +794,14 @@ rhmc_status multishift(rhmc_gauge* g, double m, int nshift, const double* shifts
         acc.total_iterations = std::max(acc.total_iterations, st.total_iterations);
         acc.reliable_updates += st.reliable_updates;
         acc.refine_rounds = std::max(acc.refine_rounds, st.refine_rounds);
+        acc.fp64_head_iterations = std::max(acc.fp64_head_iterations, st.fp64_head_iterations);
         acc.time_ms += st.time_ms;
         acc.max_true_residual = std::max(acc.max_true_residual, st.max_true_residual);
         if (stats) {
             stats->total_iterations = acc.total_iterations;
             stats->reliable_updates = acc.reliable_updates;
             stats->refine_rounds = acc.refine_rounds;
+            stats->fp64_head_iterations = acc.fp64_head_iterations;
             stats->time_ms = acc.time_ms;
             stats->max_true_residual = acc.max_true_residual;
         }
@@ -740,6 +834,8 @@ rhmc_status rational(rhmc_gauge* g, double m, const rhmc_rational* rat, int nrhs
             stats->total_iterations = std::max(stats->total_iterations, st.total_iterations);
             stats->reliable_updates += st.reliable_updates;
             stats->refine_rounds = std::max(stats->refine_rounds, st.refine_rounds);
+            stats->fp64_head_iterations =
+                std::max(stats->fp64_head_iterations, st.fp64_head_iterations);
             stats->time_ms += st.time_ms;
             stats->max_true_residual = std::max(stats->max_true_residual, st.max_true_residual);
         }
@@ -820,6 +916,8 @@ rhmc_status pf_force(rhmc_gauge* g, double m, const rhmc_rational* rat, int nrhs
             stats->total_iterations = std::max(stats->total_iterations, st.total_iterations);
             stats->reliable_updates += st.reliable_updates;
             stats->refine_rounds = std::max(stats->refine_rounds, st.refine_rounds);
+            stats->fp64_head_iterations =
+                std::max(stats->fp64_head_iterations, st.fp64_head_iterations);
             stats->time_ms += st.time_ms;
             stats->max_true_residual = std::max(stats->max_true_residual, st.max_true_residual);
         }

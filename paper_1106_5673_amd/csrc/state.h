@@ -29,6 +29,9 @@ struct SysScalars {
     // systems stay collinear with the base one.
     double alpha_num;
     int replaced;
+    // FP64 head of a MIXED solve: the relative threshold until kFinInit, then
+    // head_rr = (threshold * ||b||)^2; the head ends once rr <= head_rr.
+    double head_rr;
 };
 
 // Numerator of alpha for step q of the current block.
@@ -68,6 +71,7 @@ struct SolverState {
     int nsys, nshift;
     int blk_it;        // iterations completed inside the current block
     int all_done;
+    int head_done;     // every system done or below its head_rr (read with all_done)
     int first_block;   // P = r(k0) and X = 0 (nothing stored yet)
     int iter;          // iterations completed by the shared solve
     int maxiter;
@@ -165,6 +169,7 @@ __device__ inline void solver_finalize(int kind, void* vstate, const double* par
             s.bnorm = sqrt(b2);
             s.tolb = s.tolb * s.bnorm;   // tolb held the relative tolerance until now
             s.rr[0] = s.rr[1] = sums[nsys + tid];
+            s.head_rr = s.head_rr * s.head_rr * b2;
             s.alpha_prev = 1.0;
             s.beta_prev = 0.0;
             s.iters = 0;
@@ -256,9 +261,14 @@ __device__ inline void iteration_update(SolverState* st, const double* partR, in
     }
     __syncthreads();
     if (tid == 0) {
-        int all = 1;
-        for (int j = 0; j < nsys; ++j) all &= st->sys[j].done;
+        int all = 1, head = 1;
+        for (int j = 0; j < nsys; ++j) {
+            const SysScalars& s = st->sys[j];
+            all &= s.done;
+            head &= s.done || s.rr[nxt] <= s.head_rr;
+        }
         st->all_done = all;
+        st->head_done = head;
         st->blk_it += 1;
         st->iter += 1;
     }

@@ -58,14 +58,15 @@ class rhmc_solver_params(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxiter", C.c_int32), ("mode", C.c_int32),
                 ("reliable_every", C.c_int32), ("refine", C.c_int32), ("block", C.c_int32),
                 ("use_graph", C.c_int32), ("poll_every", C.c_int32), ("tune", C.c_int32),
-                ("per_shift", C.c_int32)]
+                ("per_shift", C.c_int32), ("fp64_head", C.c_double)]
 
 
 class rhmc_solver_stats(C.Structure):
     _fields_ = [("iterations", C.POINTER(C.c_int32)), ("true_residual", C.POINTER(C.c_double)),
                 ("refine_iterations", C.POINTER(C.c_int32)), ("total_iterations", C.c_int32),
                 ("reliable_updates", C.c_int32), ("refine_rounds", C.c_int32),
-                ("time_ms", C.c_double), ("max_true_residual", C.c_double)]
+                ("time_ms", C.c_double), ("max_true_residual", C.c_double),
+                ("fp64_head_iterations", C.c_int32)]
 
 
 class rhmc_rational(C.Structure):
@@ -302,6 +303,7 @@ class _Stats:
             refine_rounds=int(self.c.refine_rounds),
             time_ms=float(self.c.time_ms),
             max_true_residual=float(self.c.max_true_residual),
+            fp64_head_iterations=int(self.c.fp64_head_iterations),
         )
 
 

@@ -302,3 +302,38 @@ def test_mixed_solve_with_non_su3_links(rh):
         for i, s in enumerate(shifts):
             assert solvers.true_residual(A, b[r], x[r, i], s) <= 1e-10
     g.close()
+
+
+@pytest.mark.parametrize("head", [0.0, 1e-3])
+def test_mixed_fp64_head(rh, head):
+    """8^4, eps 0.8, m 0.005, 2 rhs, the 20-pole x^-1/4 of the 48^3x12
+    workload, tol 1e-10.  The MIXED shared solve iterates in FP64 until
+    ||r|| <= head ||b|| (0: the automatic 1e-2), then in FP32 with reliable
+    updates.  Every shift must meet tol (oracle FP64 true residual), and the
+    refinement the shifted systems need must fall below that of the same
+    solve in FP32 from the first iteration (fp64_head < 0)."""
+    L = (8, 8, 8, 8)
+    U, b, lat, g = _setup(rh, L, 0.8, 5151, 2, 6151)
+    m = 0.005
+    r = rational_for(4, -0.25)
+    A = lambda v: dirac.mdagm(U, m, v)  # noqa: E731
+    x, st = _solve(rh, g, lat, m, r.beta, b, tol=1e-10, mode=rh.RHMC_MODE_MIXED, fp64_head=head)
+    assert 0 < st["fp64_head_iterations"] < st["total_iterations"]
+    for j in range(2):
+        for i, s in enumerate(r.beta):
+            assert solvers.true_residual(A, b[j], x[j, i], s) <= 1e-10
+    x0, st0 = _solve(rh, g, lat, m, r.beta, b, tol=1e-10, mode=rh.RHMC_MODE_MIXED, fp64_head=-1.0)
+    assert st0["fp64_head_iterations"] == 0
+    print(f"head {head}: FP64 iterations {st['fp64_head_iterations']} of {st['total_iterations']}, "
+          f"refine {int(st['refine_iterations'].sum())} vs {int(st0['refine_iterations'].sum())} "
+          f"without the FP64 phase")
+    assert st["refine_iterations"].sum() < st0["refine_iterations"].sum()
+    # the two solves agree to the accuracy both certify
+    for j in range(2):
+        for i in range(len(r.beta)):
+            kappa = (16.0 + m * m + r.beta[i]) / (m * m + r.beta[i])
+            assert np.linalg.norm(x[j, i] - x0[j, i]) <= 2e-10 * kappa * np.linalg.norm(x0[j, i])
+    with pytest.raises(rh.RhmcError) as e:
+        _solve(rh, g, lat, m, r.beta, b, mode=rh.RHMC_MODE_MIXED, fp64_head=float("nan"))
+    assert e.value.status == rh.RHMC_ERR_INVALID_ARG
+    g.close()
