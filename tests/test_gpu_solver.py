@@ -315,7 +315,8 @@ def test_mixed_fp64_head(rh, head):
     L = (8, 8, 8, 8)
     U, b, lat, g = _setup(rh, L, 0.8, 5151, 2, 6151)
     m = 0.005
-    r = rational_for(4, -0.25)
+    r = rational_for(5, -0.25)
+    assert len(r.beta) == 20 and synth.CONFIGS[5]["m"] == m
     A = lambda v: dirac.mdagm(U, m, v)  # noqa: E731
     x, st = _solve(rh, g, lat, m, r.beta, b, tol=1e-10, mode=rh.RHMC_MODE_MIXED, fp64_head=head)
     assert 0 < st["fp64_head_iterations"] < st["total_iterations"]
