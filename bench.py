@@ -284,6 +284,8 @@ def main():
     ap.add_argument("--md-tol", type=float, default=1e-7,
                     help="also time MIXED and FP64 at this looser tolerance (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--two-pass-runs", type=int, default=1,
+                    help="timed two-pass FP64 rational applies (no shifted vectors)")
     ap.add_argument("--no-head-runs", type=int, default=1,
                     help="timed MIXED solves with no FP64 phase (fp64_head < 0), for comparison")
     ap.add_argument("--no-pf", action="store_true", help="skip the pseudofermion heat bath + action")
@@ -483,6 +485,29 @@ def main():
             log(f"fp64 solve {k}: {fp64_times[-1] * 1e3:.1f} ms, {st64['total_iterations']} iterations")
         t_fp64 = sorted(fp64_times)[len(fp64_times) // 2]
     mixed_times = sorted(s_['time_ms'] / 1e3 for s_ in stats)
+
+    # two-pass FP64 rational apply: no shifted vectors, the base solve twice
+    two_pass = None
+    if args.two_pass_runs > 0:
+        prm_tp = rhmc.solver_params(tol=c["tol"], mode=rhmc.RHMC_MODE_FP64, tune=1, two_pass=1)
+        y_tp = torch.empty_like(y)
+        tp_times = []
+        for k in range(args.two_pass_runs):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            st_tp = rhmc.rhmc_rational_apply(g, m, rat.alpha0, rat.alpha, rat.beta, bd, y_tp, prm_tp)
+            torch.cuda.synchronize()
+            tp_times.append(time.perf_counter() - t1)
+        diff = float(torch.linalg.vector_norm(y_tp - y) / torch.linalg.vector_norm(y))
+        two_pass = {"s": round(sorted(tp_times)[len(tp_times) // 2], 4),
+                    "runs_s": [round(v, 4) for v in tp_times],
+                    "iterations_per_pass": st_tp["total_iterations"],
+                    "max_recurrence_residual": st_tp["max_true_residual"],
+                    # y holds the last one-pass result: FP64 unless those runs were skipped
+                    "rel_diff_vs_one_pass_y": diff,
+                    "one_pass_mode": "fp64" if not args.no_fp64 else "mixed_batched"}
+        del y_tp
+        log(f"two-pass fp64: {two_pass['s'] * 1e3:.0f} ms, |y - y_one_pass| / |y| = {diff:.1e}")
 
     # the same MIXED solve in FP32 from the first iteration (no FP64 phase):
     # the shifted systems then carry the FP32 rounding of the early steps and
@@ -694,6 +719,7 @@ def main():
         "shifts_refined": int((st["refine_iterations"] > 0).sum()),
         "fp64_head_iterations": st["fp64_head_iterations"],
         "mixed_batched_without_fp64_phase": no_head,
+        "rational_apply_two_pass_fp64": two_pass,
     }
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")

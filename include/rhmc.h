@@ -115,6 +115,18 @@ typedef struct {
                                it is scaled down by ||r||/||b||.  0 (default): min(1,
                                1e3 sqrt(tol)), i.e. 1e-2 at tol 1e-10 and no FP64 phase for
                                tol >= 1e-6; negative or >= 1: no FP64 phase; NaN is rejected */
+    int32_t two_pass;       /* nonzero (FP64 mode, rational apply and pseudofermion action only):
+                               a two-pass variant of the shared solve of Sec. 4.3 that the paper
+                               does not describe.  Pass 1 runs the shared Krylov
+                               solve with no shifted vectors and keeps each step's alpha and
+                               beta; the weights w(k) with y = alpha0 b + sum_k w(k) r(k) follow
+                               from them; pass 2 repeats the identical iteration (deterministic
+                               reductions) and accumulates y from the residuals.  Twice the
+                               operator work, no per-shift vectors.  stats->true_residual then
+                               holds the recurrence residual |zeta_i| ||r|| / ||b|| of each shift
+                               (no x_i is formed), and no refinement runs.  UNSUPPORTED with
+                               MIXED; INVALID_ARG with per_shift, rhmc_multishift_cg and the
+                               force entry points (default 0) */
 } rhmc_solver_params;
 
 typedef struct {

@@ -89,6 +89,11 @@ static rhmc_status check_params(const rhmc_solver_params* p, const rhmc_gauge* g
     if (out->block < 1 || out->block > kMaxBlockLen) return invalid("block must be in 1..32");
     if (out->reliable_every < 1) return invalid("reliable_every must be >= 1");
     if (std::isnan(out->fp64_head)) return invalid("fp64_head is NaN");
+    if (out->two_pass && out->mode != RHMC_MODE_FP64) {
+        set_error("two_pass needs mode FP64: a mixed solve needs its shifted solutions for refinement");
+        return RHMC_ERR_UNSUPPORTED;
+    }
+    if (out->two_pass && out->per_shift) return invalid("two_pass and per_shift exclude each other");
     if (!has_fp64_op(g))
         return invalid("solvers need an FP64 operator (FP64-18 or hi/lo links): true residuals are FP64");
     if (out->mode == RHMC_MODE_MIXED && !has_fp32_op(g)) return invalid("MIXED mode needs FP32 links");
@@ -114,6 +119,7 @@ void rhmc_solver_params_default(rhmc_solver_params* p) {
     p->tune = 0;
     p->per_shift = 0;
     p->fp64_head = 0.0;
+    p->two_pass = 0;
 }
 
 rhmc_status rhmc_lattice_create(const int32_t L[4], int32_t t_bc, rhmc_lattice** out) {
@@ -311,6 +317,7 @@ rhmc_status rhmc_multishift_cg(const rhmc_gauge* gc, double m, int32_t nshift,
     RHMC_TRY(check_shifts(m, nshift, shifts));
     rhmc_solver_params prm;
     RHMC_TRY(check_params(params, g, &prm));
+    if (prm.two_pass) return invalid("two_pass forms no shifted solutions: use rhmc_rational_apply");
     RHMC_TRY(use_device(g->device));
     const size_t n = (size_t)3 * g->lat.Vh;
     return multishift(g, m, nshift, shifts, nrhs, reinterpret_cast<const double2*>(b),
@@ -339,6 +346,7 @@ rhmc_status rhmc_rational_apply(const rhmc_gauge* gc, double m, const rhmc_ratio
         stats->refine_rounds = 0;
         stats->time_ms = 0;
         stats->max_true_residual = 0;
+        stats->fp64_head_iterations = 0;
     }
     return rational(g, m, rat, nrhs, reinterpret_cast<const double2*>(b),
                     reinterpret_cast<double2*>(y), prm, stats, stream);
@@ -377,6 +385,7 @@ rhmc_status rhmc_pf_action(const rhmc_gauge* gc, double m, const rhmc_rational* 
         stats->refine_rounds = 0;
         stats->time_ms = 0;
         stats->max_true_residual = 0;
+        stats->fp64_head_iterations = 0;
     }
     return pf_action(g, m, rat, nrhs, reinterpret_cast<const double2*>(phi), S, prm, stats, stream);
 }
@@ -394,6 +403,7 @@ rhmc_status rhmc_pf_force(const rhmc_gauge* gc, double m, const rhmc_rational* r
     RHMC_TRY(check_shifts(m, rat->npole, rat->beta));
     rhmc_solver_params prm;
     RHMC_TRY(check_params(params, g, &prm));
+    if (prm.two_pass) return invalid("two_pass forms no shifted solutions: the force needs them");
     RHMC_TRY(use_device(g->device));
     if (stats) {
         stats->total_iterations = 0;
@@ -401,6 +411,7 @@ rhmc_status rhmc_pf_force(const rhmc_gauge* gc, double m, const rhmc_rational* r
         stats->refine_rounds = 0;
         stats->time_ms = 0;
         stats->max_true_residual = 0;
+        stats->fp64_head_iterations = 0;
     }
     return pf_force(g, m, rat, nrhs, reinterpret_cast<const double2*>(phi),
                     reinterpret_cast<double2*>(force), nullptr, 0.0, prm, stats, stream);
@@ -465,6 +476,7 @@ static rhmc_status check_md(const rhmc_gauge* g, const rhmc_md_params* p, rhmc_m
         return invalid("gauge_steps must be even and in 2..1e5");
     if (!(p->lambda >= 0.0 && p->lambda <= 0.5)) return invalid("lambda must be in [0, 1/2]");
     RHMC_TRY(check_rational(p->mass, p->force_rational));
+    if (p->solver.two_pass) return invalid("two_pass forms no shifted solutions: the force needs them");
     return check_params(&p->solver, g, &out->solver);
 }
 
@@ -499,6 +511,7 @@ rhmc_status rhmc_pf_force_kick(const rhmc_gauge* gc, double m, const rhmc_ration
     RHMC_TRY(check_rational(m, rat));
     rhmc_solver_params prm;
     RHMC_TRY(check_params(params, g, &prm));
+    if (prm.two_pass) return invalid("two_pass forms no shifted solutions: the force needs them");
     RHMC_TRY(use_device(g->device));
     if (stats) {
         stats->total_iterations = 0;
@@ -506,6 +519,7 @@ rhmc_status rhmc_pf_force_kick(const rhmc_gauge* gc, double m, const rhmc_ration
         stats->refine_rounds = 0;
         stats->time_ms = 0;
         stats->max_true_residual = 0;
+        stats->fp64_head_iterations = 0;
     }
     return pf_force(g, m, rat, npf, reinterpret_cast<const double2*>(phi), nullptr, mom, eps, prm,
                     stats, stream);

@@ -35,6 +35,23 @@ struct FlushArgs {
                             // true residuals, and they move only once per block
     double2* X;             // shifted solutions
     size_t x_sys, x_shift;  // element strides of X between systems / shifts
+    // two-pass rational apply, second pass: y_j += sum_l w_j(k0+l) r(k0+l)
+    // over the block's steps (y null: no accumulation)
+    const double* w;        // [nsys][w_stride] weight of each base residual
+    size_t w_stride;
+    double2* y;             // [nsys][n]
+};
+
+// Weights of the two-pass rational apply (one block; state.h hist holds the
+// first pass's per-step scalars).
+struct TwoPassArgs {
+    const void* state;      // SolverState after the first pass
+    const double* hist;     // [nsys][hist_cap][3]: alpha, beta, <r', r'>
+    int hist_cap;
+    double* coef;           // [nsys][nshift][3 * nmax] scratch, then c_i(k) in the first nmax
+    int nmax;               // largest step count of any system
+    double alpha[kMaxShift];  // rational weights
+    double* w;              // [nsys][nmax] output
 };
 
 struct CombineArgs {
@@ -75,6 +92,7 @@ hipError_t launch_finalize(int kind, void* state, const double* partial, int nbl
                            double* out_sums, hipStream_t s);
 hipError_t launch_add(const AddArgs& a, int nsys, hipStream_t s);
 hipError_t launch_narrow(const NarrowArgs& a, int nsys, hipStream_t s);
+hipError_t launch_two_pass_weights(const TwoPassArgs& a, int nsys, int nshift, hipStream_t s);
 
 // Re <a_j, b_j> per system, as block partials [nsys][vec_blocks(n)]
 struct DotArgs {

@@ -284,6 +284,22 @@ __global__ __launch_bounds__(kBlock) void k_flush(FlushArgs<VT> a,
             if (st->sh[j][sh].active) P[((size_t)j * nsh + sh) * a.n + i] = make_double2(pr, pi);
         }
     }
+    if (a.y) {
+        // two-pass rational apply: residuals r(k0)..r(k0+q-1) of this block
+        // (the host checks that this pass repeats the first one; the bound
+        // keeps a mismatch from reading past the weights)
+        const int k0 = st->sys[j].iters - q;
+        const double* wj = a.w + (size_t)j * a.w_stride + k0;
+        double2 yv = a.y[(size_t)j * a.n + i];
+#pragma unroll
+        for (int l = 0; l < Q; ++l)
+            if (l < q && k0 >= 0 && (size_t)(k0 + l) < a.w_stride) {
+                const double wl = wj[l];
+                yv.x += wl * rre[l];
+                yv.y += wl * rim[l];
+            }
+        a.y[(size_t)j * a.n + i] = yv;
+    }
     // the last stored residual is r(k0) of the next block
 #pragma unroll
     for (int l = 1; l <= Q; ++l)
@@ -387,6 +403,56 @@ __global__ __launch_bounds__(kBlock) void k_add(AddArgs a) {
     y.store(a.y[j], i);
 }
 
+// ------------------------------------------------------------------ two-pass weights
+// Two-pass rational apply.  x_i = sum_k c_i(k) r(k) over the steps k < N_i a
+// shift took part in (the shifted recurrences of Sec. 4.3:
+// x_i += a_i p_i, p_i' = zeta_i' r' + b_i p_i, p_i(0) = r(0)):
+//   c_i(k) = zeta_i(k) G_i(k),  G_i(k) = a_i(k) + b_i(k) G_i(k+1),  G_i(N_i) = 0,
+// with zeta_i, a_i = alpha zeta_i(k+1)/zeta_i(k), b_i = beta (zeta_i(k+1)/zeta_i(k))^2
+// rebuilt from the recorded base alpha and beta by the recurrence the solve
+// ran (shift_zeta_next).  One thread per (system, shift).
+__global__ __launch_bounds__(kBlock) void k_two_pass_coef(TwoPassArgs a) {
+    const SolverState* st = reinterpret_cast<const SolverState*>(a.state);
+    const int nsh = st->nshift;
+    const int p = threadIdx.x;
+    if (p >= st->nsys * nsh) return;
+    const int j = p / nsh, i = p % nsh;
+    const ShiftScalars& h = st->sh[j][i];
+    const int N = h.active ? st->sys[j].iters : h.conv_iter;
+    const double* hj = a.hist + (size_t)j * a.hist_cap * 3;
+    double* az = a.coef + (size_t)p * 3 * a.nmax;   // [a_i | b_i | zeta_i], each nmax
+    double zeta = 1.0, zeta_prev = 1.0, alpha_prev = 1.0, beta_prev = 0.0;
+    for (int k = 0; k < N; ++k) {
+        const double alpha = hj[3 * k], beta = hj[3 * k + 1];
+        const double zn = shift_zeta_next(zeta, zeta_prev, alpha, alpha_prev, beta_prev, h.off);
+        const double ratio = zn / zeta;
+        az[k] = alpha * ratio;
+        az[a.nmax + k] = beta * ratio * ratio;
+        az[2 * a.nmax + k] = zeta;
+        zeta_prev = zeta;
+        zeta = zn;
+        alpha_prev = alpha;
+        beta_prev = beta;
+    }
+    double G = 0.0;
+    for (int k = N - 1; k >= 0; --k) {
+        G = az[k] + az[a.nmax + k] * G;
+        az[k] = az[2 * a.nmax + k] * G;   // c_i(k)
+    }
+    for (int k = N; k < a.nmax; ++k) az[k] = 0.0;
+}
+
+// w_j(k) = sum_i alpha_i c_ji(k), summed over i in order.
+__global__ __launch_bounds__(kBlock) void k_two_pass_w(TwoPassArgs a) {
+    const SolverState* st = reinterpret_cast<const SolverState*>(a.state);
+    const int j = blockIdx.y, nsh = st->nshift;
+    const int k = blockIdx.x * kBlock + threadIdx.x;
+    if (k >= a.nmax) return;
+    double w = 0.0;
+    for (int i = 0; i < nsh; ++i) w += a.alpha[i] * a.coef[(size_t)(j * nsh + i) * 3 * a.nmax + k];
+    a.w[(size_t)j * a.nmax + k] = w;
+}
+
 // ------------------------------------------------------------------ narrow
 // y = x rounded to FP32 (round to nearest even), one complex number per thread
 __global__ __launch_bounds__(kBlock) void k_narrow(NarrowArgs a) {
@@ -470,6 +536,13 @@ hipError_t launch_dot32(const Dot32Args& a, int nsys, hipStream_t s) {
 }
 hipError_t launch_add(const AddArgs& a, int nsys, hipStream_t s) {
     hipLaunchKernelGGL(k_add, vec_grid(a.n, nsys), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+hipError_t launch_two_pass_weights(const TwoPassArgs& a, int nsys, int nshift, hipStream_t s) {
+    if (nsys * nshift > kBlock) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_two_pass_coef, dim3(1), dim3(kBlock), 0, s, a);
+    const dim3 g((unsigned)((a.nmax + kBlock - 1) / kBlock), (unsigned)nsys);
+    hipLaunchKernelGGL(k_two_pass_w, g, dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 hipError_t launch_narrow(const NarrowArgs& a, int nsys, hipStream_t s) {

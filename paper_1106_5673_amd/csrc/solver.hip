@@ -38,6 +38,10 @@ struct GraphKey {
     double c[kMaxSys] = {};
     int base[kMaxSys] = {};
     int variants[2][4] = {};
+    int two_pass = 0;
+    const void* wacc = nullptr;
+    const void* yacc = nullptr;
+    size_t w_stride = 0;
     bool operator==(const GraphKey& o) const { return std::memcmp(this, &o, sizeof(*this)) == 0; }
 };
 
@@ -80,6 +84,11 @@ struct Workspace {
     // pseudofermion force: D_oe x_i, [nsys][npole]
     double2* yf = nullptr;
     size_t yf_cap = 0;
+    // two-pass rational apply: per-step scalars, coefficient scratch + weights
+    double* hist = nullptr;
+    size_t hist_cap = 0;
+    double* tp = nullptr;
+    size_t tp_cap = 0;
     CachedGraph graphs[4];
     int graph_next = 0;
 };
@@ -96,7 +105,8 @@ void workspace_destroy(Workspace* w) {
     if (!w) return;
     free_graphs(w);
     for (void* p : {w->ring, w->p, w->Ap, w->t, w->P, (void*)w->t64, (void*)w->rb, (void*)w->rx,
-                    (void*)w->xr, (void*)w->ya, (void*)w->yf, (void*)w->partial, (void*)w->sums,
+                    (void*)w->xr, (void*)w->ya, (void*)w->yf, (void*)w->hist, (void*)w->tp,
+                    (void*)w->partial, (void*)w->sums,
                     (void*)w->st, (void*)w->coef})
         hipFree(p);
     hipHostFree(w->hst);
@@ -183,6 +193,15 @@ struct Problem {
     size_t x_sys, x_shift;        // element strides
     int mode, K, reliable_blocks, maxiter;
     double head_rel;              // MIXED: FP64 iterations until ||r|| <= head_rel ||b|| (0: none)
+    // two-pass rational apply: no shifted vectors (the flush only moves the
+    // residual ring); the first pass records per-step scalars into hist, the
+    // second adds w(k) r(k) into yacc
+    bool two_pass;
+    double* hist;
+    int hist_cap;
+    const double* wacc;
+    size_t w_stride;
+    double2* yacc;
     bool use_graph;
     bool tune;
     int poll_every;
@@ -260,8 +279,11 @@ static rhmc_status enqueue_block(const rhmc_gauge* g, Workspace* w, const Proble
     f.state = w->st;
     f.coef = w->coef;
     f.n = n;
-    f.nshift = pb.nshift;
+    f.nshift = pb.two_pass ? 0 : pb.nshift;
     f.nsys = ns;
+    f.w = pb.wacc;
+    f.w_stride = pb.w_stride;
+    f.y = pb.yacc;
     f.ring = reinterpret_cast<VT*>(w->ring);
     f.P = reinterpret_cast<double2*>(w->P);
     f.X = pb.X;
@@ -334,6 +356,10 @@ static rhmc_status get_graph(rhmc_gauge* g, Workspace* w, const Problem& pb, boo
     k.x = pb.X;
     k.x_sys = pb.x_sys;
     k.x_shift = pb.x_shift;
+    k.two_pass = pb.two_pass;
+    k.wacc = pb.wacc;
+    k.yacc = pb.yacc;
+    k.w_stride = pb.w_stride;
     for (auto& cg : w->graphs)
         if (cg.exec && cg.key == k) {
             *out = cg.exec;
@@ -374,6 +400,8 @@ static rhmc_status krylov_init(rhmc_gauge* g, const Problem& pb, hipStream_t s) 
     h->first_block = 1;
     h->maxiter = pb.maxiter;
     h->coef = w->coef;
+    h->hist = pb.hist;
+    h->hist_cap = pb.hist_cap;
     for (int j = 0; j < pb.nsys; ++j) {
         h->sys[j].tolb = pb.tol[j];
         h->sys[j].head_rr = pb.head_rel;
@@ -405,7 +433,7 @@ static rhmc_status krylov_init(rhmc_gauge* g, const Problem& pb, hipStream_t s) 
             set_error("source holds NaN or Inf");
             return RHMC_ERR_NONFINITE;
         }
-        if (bn == 0.0)
+        if (bn == 0.0 && pb.X)
             for (int i = 0; i < pb.nshift; ++i)
                 RHMC_HIP_TRY(hipMemsetAsync(pb.X + j * pb.x_sys + i * pb.x_shift, 0,
                                             n * sizeof(double2), s));
@@ -745,9 +773,11 @@ static rhmc_status solve_impl(rhmc_gauge* g, Problem pb, const rhmc_solver_param
     return RHMC_OK;
 }
 
-rhmc_status multishift(rhmc_gauge* g, double m, int nshift, const double* shifts, int nrhs,
-                       const double2* b, double2* x, size_t x_sys, size_t x_shift,
-                       const rhmc_solver_params& prm, rhmc_solver_stats* stats, hipStream_t s) {
+// The shared solve of nrhs <= kMaxSys right-hand sides b[j] (stride n) for
+// the shifts, from the Krylov space of the smallest one.
+static Problem make_problem(const rhmc_gauge* g, double m, int nshift, const double* shifts,
+                            int nrhs, const double2* b, double2* x, size_t x_sys, size_t x_shift,
+                            const rhmc_solver_params& prm) {
     const size_t n = (size_t)3 * g->lat.Vh;
     double smin = shifts[0];
     int base = 0;
@@ -756,33 +786,42 @@ rhmc_status multishift(rhmc_gauge* g, double m, int nshift, const double* shifts
             smin = shifts[i];
             base = i;
         }
-    rhmc_solver_stats acc{};
     const int K = std::max(1, std::min(kMaxBlockLen, prm.block));
+    Problem pb{};
+    pb.nsys = nrhs;
+    pb.nshift = nshift;
+    pb.m2 = m * m;
+    for (int j = 0; j < nrhs; ++j) {
+        pb.sigma0[j] = smin;
+        pb.base[j] = base;
+        pb.tol[j] = kKrylovMargin * prm.tol;
+        pb.b[j] = b + (size_t)j * n;
+        for (int i = 0; i < nshift; ++i) pb.off[j][i] = shifts[i] - smin;
+    }
+    pb.X = x;
+    pb.x_sys = x_sys;
+    pb.x_shift = x_shift;
+    pb.mode = prm.mode;
+    pb.K = K;
+    pb.reliable_blocks = std::max(1, (prm.reliable_every + K - 1) / K);
+    pb.maxiter = prm.maxiter;
+    pb.head_rel = mixed_head(prm);
+    pb.use_graph = prm.use_graph != 0;
+    pb.tune = prm.tune != 0;
+    pb.poll_every = prm.poll_every > 0 ? prm.poll_every : 1;
+    return pb;
+}
+
+rhmc_status multishift(rhmc_gauge* g, double m, int nshift, const double* shifts, int nrhs,
+                       const double2* b, double2* x, size_t x_sys, size_t x_shift,
+                       const rhmc_solver_params& prm, rhmc_solver_stats* stats, hipStream_t s) {
+    const size_t n = (size_t)3 * g->lat.Vh;
+    rhmc_solver_stats acc{};
     // process the right-hand sides in groups of kMaxSys
     for (int r0 = 0; r0 < nrhs; r0 += kMaxSys) {
         const int cnt = std::min(kMaxSys, nrhs - r0);
-        Problem pb{};
-        pb.nsys = cnt;
-        pb.nshift = nshift;
-        pb.m2 = m * m;
-        for (int j = 0; j < cnt; ++j) {
-            pb.sigma0[j] = smin;
-            pb.base[j] = base;
-            pb.tol[j] = kKrylovMargin * prm.tol;
-            pb.b[j] = b + (size_t)(r0 + j) * n;
-            for (int i = 0; i < nshift; ++i) pb.off[j][i] = shifts[i] - smin;
-        }
-        pb.X = x + (size_t)r0 * x_sys;
-        pb.x_sys = x_sys;
-        pb.x_shift = x_shift;
-        pb.mode = prm.mode;
-        pb.K = K;
-        pb.reliable_blocks = std::max(1, (prm.reliable_every + K - 1) / K);
-        pb.maxiter = prm.maxiter;
-        pb.head_rel = mixed_head(prm);
-        pb.use_graph = prm.use_graph != 0;
-        pb.tune = prm.tune != 0;
-        pb.poll_every = prm.poll_every > 0 ? prm.poll_every : 1;
+        const Problem pb = make_problem(g, m, nshift, shifts, cnt, b + (size_t)r0 * n,
+                                        x + (size_t)r0 * x_sys, x_sys, x_shift, prm);
         rhmc_solver_stats st{};
         if (stats) {
             st.iterations = stats->iterations ? stats->iterations + (size_t)r0 * nshift : nullptr;
@@ -810,9 +849,120 @@ rhmc_status multishift(rhmc_gauge* g, double m, int nshift, const double* shifts
     return RHMC_OK;
 }
 
+// Two-pass rational apply (FP64), a variant of the shared Krylov solve of
+// Sec. 4.3 that the paper does not describe: y = alpha0 b + sum_i alpha_i x_i
+// (Eq. system_r) with no x_i formed.
+// Pass 1 runs the shared Krylov solve with no shifted vectors and records
+// every step's alpha and beta; with x_i = sum_k c_i(k) r(k) the weights
+// w(k) = sum_i alpha_i c_i(k) follow from those scalars alone
+// (k_two_pass_coef).  Pass 2 repeats the identical iteration (every
+// reduction is deterministic, so the residuals are the same bits) and adds
+// w(k) r(k) to y from the residual ring at each block boundary.  Twice the
+// operator work of the one-pass solve, none of its per-shift vector traffic
+// or memory.  Stats: the per-shift residual is the recurrence's
+// |zeta_i| ||r|| / ||b|| at the shift's last step (no x_i exists to check).
+static rhmc_status rational_two_pass(rhmc_gauge* g, double m, const rhmc_rational* rat, int nrhs,
+                                     const double2* b, double2* y, const rhmc_solver_params& prm,
+                                     rhmc_solver_stats* stats, hipStream_t s) {
+    const size_t n = (size_t)3 * g->lat.Vh;
+    const int np = rat->npole;
+    bool converged = true;
+    for (int r0 = 0; r0 < nrhs; r0 += kMaxSys) {
+        const auto t0 = std::chrono::steady_clock::now();
+        const int cnt = std::min(kMaxSys, nrhs - r0);
+        Problem pb = make_problem(g, m, np, rat->beta, cnt, b + (size_t)r0 * n, nullptr, 0, 0, prm);
+        pb.two_pass = true;
+        RHMC_TRY(ensure_workspace(g, cnt, np, pb.K));
+        Workspace* w = g->ws;
+        const int cap = pb.maxiter + 1;
+        RHMC_TRY(grow(w, (void**)&w->hist, &w->hist_cap, sizeof(double) * 3 * (size_t)cap * cnt));
+        pb.hist = w->hist;
+        pb.hist_cap = cap;
+        RHMC_TRY(krylov_init<double2>(g, pb, s));
+        RHMC_TRY(krylov_loop<double2>(g, pb, false, s));
+        const SolverState s1 = *w->hst;
+        int nmax = 1;
+        for (int j = 0; j < cnt; ++j) nmax = std::max(nmax, s1.sys[j].iters);
+        const size_t coef_n = (size_t)cnt * np * 3 * nmax;
+        RHMC_TRY(grow(w, (void**)&w->tp, &w->tp_cap, sizeof(double) * (coef_n + (size_t)cnt * nmax)));
+        TwoPassArgs ta{};
+        ta.state = w->st;
+        ta.hist = w->hist;
+        ta.hist_cap = cap;
+        ta.coef = w->tp;
+        ta.nmax = nmax;
+        for (int i = 0; i < np; ++i) ta.alpha[i] = rat->alpha[i];
+        ta.w = w->tp + coef_n;
+        RHMC_HIP_TRY(launch_two_pass_weights(ta, cnt, np, s));
+        CombineArgs c{};   // y = alpha0 b
+        c.n = n;
+        c.nterm = 0;
+        c.alpha0 = rat->alpha0;
+        for (int j = 0; j < cnt; ++j) {
+            c.b[j] = b + (size_t)(r0 + j) * n;
+            c.y[j] = y + (size_t)(r0 + j) * n;
+        }
+        RHMC_HIP_TRY(launch_combine(c, cnt, s));
+        Problem p2 = pb;
+        p2.hist = nullptr;
+        p2.hist_cap = 0;
+        p2.wacc = ta.w;
+        p2.w_stride = (size_t)nmax;
+        p2.yacc = y + (size_t)r0 * n;
+        RHMC_TRY(krylov_init<double2>(g, p2, s));
+        RHMC_TRY(krylov_loop<double2>(g, p2, false, s));
+        for (int j = 0; j < cnt; ++j)
+            if (w->hst->sys[j].iters != s1.sys[j].iters) {
+                set_error("two-pass rational apply: the second pass did not repeat the first");
+                return RHMC_ERR_HIP;
+            }
+        // recurrence residual of each shift at its last step
+        std::vector<double> hist((size_t)cnt * nmax * 3);   // [j][nmax][3]
+        RHMC_HIP_TRY(hipMemcpy2DAsync(hist.data(), sizeof(double) * 3 * nmax, w->hist,
+                                      sizeof(double) * 3 * (size_t)cap, sizeof(double) * 3 * nmax,
+                                      cnt, hipMemcpyDeviceToHost, s));
+        RHMC_HIP_TRY(hipStreamSynchronize(s));
+        const auto t1 = std::chrono::steady_clock::now();
+        double worst = 0.0;
+        int iters = 0;
+        for (int j = 0; j < cnt; ++j) {
+            iters = std::max(iters, s1.sys[j].iters);
+            for (int i = 0; i < np; ++i) {
+                const ShiftScalars& q = s1.sh[j][i];
+                const int N = q.active ? s1.sys[j].iters : q.conv_iter;
+                const double bn = s1.sys[j].bnorm;
+                double res = 0.0;
+                if (N > 0 && bn > 0)
+                    res = std::fabs(q.zeta) * std::sqrt(hist[((size_t)j * nmax + N - 1) * 3 + 2]) / bn;
+                if (!(res <= prm.tol)) converged = false;
+                worst = std::max(worst, res);
+                const size_t p = (size_t)(r0 + j) * np + i;
+                if (stats && stats->iterations) stats->iterations[p] = N;
+                if (stats && stats->true_residual) stats->true_residual[p] = res;
+                if (stats && stats->refine_iterations) stats->refine_iterations[p] = 0;
+            }
+        }
+        if (stats) {
+            stats->total_iterations = std::max(stats->total_iterations, iters);
+            stats->time_ms += std::chrono::duration<double, std::milli>(t1 - t0).count();
+            stats->max_true_residual = std::max(stats->max_true_residual, worst);
+        }
+        if (!std::isfinite(worst)) {
+            set_error("solution is not finite");
+            return RHMC_ERR_NONFINITE;
+        }
+    }
+    if (!converged) {
+        set_error("some shift did not reach the requested tolerance");
+        return RHMC_ERR_NOT_CONVERGED;
+    }
+    return RHMC_OK;
+}
+
 rhmc_status rational(rhmc_gauge* g, double m, const rhmc_rational* rat, int nrhs,
                      const double2* b, double2* y, const rhmc_solver_params& prm,
                      rhmc_solver_stats* stats, hipStream_t s) {
+    if (prm.two_pass) return rational_two_pass(g, m, rat, nrhs, b, y, prm, stats, s);
     const size_t n = (size_t)3 * g->lat.Vh;
     const int np = rat->npole;
     const int K = std::max(1, std::min(kMaxBlockLen, prm.block));

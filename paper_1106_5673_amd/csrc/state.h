@@ -34,6 +34,15 @@ struct SysScalars {
     double head_rr;
 };
 
+// zeta_i(k+1) of a shift with offset `off` from the base step's alpha and
+// the previous step's alpha and beta (Sec. 4.3, the shifted-system
+// recurrence; alpha_prev = 1, beta_prev = 0 and zeta = zeta_prev = 1 at k = 0).
+__host__ __device__ inline double shift_zeta_next(double zeta, double zeta_prev, double alpha,
+                                                  double alpha_prev, double beta_prev, double off) {
+    return zeta * zeta_prev * alpha_prev /
+           (zeta_prev * alpha_prev * (1.0 + alpha * off) + alpha * beta_prev * (zeta_prev - zeta));
+}
+
 // Numerator of alpha for step q of the current block.
 __host__ __device__ inline double step_alpha_num(const SysScalars& s, int q) {
     return s.replaced ? s.alpha_num : s.rr[q & 1];
@@ -77,6 +86,11 @@ struct SolverState {
     int maxiter;
     int reliable_count;
     BlockCoef* coef;   // device [kMaxSys][kMaxShift]
+    // When set, every step of system j records (alpha, beta, <r', r'>) at
+    // hist[(j * hist_cap + k) * 3] (k < hist_cap): the scalars the two-pass
+    // rational apply rebuilds its weights from.
+    double* hist;
+    int hist_cap;
     SysScalars sys[kMaxSys];
     ShiftScalars sh[kMaxSys][kMaxShift];
 };
@@ -223,9 +237,7 @@ __device__ inline void iteration_update(SolverState* st, const double* partR, in
         const double alpha = step_alpha_num(s, q_step) / pap_s[j];
         const double beta = rrn_s[j] / rr;
         const double zeta = h.zeta, zeta_prev = h.zeta_prev;
-        const double zn = zeta * zeta_prev * s.alpha_prev /
-                          (zeta_prev * s.alpha_prev * (1.0 + alpha * h.off) +
-                           alpha * s.beta_prev * (zeta_prev - zeta));
+        const double zn = shift_zeta_next(zeta, zeta_prev, alpha, s.alpha_prev, s.beta_prev, h.off);
         const double ratio = zn / zeta;
         const int q = s.blk_steps;   // this step's index inside the block (0-based)
         BlockCoef& bc = st->coef[j * kMaxShift + i];
@@ -252,6 +264,12 @@ __device__ inline void iteration_update(SolverState* st, const double* partR, in
             const double rr = s.rr[cur];
             s.alpha_prev = step_alpha_num(s, q_step) / pap_s[tid];
             s.beta_prev = rrn_s[tid] / rr;
+            if (st->hist && s.iters < st->hist_cap) {
+                double* hp = st->hist + ((size_t)tid * st->hist_cap + s.iters) * 3;
+                hp[0] = s.alpha_prev;
+                hp[1] = s.beta_prev;
+                hp[2] = rrn_s[tid];
+            }
             s.replaced = 0;
             s.rr[nxt] = rrn_s[tid];
             s.iters += 1;

@@ -58,7 +58,7 @@ class rhmc_solver_params(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxiter", C.c_int32), ("mode", C.c_int32),
                 ("reliable_every", C.c_int32), ("refine", C.c_int32), ("block", C.c_int32),
                 ("use_graph", C.c_int32), ("poll_every", C.c_int32), ("tune", C.c_int32),
-                ("per_shift", C.c_int32), ("fp64_head", C.c_double)]
+                ("per_shift", C.c_int32), ("fp64_head", C.c_double), ("two_pass", C.c_int32)]
 
 
 class rhmc_solver_stats(C.Structure):

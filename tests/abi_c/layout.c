@@ -22,6 +22,7 @@ int main(void) {
     FIELD(rhmc_solver_params, tune);
     FIELD(rhmc_solver_params, per_shift);
     FIELD(rhmc_solver_params, fp64_head);
+    FIELD(rhmc_solver_params, two_pass);
 
     SIZE(rhmc_solver_stats);
     FIELD(rhmc_solver_stats, iterations);

@@ -304,26 +304,28 @@ def test_mixed_solve_with_non_su3_links(rh):
     g.close()
 
 
-@pytest.mark.parametrize("head", [0.0, 1e-3])
-def test_mixed_fp64_head(rh, head):
+@pytest.mark.parametrize("head,use_graph,block", [(0.0, 1, 25), (1e-3, 1, 25), (0.0, 0, 7)])
+def test_mixed_fp64_head(rh, head, use_graph, block):
     """8^4, eps 0.8, m 0.005, 2 rhs, the 20-pole x^-1/4 of the 48^3x12
     workload, tol 1e-10.  The MIXED shared solve iterates in FP64 until
     ||r|| <= head ||b|| (0: the automatic 1e-2), then in FP32 with reliable
     updates.  Every shift must meet tol (oracle FP64 true residual), and the
     refinement the shifted systems need must fall below that of the same
-    solve in FP32 from the first iteration (fp64_head < 0)."""
+    solve in FP32 from the first iteration (fp64_head < 0).  Graph replay and
+    eager launches with an odd block length both take the switch."""
     L = (8, 8, 8, 8)
     U, b, lat, g = _setup(rh, L, 0.8, 5151, 2, 6151)
     m = 0.005
     r = rational_for(5, -0.25)
     assert len(r.beta) == 20 and synth.CONFIGS[5]["m"] == m
     A = lambda v: dirac.mdagm(U, m, v)  # noqa: E731
-    x, st = _solve(rh, g, lat, m, r.beta, b, tol=1e-10, mode=rh.RHMC_MODE_MIXED, fp64_head=head)
+    kw = dict(tol=1e-10, mode=rh.RHMC_MODE_MIXED, use_graph=use_graph, block=block)
+    x, st = _solve(rh, g, lat, m, r.beta, b, fp64_head=head, **kw)
     assert 0 < st["fp64_head_iterations"] < st["total_iterations"]
     for j in range(2):
         for i, s in enumerate(r.beta):
             assert solvers.true_residual(A, b[j], x[j, i], s) <= 1e-10
-    x0, st0 = _solve(rh, g, lat, m, r.beta, b, tol=1e-10, mode=rh.RHMC_MODE_MIXED, fp64_head=-1.0)
+    x0, st0 = _solve(rh, g, lat, m, r.beta, b, fp64_head=-1.0, **kw)
     assert st0["fp64_head_iterations"] == 0
     print(f"head {head}: FP64 iterations {st['fp64_head_iterations']} of {st['total_iterations']}, "
           f"refine {int(st['refine_iterations'].sum())} vs {int(st0['refine_iterations'].sum())} "
@@ -337,4 +339,21 @@ def test_mixed_fp64_head(rh, head):
     with pytest.raises(rh.RhmcError) as e:
         _solve(rh, g, lat, m, r.beta, b, mode=rh.RHMC_MODE_MIXED, fp64_head=float("nan"))
     assert e.value.status == rh.RHMC_ERR_INVALID_ARG
+    g.close()
+
+
+def test_mixed_fp64_head_below_tol_is_the_fp64_solve(rh):
+    """With the FP64 phase threshold below tol the phase runs to convergence:
+    the MIXED call then launches exactly the kernels of the plain FP64 solve
+    (deterministic reductions), so the solutions are bit-identical."""
+    L = (6, 4, 4, 8)
+    U, b, lat, g = _setup(rh, L, 0.6, 5252, 3, 6252)
+    m = 0.02
+    shifts = rational_for(1, -0.25).beta
+    x64, st64 = _solve(rh, g, lat, m, shifts, b, tol=1e-10, mode=rh.RHMC_MODE_FP64)
+    xm, stm = _solve(rh, g, lat, m, shifts, b, tol=1e-10, mode=rh.RHMC_MODE_MIXED, fp64_head=1e-12)
+    assert stm["fp64_head_iterations"] == stm["total_iterations"] == st64["total_iterations"]
+    assert stm["reliable_updates"] == 0
+    assert st64["refine_rounds"] == 0 and stm["refine_rounds"] == 0
+    assert np.array_equal(xm, x64)
     g.close()
