@@ -171,8 +171,9 @@ rhmc_status rhmc_debug_neighbors(const rhmc_lattice* lat, int32_t parity, int32_
  * FP64_12, with FP64_18 instead of FP64_12 if row 3 of some link differs from
  * conj(row1 x row2) by more than 1e-12 and FP32_18 instead of FP32_12 if by
  * more than 1e-6.  The FP64 operator uses FP64_12 if stored, else FP64_18,
- * else hi + lo; the FP32 operator FP32_12 if stored, else FP32_18.  12-real storage needs SU(3) links: INVALID_ARG if row 3 is
- * off by more than 1e-12 (FP64_12) or 1e-6 (FP32_12), or links hold NaN/Inf.
+ * else hi + lo; the FP32 operator FP32_12 if stored, else FP32_18.  12-real
+ * storage needs SU(3) links: INVALID_ARG if row 3 is off by more than 1e-12
+ * (FP64_12) or 1e-6 (FP32_12), or links hold NaN/Inf.
  * The links are copied; the host array may be freed on return. */
 rhmc_status rhmc_gauge_create(const rhmc_lattice* lat, const double* links, uint32_t flags,
                               hipStream_t stream, rhmc_gauge** out);

@@ -12,8 +12,8 @@
 // replayed.  MIXED mode iterates in FP64 until every residual is below
 // fp64_head ||b||, then in FP32 with 12-real links, and every
 // `reliable_every` FP32 iterations replaces r by b - (A + sigma_0) x_0
-// computed in FP64.  At the end every shift's true residual is recomputed in FP64, and a
-// shift above tolerance gets a warm-started CG on its own system.
+// computed in FP64.  At the end every shift's true residual is recomputed in
+// FP64, and a shift above tolerance gets a warm-started CG on its own system.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
