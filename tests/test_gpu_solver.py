@@ -167,12 +167,18 @@ def test_unsorted_shifts_and_periodic_time(rh):
     g.close()
 
 
-def test_zero_source_gives_zero(rh):
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_zero_source_gives_zero(rh, mode):
+    """A zero right-hand side beside a nonzero one: done from the start (in
+    MIXED mode through the FP64 phase, the switch, reliable updates and the
+    true-residual check), its solutions exactly zero."""
     L = (4, 4, 4, 4)
     U, b, lat, g = _setup(rh, L, 0.5, 5500, 2, 6500)
     b[1] = 0
-    x, st = _solve(rh, g, lat, 0.1, [0.0, 0.3], b, tol=1e-10)
+    md = rh.RHMC_MODE_FP64 if mode == "fp64" else rh.RHMC_MODE_MIXED
+    x, st = _solve(rh, g, lat, 0.1, [0.0, 0.3], b, tol=1e-10, mode=md)
     assert np.all(x[1] == 0)
+    assert st["true_residual"][1].max() == 0 and st["iterations"][1].max() == 0
     A = lambda v: dirac.mdagm(U, 0.1, v)  # noqa: E731
     assert solvers.true_residual(A, b[0], x[0, 0], 0.0) <= 1e-10
     g.close()
