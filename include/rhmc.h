@@ -124,7 +124,8 @@ typedef struct {
                                reductions) and accumulates y from the residuals.  Twice the
                                operator work, no per-shift vectors.  stats->true_residual then
                                holds the recurrence residual |zeta_i| ||r|| / ||b|| of each shift
-                               (no x_i is formed), and no refinement runs.  UNSUPPORTED with
+                               (no x_i is formed), and no refinement runs; maxiter is capped at
+                               2^22 (24 B of recorded scalars per step and rhs).  UNSUPPORTED with
                                MIXED; INVALID_ARG with per_shift, rhmc_multishift_cg and the
                                force entry points (default 0) */
 } rhmc_solver_params;

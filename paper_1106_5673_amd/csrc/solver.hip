@@ -861,6 +861,8 @@ rhmc_status multishift(rhmc_gauge* g, double m, int nshift, const double* shifts
 // operator work of the one-pass solve, none of its per-shift vector traffic
 // or memory.  Stats: the per-shift residual is the recurrence's
 // |zeta_i| ||r|| / ||b|| at the shift's last step (no x_i exists to check).
+constexpr int kTwoPassMaxIter = 1 << 22;   // 24 B of history per step and system
+
 static rhmc_status rational_two_pass(rhmc_gauge* g, double m, const rhmc_rational* rat, int nrhs,
                                      const double2* b, double2* y, const rhmc_solver_params& prm,
                                      rhmc_solver_stats* stats, hipStream_t s) {
@@ -872,6 +874,7 @@ static rhmc_status rational_two_pass(rhmc_gauge* g, double m, const rhmc_rationa
         const int cnt = std::min(kMaxSys, nrhs - r0);
         Problem pb = make_problem(g, m, np, rat->beta, cnt, b + (size_t)r0 * n, nullptr, 0, 0, prm);
         pb.two_pass = true;
+        pb.maxiter = std::min(pb.maxiter, kTwoPassMaxIter);   // bounds the step history
         RHMC_TRY(ensure_workspace(g, cnt, np, pb.K));
         Workspace* w = g->ws;
         const int cap = pb.maxiter + 1;
