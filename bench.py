@@ -227,13 +227,15 @@ def run_md_workload(rhmc, torch, dev, ntraj):
     return out
 
 
-def run_md_chain(rhmc, torch, ntraj):
+def run_md_chain(rhmc, torch, ntraj, metropolis="fp64"):
     """A Markov chain of `ntraj` trajectories of the molecular-dynamics
     workload from its synthetic start: momenta, pseudofermion sources and the
     Metropolis numbers drawn on the host (numpy PCG64, seed 123).  Over the
     second half, <exp(-dH)> must be 1 (the equality that holds at equilibrium
     for a reversible, area-preserving integrator with an exact Metropolis
-    test)."""
+    test).  `metropolis` sets the precision of the heat-bath and action solves
+    at 1e-10: plain FP64, as the paper requires, or MIXED (FP64 phase, then
+    FP32 with reliable updates, certified by FP64 true residuals)."""
     import numpy as np
 
     import synth
@@ -247,7 +249,8 @@ def run_md_chain(rhmc, torch, ntraj):
     mdp = rhmc.MDParams(r_md, beta=w["beta"], mass=w["m"], tau=w["tau"], n_md=w["n_md"],
                         gauge_steps=w["gauge_steps"],
                         solver=rhmc.solver_params(tol=1e-7, mode=rhmc.RHMC_MODE_MIXED))
-    hp = rhmc.HMCParams(mdp, r_hb, r_act, rhmc.solver_params(tol=1e-10))
+    mode = rhmc.RHMC_MODE_MIXED if metropolis == "mixed" else rhmc.RHMC_MODE_FP64
+    hp = rhmc.HMCParams(mdp, r_hb, r_act, rhmc.solver_params(tol=1e-10, mode=mode))
     rng = np.random.default_rng(123)
     rows = []
     t0 = time.perf_counter()
@@ -269,7 +272,8 @@ def run_md_chain(rhmc, torch, ntraj):
             "acceptance": float(half[:, 1].mean()), "plaquette": float(half[:, 2].mean()),
             "plaquette_err": float(half[:, 2].std() / np.sqrt(len(half))),
             "seconds": round(time.perf_counter() - t0, 1),
-            "setting": "MIXED MD solves at 1e-7, FP64 Metropolis solves at 1e-10"}
+            "setting": f"MIXED MD solves at 1e-7, {metropolis.upper()} Metropolis solves at 1e-10",
+            "dH": [float(v) for v in a[:, 0]]}
 
 
 def main():
@@ -297,6 +301,8 @@ def main():
                     help="run a Markov chain of this many trajectories of the 4x16^3 workload "
                          "(MIXED MD solves at 1e-7, FP64 Metropolis at 1e-10) and report "
                          "<exp(-dH)>, acceptance and plaquette over its second half")
+    ap.add_argument("--md-chain-metropolis", default="fp64", choices=("fp64", "mixed"),
+                    help="precision of the chain's heat-bath and action solves")
     ap.add_argument("--md-trajectories", type=int, default=2,
                     help="timed trajectories per setting of the 4x16^3 workload (after one untimed)")
     ap.add_argument("--only-dslash", action="store_true",
@@ -386,7 +392,7 @@ def main():
         g.close()
         res["md_trajectory_16x16x16x4"] = run_md_workload(rhmc, torch, dev, args.md_trajectories)
         if args.md_chain > 0:
-            res["md_chain_16x16x16x4"] = run_md_chain(rhmc, torch, args.md_chain)
+            res["md_chain_16x16x16x4"] = run_md_chain(rhmc, torch, args.md_chain, args.md_chain_metropolis)
         print(json.dumps(res), flush=True)
         return
 
