@@ -164,9 +164,11 @@ def kernel_entry(t, t_min, nbytes, nflops):
 
 def run_md_workload(rhmc, torch, dev, ntraj):
     """Trajectories of the molecular-dynamics workload (Sec. 4.4 settings) in
-    two precision settings: MD solves MIXED at r_md = 1e-3 with FP64
-    Metropolis solves at r_metro = 1e-9 (the paper's MP_1), and everything
-    FP64 at 1e-9 (D_1).  One untimed trajectory, then `ntraj` timed ones."""
+    three precision settings: MD solves MIXED at r_md = 1e-3 with FP64
+    Metropolis solves at r_metro = 1e-9 (the paper's MP_1), everything FP64 at
+    1e-9 (D_1), and MP_1 with MIXED Metropolis solves (FP64 phase, then FP32,
+    FP64-certified), which the paper rules out for shifted solvers.  One
+    untimed trajectory, then `ntraj` timed ones."""
     import numpy as np
 
     import synth
@@ -181,13 +183,14 @@ def run_md_workload(rhmc, torch, dev, ntraj):
            "poles_md": len(r_md.beta), "poles_metropolis": len(r_act.beta),
            "gauge_field": "synthetic, not thermalised"}
     settings = {
-        "MP1_mixed_md_1e-3_fp64_metropolis_1e-9": (rhmc.RHMC_MODE_MIXED, 1e-3),
-        "D1_fp64_1e-9": (rhmc.RHMC_MODE_FP64, 1e-9),
+        "MP1_mixed_md_1e-3_fp64_metropolis_1e-9": (rhmc.RHMC_MODE_MIXED, 1e-3, rhmc.RHMC_MODE_FP64),
+        "D1_fp64_1e-9": (rhmc.RHMC_MODE_FP64, 1e-9, rhmc.RHMC_MODE_FP64),
+        "mixed_md_1e-3_mixed_metropolis_1e-9": (rhmc.RHMC_MODE_MIXED, 1e-3, rhmc.RHMC_MODE_MIXED),
     }
-    for name, (mode, md_tol) in settings.items():
+    for name, (mode, md_tol, metro_mode) in settings.items():
         lat = rhmc.rhmc_lattice_create(L, -1)
         g = rhmc.rhmc_gauge_create(lat, U)
-        metro = rhmc.solver_params(tol=1e-9, mode=rhmc.RHMC_MODE_FP64)
+        metro = rhmc.solver_params(tol=1e-9, mode=metro_mode)
         mdp = rhmc.MDParams(r_md, beta=w["beta"], mass=w["m"], tau=w["tau"], n_md=w["n_md"],
                             gauge_steps=w["gauge_steps"],
                             solver=rhmc.solver_params(tol=md_tol, mode=mode))
