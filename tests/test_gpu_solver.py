@@ -363,3 +363,27 @@ def test_mixed_fp64_head_below_tol_is_the_fp64_solve(rh):
     assert st64["refine_rounds"] == 0 and stm["refine_rounds"] == 0
     assert np.array_equal(xm, x64)
     g.close()
+
+
+def test_true_residual_check_trips_without_reliable_updates(rh):
+    """Failure detection: a MIXED solve of one system with residual
+    replacement effectively off (and no FP64 phase, no refinement) lets the
+    FP32 recursion report convergence while the true residual has stalled far
+    above tol; the FP64 check must return NOT_CONVERGED with the stalled
+    residual in the statistics.  With replacement every 50 iterations the same
+    solve meets tol (Sec. 4.3, residual replacement)."""
+    L = (8, 8, 8, 6)
+    U, b, lat, g = _setup(rh, L, 0.6, 5901, 1, 6901)
+    m = 0.01
+    kw = dict(tol=1e-10, mode=rh.RHMC_MODE_MIXED, refine=0, fp64_head=-1.0, maxiter=20000)
+    x, st = _solve(rh, g, lat, m, [0.0], b, reliable_every=10**9, allow_not_converged=True, **kw)
+    print(f"no replacement: {st['total_iterations']} iterations, true residual "
+          f"{st['max_true_residual']:.2e}")
+    assert st["status"] == rh.RHMC_ERR_NOT_CONVERGED
+    assert st["reliable_updates"] == 0
+    assert st["max_true_residual"] > 1e-8
+    x, st = _solve(rh, g, lat, m, [0.0], b, reliable_every=50, **kw)
+    assert st["status"] == rh.RHMC_OK and st["reliable_updates"] > 0
+    A = lambda v: dirac.mdagm(U, m, v)  # noqa: E731
+    assert solvers.true_residual(A, b[0], x[0, 0], 0.0) <= 1e-10
+    g.close()
