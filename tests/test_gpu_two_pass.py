@@ -168,3 +168,32 @@ def test_two_pass_not_converged_and_misuse(rh):
         rh.rhmc_pf_force(g, m, r.alpha0, r.alpha, r.beta, _to(b), F, rh.solver_params(two_pass=1))
     assert e.value.status == rh.RHMC_ERR_INVALID_ARG
     g.close()
+
+
+@pytest.mark.parametrize("case", ["one_pole", "periodic", "hilo_links"])
+def test_two_pass_edge_cases(rh, case):
+    """A single pole, a periodic time boundary, and an FP64 operator rebuilt
+    from hi/lo FP32 links: the two-pass apply equals the one-pass apply."""
+    L, m = (6, 4, 4, 8), 0.03
+    t_bc = 1 if case == "periodic" else -1
+    U = synth.gauge_field(L, 0.6, 7601)
+    b = synth.source(L, 7602, 2)
+    lat = rh.rhmc_lattice_create(L, t_bc)
+    flags = rh.RHMC_LINKS_HILO_12 if case == "hilo_links" else 0
+    g = rh.rhmc_gauge_create(lat, U, flags=flags)
+    r0 = rational_for(3, -0.25)
+    if case == "one_pole":
+        r = SimpleNamespace(alpha0=0.0, alpha=np.array([1.0]), beta=np.array([0.0]))
+    else:
+        r = r0
+    y1, st1 = _apply(rh, g, lat, m, r, b, tol=1e-10)
+    y2, st2 = _apply(rh, g, lat, m, r, b, tol=1e-10, two_pass=1)
+    assert st2["total_iterations"] == st1["total_iterations"]
+    for j in range(2):
+        assert np.linalg.norm(y2[j] - y1[j]) <= 1e-11 * np.linalg.norm(y1[j])
+    if case == "one_pole":
+        # y = A^-1 b: its oracle residual is within tol
+        A = lambda v: dirac.mdagm(U, m, v, t_bc)  # noqa: E731
+        for j in range(2):
+            assert solvers.true_residual(A, b[j], y2[j], 0.0) <= 1e-10
+    g.close()
