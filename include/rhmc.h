@@ -97,8 +97,8 @@ typedef struct {
     int32_t reliable_every; /* MIXED: iterations between FP64 residual replacements (default 50) */
     int32_t refine;         /* nonzero: shifts whose FP64 true residual exceeds tol get a
                                warm-started CG on their own system (default 1) */
-    int32_t block;          /* iterations between updates of the shifted solutions (1..32,
-                               default 25; MIXED rounds reliable_every up to a multiple) */
+    int32_t block;          /* iterations between updates of the shifted solutions (1..50,
+                               default 32; MIXED rounds reliable_every up to a multiple) */
     int32_t use_graph;      /* nonzero: replay each block of iterations as a hipGraph (default 1) */
     int32_t poll_every;     /* blocks launched between convergence polls (0 = automatic) */
     int32_t tune;           /* nonzero: time the Dslash launch shapes once and keep the best */

@@ -86,7 +86,7 @@ static rhmc_status check_params(const rhmc_solver_params* p, const rhmc_gauge* g
     if (!(out->tol > 0) || !std::isfinite(out->tol)) return invalid("tol must be positive");
     if (out->maxiter < 1) return invalid("maxiter must be >= 1");
     if (out->mode != RHMC_MODE_FP64 && out->mode != RHMC_MODE_MIXED) return invalid("unknown mode");
-    if (out->block < 1 || out->block > kMaxBlockLen) return invalid("block must be in 1..32");
+    if (out->block < 1 || out->block > kMaxBlockLen) return invalid("block must be in 1..50");
     if (out->reliable_every < 1) return invalid("reliable_every must be >= 1");
     if (std::isnan(out->fp64_head)) return invalid("fp64_head is NaN");
     if (out->two_pass && out->mode != RHMC_MODE_FP64) {
@@ -113,7 +113,7 @@ void rhmc_solver_params_default(rhmc_solver_params* p) {
     p->mode = RHMC_MODE_FP64;
     p->reliable_every = 50;
     p->refine = 1;
-    p->block = 25;
+    p->block = 32;
     p->use_graph = 1;
     p->poll_every = 0;
     p->tune = 0;

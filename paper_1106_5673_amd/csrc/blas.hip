@@ -5,6 +5,8 @@
 //
 // Vectors of a system are flat arrays of n = 3*Vh complex numbers; a thread
 // handles two consecutive complex numbers (one 16-byte load in FP32).
+#include <type_traits>
+
 #include "blas.h"
 #include "state.h"
 
@@ -232,14 +234,19 @@ __global__ __launch_bounds__(kBlock) void k_flush(FlushArgs<VT> a,
     const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
     const int q = st->sys[j].blk_steps;
     if (q == 0 || i >= a.n) return;
-    double rre[Q + 1], rim[Q + 1];
+    // Long blocks keep an FP32 ring in FP32 registers (widened exactly where
+    // used); below 32 steps that form makes the compiler spill, so the
+    // residuals are widened on load instead.
+    using RR = typename std::conditional<std::is_same<VT, float2>::value && (Q >= 32), float,
+                                         double>::type;
+    RR rre[Q + 1], rim[Q + 1];
 #pragma unroll
     for (int l = 0; l <= Q; ++l) {
         rre[l] = rim[l] = 0.0;
         if (l <= q) {
             const VT v = a.ring[((size_t)l * a.nsys + j) * a.n + i];
-            rre[l] = (double)v.x;
-            rim[l] = (double)v.y;
+            rre[l] = v.x;
+            rim[l] = v.y;
         }
     }
     const bool first = st->first_block != 0;
@@ -275,10 +282,10 @@ __global__ __launch_bounds__(kBlock) void k_flush(FlushArgs<VT> a,
 #pragma unroll
             for (int l = 1; l <= Q; ++l) {
                 const double f = bc.f[l], d = bc.d[l];
-                xr += f * rre[l];
-                xi += f * rim[l];
-                pr += d * rre[l];
-                pi += d * rim[l];
+                xr += f * (double)rre[l];
+                xi += f * (double)rim[l];
+                pr += d * (double)rre[l];
+                pi += d * (double)rim[l];
             }
             X[j * a.x_sys + sh * a.x_shift + i] = make_double2(xr, xi);
             if (st->sh[j][sh].active) P[((size_t)j * nsh + sh) * a.n + i] = make_double2(pr, pi);
@@ -295,8 +302,8 @@ __global__ __launch_bounds__(kBlock) void k_flush(FlushArgs<VT> a,
         for (int l = 0; l < Q; ++l)
             if (l < q && k0 >= 0 && (size_t)(k0 + l) < a.w_stride) {
                 const double wl = wj[l];
-                yv.x += wl * rre[l];
-                yv.y += wl * rim[l];
+                yv.x += wl * (double)rre[l];
+                yv.y += wl * (double)rim[l];
             }
         a.y[(size_t)j * a.n + i] = yv;
     }
@@ -517,8 +524,10 @@ hipError_t launch_flush(const FlushArgs<VT>& a, int nsys, int qmax, hipStream_t 
         hipLaunchKernelGGL((k_flush<VT, 20>), g, b, 0, s, a, coef);
     else if (qmax <= 25)
         hipLaunchKernelGGL((k_flush<VT, 25>), g, b, 0, s, a, coef);
-    else
+    else if (qmax <= 32)
         hipLaunchKernelGGL((k_flush<VT, 32>), g, b, 0, s, a, coef);
+    else
+        hipLaunchKernelGGL((k_flush<VT, 50>), g, b, 0, s, a, coef);
     hipLaunchKernelGGL(k_flush_reset, dim3(1), dim3(kBlock), 0, s, a.state);
     return hipGetLastError();
 }

@@ -41,7 +41,7 @@ struct Geom {
 constexpr int kBlock = 256;       // threads per block for every kernel
 constexpr int kMaxSys = 8;        // right-hand sides per operator launch
 constexpr int kMaxShift = 32;
-constexpr int kMaxBlockLen = 32;  // iterations between shifted-solution updates
+constexpr int kMaxBlockLen = 50;  // iterations between shifted-solution updates
 
 #if defined(__HIPCC__)
 // Blocks of a launch are dispatched round-robin over the eight XCDs; give

@@ -44,7 +44,7 @@ def test_status_strings(rh):
 
 def test_params_defaults(rh):
     p = rh.rhmc_solver_params_default()
-    assert p.tol == 1e-10 and p.reliable_every == 50 and p.block == 25 and p.use_graph == 1
+    assert p.tol == 1e-10 and p.reliable_every == 50 and p.block == 32 and p.use_graph == 1
     assert p.maxiter == 100000 and p.mode == rh.RHMC_MODE_FP64 and p.refine == 1
     assert p.per_shift == 0 and p.two_pass == 0 and p.fp64_head == 0.0 and p.tune == 0
 

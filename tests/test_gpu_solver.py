@@ -106,7 +106,7 @@ def test_multishift_true_residuals(rh, mode, L, nrhs):
     g.close()
 
 
-@pytest.mark.parametrize("block,use_graph", [(1, 1), (3, 0), (7, 1), (16, 1), (20, 0), (32, 1)])
+@pytest.mark.parametrize("block,use_graph", [(1, 1), (3, 0), (7, 1), (16, 1), (20, 0), (32, 1), (41, 0), (50, 1)])
 def test_block_lengths_and_graph(rh, block, use_graph):
     L = (8, 8, 8, 6)
     m = 0.03
