@@ -45,6 +45,8 @@ struct GraphKey {
     bool operator==(const GraphKey& o) const { return std::memcmp(this, &o, sizeof(*this)) == 0; }
 };
 
+constexpr int kGraphSlots = 12;
+
 struct CachedGraph {
     GraphKey key;
     hipGraphExec_t exec = nullptr;
@@ -89,7 +91,9 @@ struct Workspace {
     size_t hist_cap = 0;
     double* tp = nullptr;
     size_t tp_cap = 0;
-    CachedGraph graphs[4];
+    // a MIXED call replays up to seven graphs (FP64 phase; FP32 with and
+    // without replacement; the same two per refinement chunk of up to 8 systems)
+    CachedGraph graphs[kGraphSlots];
     int graph_next = 0;
 };
 
@@ -366,7 +370,7 @@ static rhmc_status get_graph(rhmc_gauge* g, Workspace* w, const Problem& pb, boo
             return RHMC_OK;
         }
     CachedGraph& slot = w->graphs[w->graph_next];
-    w->graph_next = (w->graph_next + 1) % 4;
+    w->graph_next = (w->graph_next + 1) % kGraphSlots;
     if (slot.exec) hipGraphExecDestroy(slot.exec);
     slot.exec = nullptr;
     hipGraph_t graph = nullptr;
