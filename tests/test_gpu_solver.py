@@ -387,3 +387,19 @@ def test_true_residual_check_trips_without_reliable_updates(rh):
     A = lambda v: dirac.mdagm(U, m, v)  # noqa: E731
     assert solvers.true_residual(A, b[0], x[0, 0], 0.0) <= 1e-10
     g.close()
+
+
+def test_invalid_solver_params_rejected(rh):
+    L = (4, 4, 4, 4)
+    U, b, lat, g = _setup(rh, L, 0.5, 5950, 1, 6950)
+    bad = [dict(block=0), dict(block=51), dict(reliable_every=0), dict(maxiter=0), dict(tol=0.0),
+           dict(tol=float("nan")), dict(mode=7)]
+    for kw in bad:
+        with pytest.raises(rh.RhmcError) as e:
+            _solve(rh, g, lat, 0.1, [0.0, 0.2], b, **kw)
+        assert e.value.status == rh.RHMC_ERR_INVALID_ARG, kw
+    # the bounds themselves are accepted
+    for kw in (dict(block=1), dict(block=50, mode=rh.RHMC_MODE_MIXED)):
+        x, st = _solve(rh, g, lat, 0.1, [0.0, 0.2], b, tol=1e-10, **kw)
+        assert st["max_true_residual"] <= 1e-10
+    g.close()
