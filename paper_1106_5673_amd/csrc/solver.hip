@@ -74,6 +74,7 @@ struct Workspace {
     BlockCoef* coef = nullptr;     // device [kMaxSys][kMaxShift]
     SolverState* hst = nullptr;    // pinned host mirror
     int* flags_host = nullptr;     // pinned [2][2]: all_done, head_done per poll slot
+    double* ratio_host = nullptr;  // pinned [2]: conv_ratio per poll slot
     double* sums_host = nullptr;   // pinned [kMaxSys]
     hipStream_t cap = nullptr;     // capture stream
     hipEvent_t ev[2] = {nullptr, nullptr};
@@ -115,6 +116,7 @@ void workspace_destroy(Workspace* w) {
         hipFree(p);
     hipHostFree(w->hst);
     hipHostFree(w->flags_host);
+    hipHostFree(w->ratio_host);
     hipHostFree(w->sums_host);
     if (w->cap) hipStreamDestroy(w->cap);
     for (auto& e : w->ev)
@@ -163,6 +165,7 @@ static rhmc_status ensure_workspace(rhmc_gauge* g, int nsys, int nshift, int K) 
         RHMC_TRY(alloc((void**)&w->coef, sizeof(BlockCoef) * kMaxSys * kMaxShift));
         RHMC_HIP_TRY(hipHostMalloc((void**)&w->hst, sizeof(SolverState), hipHostMallocDefault));
         RHMC_HIP_TRY(hipHostMalloc((void**)&w->flags_host, sizeof(int) * 4, hipHostMallocDefault));
+        RHMC_HIP_TRY(hipHostMalloc((void**)&w->ratio_host, sizeof(double) * 2, hipHostMallocDefault));
         RHMC_HIP_TRY(hipHostMalloc((void**)&w->sums_host, sizeof(double) * kMaxSys, hipHostMallocDefault));
         RHMC_HIP_TRY(hipStreamCreateWithFlags(&w->cap, hipStreamNonBlocking));
         RHMC_HIP_TRY(hipEventCreateWithFlags(&w->ev[0], hipEventDisableTiming));
@@ -467,7 +470,8 @@ static rhmc_status krylov_loop(rhmc_gauge* g, const Problem& pb, bool head, hipS
     const int max_blocks = (left + pb.K - 1) / pb.K + 1;
     int launched = 0;
     bool done = h->all_done != 0 || (head && h->head_done != 0);
-    int pending = -1;  // poll slot whose flag copy is in flight
+    int pending = -1;         // poll slot whose flag copy is in flight
+    double prev_ratio = -1.0; // conv_ratio at the previous poll read
     while (!done && launched < max_blocks) {
         const bool rel = pb.mode == RHMC_MODE_MIXED && ((launched + 1) % pb.reliable_blocks == 0);
         if (pb.use_graph) {
@@ -481,11 +485,26 @@ static rhmc_status krylov_loop(rhmc_gauge* g, const Problem& pb, bool head, hipS
             const int slot = (launched / pb.poll_every) & 1;
             RHMC_HIP_TRY(hipMemcpyAsync(&w->flags_host[2 * slot], &w->st->all_done,
                                         2 * sizeof(int), hipMemcpyDeviceToHost, s));
+            RHMC_HIP_TRY(hipMemcpyAsync(&w->ratio_host[slot], &w->st->conv_ratio, sizeof(double),
+                                        hipMemcpyDeviceToHost, s));
             RHMC_HIP_TRY(hipEventRecord(w->ev[slot], s));
             if (pending >= 0) {
                 RHMC_HIP_TRY(hipEventSynchronize(w->ev[pending]));
                 done = w->flags_host[2 * pending] != 0 ||
                        (head && w->flags_host[2 * pending + 1] != 0);
+                const double ratio = w->ratio_host[pending];
+                // With the residual falling by f per poll interval, the blocks
+                // in flight reach tolerance when ratio * f <= 1: wait for them
+                // rather than queue another block that would only early-exit.
+                if (!done && !head && prev_ratio > 0.0 && ratio < prev_ratio &&
+                    ratio * (ratio / prev_ratio) <= 1.0) {
+                    RHMC_HIP_TRY(hipEventSynchronize(w->ev[slot]));
+                    done = w->flags_host[2 * slot] != 0;
+                    prev_ratio = w->ratio_host[slot];
+                    pending = -1;
+                    continue;
+                }
+                prev_ratio = ratio;
             }
             pending = slot;
         }

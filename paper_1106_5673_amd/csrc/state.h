@@ -91,6 +91,10 @@ struct SolverState {
     // rational apply rebuilds its weights from.
     double* hist;
     int hist_cap;
+    // largest rr / tolb^2 over the systems still iterating (0 once all are
+    // done): the host extrapolates it to stop launching blocks once the one
+    // in flight should finish the solve
+    double conv_ratio;
     SysScalars sys[kMaxSys];
     ShiftScalars sh[kMaxSys][kMaxShift];
 };
@@ -280,13 +284,16 @@ __device__ inline void iteration_update(SolverState* st, const double* partR, in
     __syncthreads();
     if (tid == 0) {
         int all = 1, head = 1;
+        double ratio = 0.0;
         for (int j = 0; j < nsys; ++j) {
             const SysScalars& s = st->sys[j];
             all &= s.done;
             head &= s.done || s.rr[nxt] <= s.head_rr;
+            if (!s.done && s.tolb > 0.0) ratio = fmax(ratio, s.rr[nxt] / (s.tolb * s.tolb));
         }
         st->all_done = all;
         st->head_done = head;
+        st->conv_ratio = ratio;
         st->blk_it += 1;
         st->iter += 1;
     }
