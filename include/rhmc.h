@@ -154,7 +154,8 @@ typedef struct {
 /* Fills the documented defaults. */
 void rhmc_solver_params_default(rhmc_solver_params* p);
 
-/* Lattice geometry (Sec. 2): L = {Lx, Ly, Lz, Lt}, each even and >= 2, V <= 2^28.
+/* Lattice geometry (Sec. 2): L = {Lx, Ly, Lz, Lt}, each even and >= 2, V <= 2^26
+ * (the kernels address a link plane of 4V entries with 32-bit byte offsets).
  * t_bc is +1 or -1.  *out must be released with rhmc_lattice_destroy. */
 rhmc_status rhmc_lattice_create(const int32_t L[4], int32_t t_bc, rhmc_lattice** out);
 void rhmc_lattice_destroy(rhmc_lattice* lat);
@@ -259,8 +260,8 @@ rhmc_status rhmc_pf_force(const rhmc_gauge* g, double m, const rhmc_rational* ra
                           rhmc_solver_stats* stats, hipStream_t stream);
 
 /* Autotuner of the hopping kernel (the batching form's launch shapes): times
- * every launch variant (site processing order, non-temporal link loads, loads
- * of one or two hops per batch) of one application D_oe on the given vectors
+ * every launch variant (site processing order, hops per load batch, rows staged
+ * in LDS per block) of one application D_oe on the given vectors
  * and keeps the fastest for this precision and rhs count in the gauge object;
  * later calls of every entry point use it.  in: device [nrhs][3][Vh] even
  * sites; out: device [nrhs][3][Vh], overwritten.  Blocks until timed.
@@ -270,16 +271,18 @@ rhmc_status rhmc_tune_dslash(rhmc_gauge* g, rhmc_prec prec, int32_t nrhs, const 
 
 /* The launch variant the hopping kernel currently uses for this precision and
  * rhs count (the measured default, or the autotuner's choice), for reports:
- * variant (host int32) = order | nt << 2 | batch << 3 | occ << 5, with order the
- * site processing order 0..3 (0 even-odd index, 1 x,y,t,z, 2 and 3 z-tiles of 4
- * and 2 planes with t inside a tile), nt non-temporal link loads, batch the
- * number of hops whose loads are issued together (1, 2, 4, 8 for 0..3) and occ
- * a cap on resident workgroups per CU (none, 5, 4, 3). */
+ * variant (host int32) = order + 8 * batch + 24 * stage, with order the site
+ * processing order 0..7 (0 even-odd index; 1..7 z-tiles of 1, 2, 4, 6, 8, 3, 12
+ * planes with t inside a tile, a tile that does not divide Lz read as 1), batch
+ * the number of hops whose loads are issued together (1, 2, 4 for 0..2) and
+ * stage the rows of an xy-plane a block stages in LDS for its +-x and +-y hops
+ * (0 none, 1 the fewest, 2 the most rows that fit: whole waves of 64..512 sites
+ * and 48 KB of LDS; none where no row count fits). */
 rhmc_status rhmc_dslash_variant(const rhmc_gauge* g, rhmc_prec prec, int32_t nrhs,
                                 int32_t* variant);
 
 /* Pin the launch variant of the hopping kernel for this precision and rhs
- * count (0 <= variant < 128, layout as above).  Every variant computes the
+ * count (0 <= variant < 72, layout as above).  Every variant computes the
  * same result bit for bit; they differ only in speed.  Marks the class as
  * tuned, so tune = 1 in later solver calls keeps it. */
 rhmc_status rhmc_set_dslash_variant(rhmc_gauge* g, rhmc_prec prec, int32_t nrhs,

@@ -130,7 +130,8 @@ rhmc_status rhmc_lattice_create(const int32_t L[4], int32_t t_bc, rhmc_lattice**
         if (L[i] < 2 || (L[i] & 1)) return invalid("every lattice extent must be even and >= 2");
         V *= L[i];
     }
-    if (V > (int64_t(1) << 28)) return invalid("lattice volume above 2^28 sites");
+    // 32-bit byte offsets within a link plane (8 * Vh entries of up to 16 B)
+    if (V > (int64_t(1) << 26)) return invalid("lattice volume above 2^26 sites");
     if (t_bc != 1 && t_bc != -1) return invalid("t_bc must be +1 or -1");
     rhmc_lattice* lat = new (std::nothrow) rhmc_lattice();
     if (!lat) return RHMC_ERR_OOM;
@@ -149,6 +150,7 @@ rhmc_status rhmc_lattice_create(const int32_t L[4], int32_t t_bc, rhmc_lattice**
     g.sz = g.hx * L[1];
     g.st = g.hx * L[1] * L[2];
     g.tbc = t_bc;
+    geom_init_divs(g);
     *out = lat;
     return RHMC_OK;
 }
@@ -231,7 +233,7 @@ rhmc_status rhmc_gauge_create(const rhmc_lattice* lat, const double* links, uint
     if (e == hipSuccess && (flags & RHMC_LINKS_FP32_18))
         e = hipMalloc(&g->u32f, nlinks * 9 * sizeof(float2));
     if (e == hipSuccess)
-        e = hipMalloc(&g->partial, sizeof(double) * kMaxSys * (size_t)dslash_grid((int)lat->Vh));
+        e = hipMalloc(&g->partial, sizeof(double) * kMaxSys * (size_t)max_hop_grid((int)lat->Vh));
     if (e == hipSuccess) e = hipMalloc(&canon, nlinks * 9 * sizeof(double2));
     if (e == hipSuccess)
         e = hipMemcpyAsync(canon, links, nlinks * 9 * sizeof(double2), hipMemcpyHostToDevice, stream);
@@ -440,7 +442,7 @@ rhmc_status rhmc_set_dslash_variant(rhmc_gauge* g, rhmc_prec prec, int32_t nrhs,
                                     int32_t variant) {
     if (!g) return invalid("null argument");
     if (nrhs < 1 || nrhs > 64) return invalid("nrhs must be in 1..64");
-    if (variant < 0 || variant >= kHopVariants) return invalid("variant must be in 0..127");
+    if (variant < 0 || variant >= kHopVariants) return invalid("variant must be in 0..71");
     RHMC_TRY(check_prec(g, prec));
     const int cls = nr_class(nrhs < kMaxSys ? nrhs : kMaxSys);
     g->hop_variant[prec][cls] = variant;

@@ -29,6 +29,26 @@ void set_error(const std::string& msg);
     } while (0)
 
 // ---------------------------------------------------------------- geometry
+// Division of non-negative 32-bit integers by a divisor fixed at set-up:
+// q = (t + ((n - t) >> s1)) >> s2 with t = mulhi(m, n), exact for every
+// divisor d >= 1 and dividend n < 2^32 (round-up multiply-high method of
+// Granlund and Montgomery, 1994).  Replaces the ~25-instruction integer
+// division in the index arithmetic of every site.
+struct FastDiv {
+    uint32_t d, m, s1, s2;
+};
+
+inline FastDiv make_fastdiv(uint32_t d) {
+    uint32_t l = 0;
+    while (l < 32 && (uint64_t(1) << l) < d) ++l;
+    FastDiv f;
+    f.d = d;
+    f.m = (uint32_t)(((uint64_t(1) << 32) * ((uint64_t(1) << l) - d)) / d + 1);
+    f.s1 = l < 1 ? l : 1;
+    f.s2 = l > 0 ? l - 1 : 0;
+    return f;
+}
+
 // Everything a kernel needs to locate a site and its eight neighbours.
 struct Geom {
     int Lx, Ly, Lz, Lt;
@@ -36,7 +56,16 @@ struct Geom {
     int Vh;          // sites per parity
     int sy, sz, st;  // eo strides of one step in y, z, t: hx, hx*Ly, hx*Ly*Lz
     int tbc;         // +1 or -1
+    FastDiv dhx, dLy, dLz, dLt;
 };
+
+// Fills the divisor tables of a geometry whose extents are set.
+inline void geom_init_divs(Geom& g) {
+    g.dhx = make_fastdiv((uint32_t)g.hx);
+    g.dLy = make_fastdiv((uint32_t)g.Ly);
+    g.dLz = make_fastdiv((uint32_t)g.Lz);
+    g.dLt = make_fastdiv((uint32_t)g.Lt);
+}
 
 constexpr int kBlock = 256;       // threads per block for every kernel
 constexpr int kMaxSys = 8;        // right-hand sides per operator launch
@@ -52,47 +81,48 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblk) {
     return (xcd < r) ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
 }
 
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv& f) {
+    const uint32_t t = __umulhi(f.m, n);
+    return (t + ((n - t) >> f.s1)) >> f.s2;
+}
+
+// q = n / d and r = n % d
+__device__ __forceinline__ void fdivmod(int n, const FastDiv& f, int& q, int& r) {
+    q = (int)fdiv((uint32_t)n, f);
+    r = n - q * (int)f.d;
+}
+
 // Coordinates of site eo of parity par.
 __device__ __forceinline__ void site_coords(const Geom& g, int eo, int par, int& x, int& y,
                                             int& z, int& t) {
-    const int xh = eo % g.hx;
-    int r = eo / g.hx;
-    y = r % g.Ly;
-    r /= g.Ly;
-    z = r % g.Lz;
-    t = r / g.Lz;
+    int xh, r;
+    fdivmod(eo, g.dhx, r, xh);
+    fdivmod(r, g.dLy, r, y);
+    fdivmod(r, g.dLz, t, z);
     x = 2 * xh + ((par + y + z + t) & 1);
 }
 
 // Site visited by processing index p (0 <= p < Vh) of a hopping launch.
 // Blocks give each XCD a contiguous range of p, so the order decides how far
 // apart (in sites processed) the eight uses of an input site are:
-//   0: the eo index itself (x fastest, then y, z, t)
-//   1: x, y, t, z             (t neighbours one xy-plane apart)
-//   2: x, y, z mod 4, t, z/4  (z-tiles of 4 planes, t inside the tile)
-//   3: x, y, z mod 2, t, z/2  (z-tiles of 2 planes)
-// Order 2 needs Lz % 4 == 0 (the launcher falls back to 1 otherwise).
-__device__ __forceinline__ void process_site(const Geom& g, int p, int par, int order, int& eo,
-                                             int& x, int& y, int& z, int& t) {
-    if (order == 0) {
+//   zt == 0: the eo index itself (x fastest, then y, z, t)
+//   zt >= 1: x, y, z mod zt, t, z / zt: z-tiles of zt planes with t inside a
+//            tile (zt == 1: x, y, t, z), so that the t neighbours of a wave's
+//            sites are zt xy-planes away; zt must divide Lz
+__device__ __forceinline__ void process_site(const Geom& g, int p, int par, const FastDiv& zt,
+                                             int& eo, int& x, int& y, int& z, int& t) {
+    if (zt.d == 0) {
         eo = p;
         site_coords(g, eo, par, x, y, z, t);
         return;
     }
-    const int xh = p % g.hx;
-    int r = p / g.hx;
-    y = r % g.Ly;
-    r /= g.Ly;
-    if (order == 1) {
-        t = r % g.Lt;
-        z = r / g.Lt;
-    } else {
-        const int T = order == 2 ? 4 : 2;
-        const int tz = r % T;
-        r /= T;
-        t = r % g.Lt;
-        z = (r / g.Lt) * T + tz;
-    }
+    int xh, r, tz;
+    fdivmod(p, g.dhx, r, xh);
+    fdivmod(r, g.dLy, r, y);
+    fdivmod(r, zt, r, tz);
+    int zq;
+    fdivmod(r, g.dLt, zq, t);
+    z = zq * (int)zt.d + tz;
     eo = xh + g.hx * (y + g.Ly * (z + g.Lz * t));
     x = 2 * xh + ((par + y + z + t) & 1);
 }
@@ -134,6 +164,35 @@ __device__ __forceinline__ Hops make_hops(const Geom& g, int eo, int x, int y, i
     h.coef[3] = e3 * bf;
     h.coef[7] = -e3 * bb;
     return h;
+}
+// The two hops of direction mu (0..3, may differ per lane) from site eo
+// with coordinates (x,y,z,t) and row = Lx*(y + Ly*(z + Lz*t)): neighbour eo
+// indices n +- mu and the factors of D on them (as in make_hops).
+__device__ __forceinline__ void dir_hops(const Geom& g, int mu, int eo, int x, int y, int z,
+                                         int t, int row, int& nbp, int& nbm, float& cp,
+                                         float& cm) {
+    // The extents and strides are uniform; reading them through readfirstlane
+    // keeps a select between fields of g (mu differs per lane) from becoming
+    // an indexed access to the kernel argument, which would be copied to scratch.
+    const int Lx = __builtin_amdgcn_readfirstlane(g.Lx), Ly = __builtin_amdgcn_readfirstlane(g.Ly);
+    const int Lz = __builtin_amdgcn_readfirstlane(g.Lz), Lt = __builtin_amdgcn_readfirstlane(g.Lt);
+    const int sy = __builtin_amdgcn_readfirstlane(g.sy), sz = __builtin_amdgcn_readfirstlane(g.sz);
+    const int st = __builtin_amdgcn_readfirstlane(g.st);
+    const int c = mu == 0 ? x : mu == 1 ? y : mu == 2 ? z : t;
+    const int L = mu == 0 ? Lx : mu == 1 ? Ly : mu == 2 ? Lz : Lt;
+    const int stride = mu == 1 ? sy : mu == 2 ? sz : st;
+    const bool fw = c + 1 == L, bw = c == 0;
+    if (mu == 0) {
+        nbp = (row + (fw ? 0 : x + 1)) >> 1;
+        nbm = (row + (bw ? Lx - 1 : x - 1)) >> 1;
+    } else {
+        nbp = fw ? eo - (L - 1) * stride : eo + stride;
+        nbm = bw ? eo + (L - 1) * stride : eo - stride;
+    }
+    const int par = mu == 0 ? 0 : mu == 1 ? x : mu == 2 ? x + y : x + y + z;
+    const float eta = (par & 1) ? -0.5f : 0.5f;
+    cp = (mu == 3 && fw) ? eta * (float)g.tbc : eta;
+    cm = (mu == 3 && bw) ? -eta * (float)g.tbc : -eta;
 }
 #endif  // __HIPCC__
 
@@ -198,27 +257,59 @@ struct DslashArgs {
     const int* all_done;          // if non-null and set: the launch does nothing
     double* partial;              // [nrhs][nblocks] block sums (kModeA, kModeResid)
     int variant;                  // launch variant (HopVariant index)
+    FastDiv zt;                   // site order: z-tile planes (d == 0: eo order), set at launch
 };
 
-// Launch variants of the hopping kernel, index = order | nt << 2 | batch << 3
-// | occ << 5:
-//   order  site processing order (process_site), 0..3
-//   nt     non-temporal (streaming) loads of the links, which are read once
-//          per application and need not displace neighbour vectors
-//   batch  hops whose loads are issued together: 1, 2, 4 or 8 (bits 0..3)
-//   occ    cap on resident workgroups per CU (none, 5, 4, 3), set through an
-//          unused dynamic LDS allocation: fewer sites in flight per XCD keep
-//          the neighbour vectors they share inside that XCD's L2
-constexpr int kHopVariants = 128;
-// dynamic LDS bytes per workgroup for occ = 0..3 (160 KB of LDS per CU)
-constexpr int kOccLds[4] = {0, 32 * 1024, 40 * 1024, 53 * 1024};
+// Launch variants of the hopping kernel, index = order + 8 * batch + 24 * stage:
+//   order  site processing order (process_site): 0 the eo index; 1..7 z-tiles
+//          of kZTile[order] planes with t inside a tile (a tile size that does
+//          not divide Lz falls back to 1)
+//   batch  hops whose loads are issued together: 1, 2 or 4
+//   stage  rows of the xy-plane staged in LDS per block (none, fewest, most;
+//          stage_rows), so the +-x and +-y hops read LDS; falls back to none
+//          where no row count fits
+// Link loads are non-temporal (read once per application).  Every variant
+// computes the same bits.
+constexpr int kHopOrders = 8, kHopBatches = 3, kHopStages = 3;
+constexpr int kHopVariants = kHopOrders * kHopBatches * kHopStages;
+constexpr int kZTile[kHopOrders] = {0, 1, 2, 4, 6, 8, 3, 12};
+inline int hop_order(int v) { return v % kHopOrders; }
+inline int hop_batch(int v) { return (v / kHopOrders) % kHopBatches; }
+inline int hop_stage(int v) { return v / (kHopOrders * kHopBatches); }
 // right-hand-side classes of the kernel templates: 1, 2, 4, 8
 inline int nr_class(int nrhs) { return nrhs <= 1 ? 0 : nrhs <= 2 ? 1 : nrhs <= 4 ? 2 : 3; }
+inline int nr_of_class(int cls) { return 1 << cls; }
 // measured defaults on MI355X (48^3 x 12), [precision][rhs class]
 void default_hop_variants(int (&v)[2][4]);
 
-// Geometry of a hopping launch.
-int dslash_grid(int Vh);
+// LDS budget of a staged block (three blocks fit a CU's 160 KB)
+constexpr size_t kStageLdsMax = 48 * 1024;
+
+// Rows per block of a staged launch (0: staging not possible): R divides Ly,
+// the block of R * Lx/2 sites is a whole number of waves (64..512 sites), and
+// the staged input [NR][3][R + 2][Lx/2] fits the LDS budget; stage 1 takes
+// the smallest such R, stage 2 the largest.
+inline int stage_rows(const Geom& g, int stage, int nr, int vt_bytes) {
+    if (stage == 0) return 0;
+    int best = 0;
+    for (int R = 1; R <= g.Ly; ++R) {
+        const int B = R * g.hx;
+        if (g.Ly % R || B % 64 || B > 512) continue;
+        const size_t lds = (size_t)nr * 3 * (R + 2) * g.hx * vt_bytes;
+        if (lds > kStageLdsMax) continue;
+        if (stage == 1) return R;
+        best = R;
+    }
+    return best;
+}
+
+// Blocks of a hopping launch of this variant (one partial sum per block and
+// rhs in the reducing modes); at most max_hop_grid(Vh).
+inline int hop_grid(const Geom& g, int variant, int nr, int vt_bytes) {
+    const int R = stage_rows(g, hop_stage(variant), nr, vt_bytes);
+    return R ? g.Vh / (R * g.hx) : (g.Vh + kBlock - 1) / kBlock;
+}
+inline int max_hop_grid(int Vh) { return (Vh + 63) / 64; }
 
 hipError_t launch_pack_links(const rhmc_gauge* g, const double2* canon, hipStream_t s);
 // Links of the FP64 operator rebuilt from the FP32 hi and lo planes.
@@ -272,6 +363,14 @@ inline bool has_fp64_op(const rhmc_gauge* g) {
 template <typename VT>
 inline void set_variant(DslashArgs<VT>& a, const rhmc_gauge* g) {
     a.variant = g->hop_variant[sizeof(VT) == 8 ? RHMC_PREC_FP32 : RHMC_PREC_FP64][nr_class(a.nrhs)];
+}
+
+// Blocks of the hopping launch the gauge object makes for this precision and
+// rhs count (the consumer of the partial sums needs their number).
+inline int gauge_hop_grid(const rhmc_gauge* g, rhmc_prec prec, int nrhs) {
+    const int cls = nr_class(nrhs);
+    return hop_grid(g->lat.geom, g->hop_variant[prec][cls], nr_of_class(cls),
+                    prec == RHMC_PREC_FP32 ? 8 : 16);
 }
 
 // Time every launch variant of one hopping application (out_parity 1, plain D)

@@ -92,8 +92,6 @@ hipError_t launch_neighbors(const Geom& g, int par, int* nb, int* sign, hipStrea
 }
 
 
-int dslash_grid(int Vh) { return (Vh + kBlock - 1) / kBlock; }
-
 hipError_t launch_dslash32(const float4* u32, int nlinks, const DslashArgs<float2>& a, int mode,
                            hipStream_t s) {
     switch (mode) {

@@ -22,6 +22,26 @@ struct Link {
 typedef double d2v __attribute__((ext_vector_type(2)));
 typedef float f4v __attribute__((ext_vector_type(4)));
 
+template <typename T>
+using gp = const __attribute__((address_space(1))) T*;
+
+template <bool NT>
+__device__ __forceinline__ double2 ldg(gp<double2> p) {
+    const __attribute__((address_space(1))) d2v* q =
+        reinterpret_cast<const __attribute__((address_space(1))) d2v*>(p);
+    d2v v;
+    if constexpr (NT)
+        v = __builtin_nontemporal_load(q);
+    else
+        v = *q;
+    return make_double2(v.x, v.y);
+}
+
+template <bool NT>
+__device__ __forceinline__ float4 ldg(gp<float4> p);
+template <bool NT>
+__device__ __forceinline__ float2 ldg(gp<float2> p);
+
 template <bool NT>
 __device__ __forceinline__ double2 ldg(const double2* p) {
     if constexpr (NT) {
@@ -45,6 +65,30 @@ __device__ __forceinline__ float2 ldg(const float2* p) {
 }
 
 template <bool NT>
+__device__ __forceinline__ float2 ldg(gp<float2> p) {
+    const __attribute__((address_space(1))) f2v* q =
+        reinterpret_cast<const __attribute__((address_space(1))) f2v*>(p);
+    f2v v;
+    if constexpr (NT)
+        v = __builtin_nontemporal_load(q);
+    else
+        v = *q;
+    return make_float2(v.x, v.y);
+}
+
+template <bool NT>
+__device__ __forceinline__ float4 ldg(gp<float4> p) {
+    const __attribute__((address_space(1))) f4v* q =
+        reinterpret_cast<const __attribute__((address_space(1))) f4v*>(p);
+    f4v v;
+    if constexpr (NT)
+        v = __builtin_nontemporal_load(q);
+    else
+        v = *q;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+
+template <bool NT>
 __device__ __forceinline__ float4 ldg(const float4* p) {
     if constexpr (NT) {
         const f4v v = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(p));
@@ -54,18 +98,37 @@ __device__ __forceinline__ float4 ldg(const float4* p) {
     }
 }
 
-template <bool NT>
-__device__ __forceinline__ void load_link(const double2* __restrict__ u, int nlinks, int k,
-                                          Link<double>& L) {
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            const double2 v = ldg<NT>(u + (size_t)(3 * i + j) * nlinks + k);
-            L.re[i][j] = v.x;
-            L.im[i][j] = v.y;
-        }
+// The planes of a structure-of-arrays field (link entries, colour planes of
+// a vector): every plane's base address is uniform and held in scalar
+// registers (readfirstlane keeps the compiler from folding it into per-lane
+// address arithmetic), and a lane adds a 32-bit byte offset (the lattice
+// volume cap keeps it below 2^32): one offset per lane serves every plane.
+typedef const __attribute__((address_space(1))) char* gbl_ptr;   // global memory
+
+__device__ __forceinline__ gbl_ptr uniform_ptr(const void* q) {
+    const uint64_t v = reinterpret_cast<uint64_t>(q);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return reinterpret_cast<gbl_ptr>(((uint64_t)hi << 32) | lo);
 }
+
+template <typename T, int E>
+struct Planes {
+    gbl_ptr p[E];
+    __device__ __forceinline__ const __attribute__((address_space(1))) T* at(int e, uint32_t byte_off) const {
+        return reinterpret_cast<const __attribute__((address_space(1))) T*>(p[e] + byte_off);
+    }
+};
+
+template <typename T, int E>
+__device__ __forceinline__ Planes<T, E> make_planes(const T* base, size_t stride) {
+    Planes<T, E> P;
+#pragma unroll
+    for (int e = 0; e < E; ++e) P.p[e] = uniform_ptr(base + (size_t)e * stride);
+    return P;
+}
+
+__device__ __forceinline__ uint32_t byte_off(int k, uint32_t size) { return (uint32_t)k * size; }
 
 // Row 3 of an SU(3) matrix from rows 1-2: conj(row1 x row2) (valid for det U = 1).
 template <typename RT>
@@ -86,13 +149,43 @@ __device__ __forceinline__ void rebuild_row3(Link<RT>& L) {
     }
 }
 
-// 12-real link: rows 1-2 stored, row 3 = conj(row1 x row2) (valid for det U = 1).
+// Link storages as planes of entries: entry type and number of planes.
+template <typename LT> struct LinkFmt;
+template <> struct LinkFmt<double2> { using T = double2; static constexpr int E = 9; };       // FP64-18
+template <> struct LinkFmt<Fp64x12Link> { using T = double2; static constexpr int E = 6; };   // FP64-12
+template <> struct LinkFmt<float4> { using T = float4; static constexpr int E = 3; };         // FP32-12
+template <> struct LinkFmt<HiLoLink> { using T = float4; static constexpr int E = 6; };       // hi, lo
+template <> struct LinkFmt<Fp32x18Link> { using T = float2; static constexpr int E = 9; };    // FP32-18
+
+template <typename LT>
+using LinkPlanes = Planes<typename LinkFmt<LT>::T, LinkFmt<LT>::E>;
+
+template <typename LT>
+__device__ __forceinline__ LinkPlanes<LT> link_planes(const LT* u, int nlinks) {
+    using T = typename LinkFmt<LT>::T;
+    return make_planes<T, LinkFmt<LT>::E>(reinterpret_cast<const T*>(u), (size_t)nlinks);
+}
+
+// FP64-18: all 18 reals stored.
 template <bool NT>
-__device__ __forceinline__ void load_link(const float4* __restrict__ u, int nlinks, int k,
-                                          Link<float>& L) {
-    const float4 a = ldg<NT>(u + k);
-    const float4 b = ldg<NT>(u + (size_t)nlinks + k);
-    const float4 c = ldg<NT>(u + (size_t)2 * nlinks + k);
+__device__ __forceinline__ void load_link(const Planes<double2, 9>& P, int k, Link<double>& L) {
+    const uint32_t o = byte_off(k, 16);
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+        const double2 v = ldg<NT>(P.at(e, o));
+        L.re[e / 3][e % 3] = v.x;
+        L.im[e / 3][e % 3] = v.y;
+    }
+}
+
+// FP32-12: rows 1-2 stored as three float4, row 3 = conj(row1 x row2) (valid
+// for det U = 1).
+template <bool NT>
+__device__ __forceinline__ void load_link(const Planes<float4, 3>& P, int k, Link<float>& L) {
+    const uint32_t o = byte_off(k, 16);
+    const float4 a = ldg<NT>(P.at(0, o));
+    const float4 b = ldg<NT>(P.at(1, o));
+    const float4 c = ldg<NT>(P.at(2, o));
     L.re[0][0] = a.x; L.im[0][0] = a.y; L.re[0][1] = a.z; L.im[0][1] = a.w;
     L.re[0][2] = b.x; L.im[0][2] = b.y; L.re[1][0] = b.z; L.im[1][0] = b.w;
     L.re[1][1] = c.x; L.im[1][1] = c.y; L.re[1][2] = c.z; L.im[1][2] = c.w;
@@ -102,14 +195,13 @@ __device__ __forceinline__ void load_link(const float4* __restrict__ u, int nlin
 // FP64 link from hi + lo planes: rows 1-2 = hi + lo in FP64, row 3 rebuilt in
 // FP64 as conj(row1 x row2).
 template <bool NT>
-__device__ __forceinline__ void load_link(const HiLoLink* __restrict__ uh, int nlinks, int k,
-                                          Link<double>& L) {
-    const float4* u = reinterpret_cast<const float4*>(uh);
+__device__ __forceinline__ void load_link(const Planes<float4, 6>& P, int k, Link<double>& L) {
+    const uint32_t o = byte_off(k, 16);
     float4 h[3], l[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        h[i] = ldg<NT>(u + (size_t)i * nlinks + k);
-        l[i] = ldg<NT>(u + (size_t)(3 + i) * nlinks + k);
+        h[i] = ldg<NT>(P.at(i, o));
+        l[i] = ldg<NT>(P.at(3 + i, o));
     }
     const double w[12] = {(double)h[0].x + (double)l[0].x, (double)h[0].y + (double)l[0].y,
                           (double)h[0].z + (double)l[0].z, (double)h[0].w + (double)l[0].w,
@@ -125,188 +217,337 @@ __device__ __forceinline__ void load_link(const HiLoLink* __restrict__ uh, int n
     rebuild_row3(L);
 }
 
-// FP32 link from 18 stored floats (no reconstruction: any complex 3x3 matrix).
+// FP32-18: all 18 reals stored (no reconstruction: any complex 3x3 matrix).
 template <bool NT>
-__device__ __forceinline__ void load_link(const Fp32x18Link* __restrict__ uf, int nlinks, int k,
-                                          Link<float>& L) {
-    const float2* u = reinterpret_cast<const float2*>(uf);
+__device__ __forceinline__ void load_link(const Planes<float2, 9>& P, int k, Link<float>& L) {
+    const uint32_t o = byte_off(k, 8);
 #pragma unroll
     for (int e = 0; e < 9; ++e) {
-        const float2 v = ldg<NT>(u + (size_t)e * nlinks + k);
+        const float2 v = ldg<NT>(P.at(e, o));
         L.re[e / 3][e % 3] = v.x;
         L.im[e / 3][e % 3] = v.y;
     }
 }
 
-// FP64 link from 12 stored doubles (rows 1-2), row 3 rebuilt in FP64.
+// FP64-12: rows 1-2 stored in FP64, row 3 rebuilt in FP64.
 template <bool NT>
-__device__ __forceinline__ void load_link(const Fp64x12Link* __restrict__ uc, int nlinks, int k,
-                                          Link<double>& L) {
-    const double2* u = reinterpret_cast<const double2*>(uc);
+__device__ __forceinline__ void load_link(const Planes<double2, 6>& P, int k, Link<double>& L) {
+    const uint32_t o = byte_off(k, 16);
 #pragma unroll
     for (int e = 0; e < 6; ++e) {
-        const double2 v = ldg<NT>(u + (size_t)e * nlinks + k);
+        const double2 v = ldg<NT>(P.at(e, o));
         L.re[e / 3][e % 3] = v.x;
         L.im[e / 3][e % 3] = v.y;
     }
     rebuild_row3(L);
 }
 
+// Link k of a storage given by its base address (kernels outside the
+// hopping term).
+template <bool NT, typename LT, typename RT>
+__device__ __forceinline__ void load_link(const LT* __restrict__ u, int nlinks, int k, Link<RT>& L) {
+    load_link<NT>(link_planes(u, nlinks), k, L);
+}
+
 template <typename VT> struct RealOf;
 template <> struct RealOf<double2> { using T = double; };
 template <> struct RealOf<float2> { using T = float; };
 
+// Vector access through buffer resources: one resource per right-hand side
+// (base address in scalar registers), the colour plane as the scalar offset
+// and the site as the per-lane offset, so a load needs no per-lane address
+// arithmetic.  The lattice volume is capped so that 3 * Vh * 16 bytes fits
+// the 32-bit buffer range.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t vec_rsrc(const void* p, int Vh, int bytes_per) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, 3 * Vh * bytes_per,
+                                             0x00020000);
+}
+constexpr int kBufNT = 2;   // aux bit 1: non-temporal (data not reused by this kernel)
+
+template <int AUX>
+__device__ __forceinline__ float2 buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, float2*) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, AUX);
+    float2 o;
+    __builtin_memcpy(&o, &v, 8);
+    return o;
+}
+template <int AUX>
+__device__ __forceinline__ double2 buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, double2*) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, AUX);
+    double2 o;
+    __builtin_memcpy(&o, &v, 16);
+    return o;
+}
+template <int AUX>
+__device__ __forceinline__ void buf_st(float2 x, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    __attribute__((ext_vector_type(2))) unsigned int v;
+    __builtin_memcpy(&v, &x, 8);
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, soff, AUX);
+}
+template <int AUX>
+__device__ __forceinline__ void buf_st(double2 x, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    __attribute__((ext_vector_type(4))) unsigned int v;
+    __builtin_memcpy(&v, &x, 16);
+    __builtin_amdgcn_raw_buffer_store_b128(v, r, voff, soff, AUX);
+}
+
+__device__ __forceinline__ float fmar(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmar(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// Value of lane (lane ^ 1) or (lane ^ 2) of the same quad (DPP quad_perm),
+// for the exchange between the lanes that share one output site.
+template <int CTRL>
+__device__ __forceinline__ float quad_xor(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double quad_xor(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+constexpr int kQuadXor1 = 0xB1;   // quad_perm [1, 0, 3, 2]
+constexpr int kQuadXor2 = 0x4E;   // quad_perm [2, 3, 0, 1]
+
+// One hop for every right-hand side: S += s * (U v) (forward) or
+// S += s * (U^dagger v) (backward), with s = +-1/2.  The input is scaled by s
+// first (exact: a power of two), then each real component of the product is
+// accumulated into S by a fixed chain of six fused multiply-adds (the first
+// hop starts the chain with a product): every launch shape forms the same
+// sequence of roundings, so all give the same bits.
+template <bool FWD, bool FIRST, typename RT, typename VT, int NR>
+__device__ __forceinline__ void hop_apply(const Link<RT>& U, const VT (&v)[NR][3], RT s,
+                                          RT (&sr)[NR][3], RT (&si)[NR][3]) {
+#pragma clang fp contract(off)
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        RT wr[3], wi[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            wr[j] = s * v[r][j].x;
+            wi[j] = s * v[r][j].y;
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            // forward (U v)_i = sum_j U_ij v_j; backward (U^dagger v)_i = sum_j conj(U_ji) v_j
+            RT xr = sr[r][i], xi = si[r][i];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const RT ur = FWD ? U.re[i][j] : U.re[j][i];
+                const RT ui = FWD ? U.im[i][j] : -U.im[j][i];
+                if (FIRST && j == 0) {
+                    xr = ur * wr[j];
+                    xi = ur * wi[j];
+                } else {
+                    xr = fmar(ur, wr[j], xr);
+                    xi = fmar(ur, wi[j], xi);
+                }
+                xr = fmar(-ui, wi[j], xr);
+                xi = fmar(ui, wr[j], xi);
+            }
+            sr[r][i] = xr;
+            si[r][i] = xi;
+        }
+    }
+}
+
 // ------------------------------------------------------------------ hopping kernel
-template <typename VT, typename LT, int NR, int MODE, bool NT, int BATCH>
-__global__ __launch_bounds__(kBlock) void k_dslash(const LT* __restrict__ links, int nlinks,
-                                                    DslashArgs<VT> a) {
+// One lane owns one output site and every right-hand side of the launch, so
+// each link is read once per application however many vectors are batched.
+// The eight hops run in the order +x, -x, +y, -y, +z, -z, +t, -t and every
+// launch shape forms the same sequence of roundings (hop_apply), so all give
+// the same bits.  BATCH is the number of hops whose loads are issued
+// together.
+//
+// STG (staged rows): a block is R whole rows (R * Lx/2 sites) of one xy-plane.
+// It first copies the input of its rows and of the row above and below
+// (periodic in y) into LDS with coalesced loads, and the +-x and +-y hops
+// read their neighbours from LDS.  Every neighbour vector otherwise passes
+// through the per-CU vector-memory pipeline (address unit and L1) once per
+// hop, eight times per site; staging takes half of those accesses off it.
+template <typename VT, typename LT, int NR, int MODE, bool NT, int BATCH, bool STG>
+__global__ __launch_bounds__(STG ? 512 : kBlock) void k_dslash(const LT* __restrict__ links,
+                                                               int nlinks, DslashArgs<VT> a) {
+#pragma clang fp contract(off)
     using RT = typename RealOf<VT>::T;
     if (a.all_done && *a.all_done) return;
     const int nblk = gridDim.x;
     const int blk = xcd_remap(blockIdx.x, nblk);
     const int Vh = a.g.Vh;
-    const int p = blk * kBlock + threadIdx.x;
+    const int bsites = STG ? (int)blockDim.x : kBlock;   // sites per block
+    const int p_raw = blk * bsites + (int)threadIdx.x;
+    if (p_raw >= Vh && MODE == kModeD) return;   // (staged blocks are never partial)
+    const bool in_range = p_raw < Vh;
+    const int p = in_range ? p_raw : Vh - 1;
 
     // Every lane loads all NR vectors of a hop with no branch in between, so
     // the compiler can keep every load of a hop in flight at once; slots of
     // finished or absent right-hand sides read rhs 0 (valid, cached) and only
     // their stores are suppressed.
     bool act[NR];
-    const VT* inp[NR];
+    Planes<VT, 3> vin[NR];   // colour planes of every input
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-        act[r] = (r < a.nrhs) && !(a.skip && a.skip[r * a.skip_stride]);
-        inp[r] = (r < a.nrhs) ? a.in[r] : a.in[0];
+        act[r] = in_range && (r < a.nrhs) && !(a.skip && a.skip[r * a.skip_stride]);
+        vin[r] = make_planes<VT, 3>((r < a.nrhs) ? a.in[r] : a.in[0], (size_t)Vh);
+    }
+    const LinkPlanes<LT> lp = link_planes(links, nlinks);
+
+    int eo, x, y, z, t;
+    process_site(a.g, p, a.out_par, a.zt, eo, x, y, z, t);
+    const Hops h = make_hops(a.g, eo, x, y, z, t);
+
+    // staged rows: LDS [NR][3][R + 2][hx], row 0 = y0 - 1, row R + 1 = y0 + R
+    extern __shared__ unsigned char lds_stage[];
+    VT* stage = reinterpret_cast<VT*>(lds_stage);
+    int srow = 0, shx = 0, sR2 = 0;   // this site's staged row, hx, R + 2
+    if (STG) {
+        const int hx = a.g.hx, Ly = a.g.Ly;
+        const int R = bsites / hx;
+        int eo0, x0, y0, z0, t0;
+        process_site(a.g, blk * bsites, a.out_par, a.zt, eo0, x0, y0, z0, t0);
+        const int base = hx * Ly * (z0 + a.g.Lz * t0);   // first site of the plane
+        const int rows = (R + 2) * hx;
+        for (int idx = (int)threadIdx.x; idx < rows; idx += bsites) {
+            int rr, xs;
+            fdivmod(idx, a.g.dhx, rr, xs);
+            int yy = y0 - 1 + rr;
+            yy = yy < 0 ? yy + Ly : (yy >= Ly ? yy - Ly : yy);
+            const int src = base + hx * yy + xs;
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                if (r >= a.nrhs) break;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) stage[(r * 3 + c) * rows + idx] = a.in[r][c * Vh + src];
+            }
+        }
+        srow = y - y0 + 1;
+        shx = hx;
+        sR2 = R + 2;
+        __syncthreads();
+    }
+
+    RT ar[NR][3], ai[NR][3];
+    int nbh = h.nb[0];
+#pragma unroll
+    for (int hop = 0; hop < 8; ++hop) {
+        const int mu = hop >> 1;
+        const bool fwd = (hop & 1) == 0;
+        const int slot = fwd ? mu : 4 + mu;   // index into Hops (0..3 forward, 4..7 backward)
+        const int nb = nbh;
+        // forward: U_mu(n) at this site; backward: U_mu(n-mu) at the neighbour
+        const int kl = fwd ? (2 * mu + a.out_par) * Vh + eo : (2 * mu + 1 - a.out_par) * Vh + nb;
+        Link<RT> U;
+        load_link<NT>(lp, kl, U);
+        VT v[NR][3];
+        if (STG && mu < 2) {
+            // x neighbours: same row, half-index of x +- 1 (periodic); y
+            // neighbours: the row above or below, same half-index
+            int col, row = srow;
+            if (mu == 0)
+                col = fwd ? ((x + 1 == a.g.Lx) ? 0 : (x + 1) >> 1) : ((x == 0) ? shx - 1 : (x - 1) >> 1);
+            else {
+                col = x >> 1;
+                row += fwd ? 1 : -1;
+            }
+            const int li = row * shx + col;
+            const int rows = sR2 * shx;
+#pragma unroll
+            for (int r = 0; r < NR; ++r)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) v[r][c] = stage[(r * 3 + c) * rows + li];
+        } else {
+            const uint32_t o = byte_off(nb, (uint32_t)sizeof(VT));
+#pragma unroll
+            for (int r = 0; r < NR; ++r)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) v[r][c] = ldg<false>(vin[r].at(c, o));
+        }
+        const RT s = (RT)h.coef[slot];
+        if (hop == 0)
+            hop_apply<true, true>(U, v, s, ar, ai);
+        else if (fwd)
+            hop_apply<true, false>(U, v, s, ar, ai);
+        else
+            hop_apply<false, false>(U, v, s, ar, ai);
+        if (hop + 1 < 8) {
+            // Empty volatile asms (no instruction) pin the sums after every
+            // BATCH hops and make the next hop's index depend on them: each
+            // wave then issues the loads of BATCH hops together and finishes
+            // their arithmetic before the next batch, instead of the
+            // scheduler hoisting all eight hops' loads and keeping them live
+            // (one wave per SIMD).  Latency is hidden by the other resident
+            // waves.  BATCH = 8 leaves the schedule to the compiler.
+            if ((hop + 1) % BATCH == 0) {
+#pragma unroll
+                for (int r = 0; r < NR; ++r)
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) asm volatile("" : "+v"(ar[r][i]), "+v"(ai[r][i]));
+            }
+            const int next = hop + 1;
+            nbh = h.nb[(next & 1) ? 4 + (next >> 1) : (next >> 1)];
+            asm volatile("" : "+v"(nbh));
+        }
     }
 
     double dot[NR];
 #pragma unroll
-    for (int r = 0; r < NR; ++r) dot[r] = 0.0;
-
-    if (p < Vh) {
-        int eo, x, y, z, t;
-        process_site(a.g, p, a.out_par, a.variant & 3, eo, x, y, z, t);
-        const Hops h = make_hops(a.g, eo, x, y, z, t);
-        RT ar[NR][3], ai[NR][3];
+    for (int r = 0; r < NR; ++r) {
+        dot[r] = 0.0;
+        if (!act[r]) continue;
+        if (MODE == kModeD) {
 #pragma unroll
-        for (int r = 0; r < NR; ++r)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) ar[r][c] = ai[r][c] = RT(0);
-
-        // Hops in the order +x, -x, +y, -y, +z, -z, +t, -t: both uses of an
-        // input site along one direction fall in the same load batch, and the
-        // sums run in this order in every launch variant (same bits).
-        int nbh = h.nb[0];
-#pragma unroll
-        for (int hop = 0; hop < 8; ++hop) {
-            const int mu = hop >> 1;
-            const bool fwd = (hop & 1) == 0;
-            const int slot = fwd ? mu : 4 + mu;   // index into Hops (0..3 forward, 4..7 backward)
-            const int nb = nbh;
-            // forward: U_mu(n) at this site; backward: U_mu(n-mu) at the neighbour
-            const int k = fwd ? (2 * mu + a.out_par) * Vh + eo : (2 * mu + 1 - a.out_par) * Vh + nb;
-            Link<RT> U;
-            load_link<NT>(links, nlinks, k, U);
-            VT v[NR][3];
-#pragma unroll
-            for (int r = 0; r < NR; ++r) {
-                v[r][0] = inp[r][nb];
-                v[r][1] = inp[r][Vh + nb];
-                v[r][2] = inp[r][2 * Vh + nb];
+            for (int c = 0; c < 3; ++c) {
+                VT o;
+                o.x = ar[r][c];
+                o.y = ai[r][c];
+                a.out[r][c * Vh + eo] = o;
             }
-            const RT s = (RT)h.coef[slot];
+        } else if (MODE == kModeA) {
+            const RT cr = (RT)a.c[r];
+            double d = 0.0;
 #pragma unroll
-            for (int r = 0; r < NR; ++r) {
-#pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    RT tr, ti;
-                    if (fwd) {  // (U v)_i = sum_j U_ij v_j
-                        tr = U.re[i][0] * v[r][0].x - U.im[i][0] * v[r][0].y + U.re[i][1] * v[r][1].x -
-                             U.im[i][1] * v[r][1].y + U.re[i][2] * v[r][2].x - U.im[i][2] * v[r][2].y;
-                        ti = U.re[i][0] * v[r][0].y + U.im[i][0] * v[r][0].x + U.re[i][1] * v[r][1].y +
-                             U.im[i][1] * v[r][1].x + U.re[i][2] * v[r][2].y + U.im[i][2] * v[r][2].x;
-                    } else {    // (U^dagger v)_i = sum_j conj(U_ji) v_j
-                        tr = U.re[0][i] * v[r][0].x + U.im[0][i] * v[r][0].y + U.re[1][i] * v[r][1].x +
-                             U.im[1][i] * v[r][1].y + U.re[2][i] * v[r][2].x + U.im[2][i] * v[r][2].y;
-                        ti = U.re[0][i] * v[r][0].y - U.im[0][i] * v[r][0].x + U.re[1][i] * v[r][1].y -
-                             U.im[1][i] * v[r][1].x + U.re[2][i] * v[r][2].y - U.im[2][i] * v[r][2].x;
-                    }
-                    ar[r][i] += s * tr;
-                    ai[r][i] += s * ti;
-                }
+            for (int c = 0; c < 3; ++c) {
+                const VT pv = a.self[r][c * Vh + eo];
+                VT o;
+                o.x = cr * pv.x - ar[r][c];
+                o.y = cr * pv.y - ai[r][c];
+                a.out[r][c * Vh + eo] = o;
+                d = d + (double)pv.x * (double)o.x;
+                d = d + (double)pv.y * (double)o.y;
             }
-            if (hop + 1 < 8) {
-                // Empty volatile asms (no instruction) pin the sums after every
-                // BATCH hops and make the next hop's index depend on them: each
-                // wave then issues the loads of BATCH hops together and finishes
-                // their arithmetic before the next batch, instead of the
-                // scheduler hoisting all eight hops' loads and keeping them live
-                // (one wave per SIMD).  Latency is hidden by the other resident
-                // waves.  BATCH = 8 leaves the schedule to the compiler.
-                if ((hop + 1) % BATCH == 0) {
+            dot[r] = d;
+        } else {  // kModeResid (FP64 operator)
+            const double cr = a.c[r];
+            double d = 0.0;
 #pragma unroll
-                    for (int r = 0; r < NR; ++r)
-#pragma unroll
-                        for (int i = 0; i < 3; ++i) asm volatile("" : "+v"(ar[r][i]), "+v"(ai[r][i]));
+            for (int c = 0; c < 3; ++c) {
+                const VT xv = a.self[r][c * Vh + eo];
+                const double2 bv = a.rhs[r][c * Vh + eo];
+                double2 o;
+                o.x = (bv.x - cr * (double)xv.x) + (double)ar[r][c];
+                o.y = (bv.y - cr * (double)xv.y) + (double)ai[r][c];
+                if (a.out[r]) {
+                    VT w;
+                    w.x = o.x;
+                    w.y = o.y;
+                    a.out[r][c * Vh + eo] = w;
                 }
-                const int next = hop + 1;
-                nbh = h.nb[(next & 1) ? 4 + (next >> 1) : (next >> 1)];
-                asm volatile("" : "+v"(nbh));
+                if (a.out32[r]) a.out32[r][c * Vh + eo] = make_float2((float)o.x, (float)o.y);
+                d = d + o.x * o.x;
+                d = d + o.y * o.y;
             }
-        }
-
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            if (!act[r]) continue;
-            if (MODE == kModeD) {
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    VT o;
-                    o.x = ar[r][c];
-                    o.y = ai[r][c];
-                    a.out[r][c * Vh + eo] = o;
-                }
-            } else if (MODE == kModeA) {
-                const RT cr = (RT)a.c[r];
-                double d = 0.0;
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const VT p = a.self[r][c * Vh + eo];
-                    VT o;
-                    o.x = cr * p.x - ar[r][c];
-                    o.y = cr * p.y - ai[r][c];
-                    a.out[r][c * Vh + eo] = o;
-                    d += (double)p.x * (double)o.x + (double)p.y * (double)o.y;
-                }
-                dot[r] = d;
-            } else {  // kModeResid (FP64 operator)
-                const double cr = a.c[r];
-                double d = 0.0;
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const VT xv = a.self[r][c * Vh + eo];
-                    const double2 bv = a.rhs[r][c * Vh + eo];
-                    double2 o;
-                    o.x = bv.x - cr * (double)xv.x + (double)ar[r][c];
-                    o.y = bv.y - cr * (double)xv.y + (double)ai[r][c];
-                    if (a.out[r]) {
-                        VT w;
-                        w.x = o.x;
-                        w.y = o.y;
-                        a.out[r][c * Vh + eo] = w;
-                    }
-                    if (a.out32[r]) a.out32[r][c * Vh + eo] = make_float2((float)o.x, (float)o.y);
-                    d += o.x * o.x + o.y * o.y;
-                }
-                dot[r] = d;
-            }
+            dot[r] = d;
         }
     }
 
     if (MODE != kModeD) {
         // deterministic block reduction -> one partial per rhs and block
-        __shared__ double sm[NR][kBlock / 64];
+        constexpr int kMaxWaves = (STG ? 512 : kBlock) / 64;
+        __shared__ double sm[NR][kMaxWaves];
         const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+        const int nw = bsites >> 6;
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             double v = dot[r];
@@ -314,52 +555,55 @@ __global__ __launch_bounds__(kBlock) void k_dslash(const LT* __restrict__ links,
             if (lane == 0) sm[r][wid] = v;
         }
         __syncthreads();
-        if (threadIdx.x < NR && threadIdx.x < a.nrhs) {
-            double t = 0.0;
-#pragma unroll
-            for (int w = 0; w < kBlock / 64; ++w) t += sm[threadIdx.x][w];
-            a.partial[(size_t)threadIdx.x * nblk + blk] = t;
+        if ((int)threadIdx.x < NR && (int)threadIdx.x < a.nrhs) {
+            double t2 = 0.0;
+            for (int w = 0; w < nw; ++w) t2 += sm[threadIdx.x][w];
+            a.partial[(size_t)threadIdx.x * nblk + blk] = t2;
         }
     }
 }
 
-template <typename VT, typename LT, int MODE, bool NT, int BATCH>
-inline hipError_t dispatch_nt(const LT* links, int nlinks, const DslashArgs<VT>& a, size_t lds,
-                              hipStream_t s) {
-    const dim3 grid(dslash_grid(a.g.Vh)), block(kBlock);
-    if (a.nrhs <= 1)
-        hipLaunchKernelGGL((k_dslash<VT, LT, 1, MODE, NT, BATCH>), grid, block, lds, s, links, nlinks, a);
-    else if (a.nrhs <= 2)
-        hipLaunchKernelGGL((k_dslash<VT, LT, 2, MODE, NT, BATCH>), grid, block, lds, s, links, nlinks, a);
-    else if (a.nrhs <= 4)
-        hipLaunchKernelGGL((k_dslash<VT, LT, 4, MODE, NT, BATCH>), grid, block, lds, s, links, nlinks, a);
-    else
-        hipLaunchKernelGGL((k_dslash<VT, LT, 8, MODE, NT, BATCH>), grid, block, lds, s, links, nlinks, a);
+template <typename VT, typename LT, int MODE, int BATCH, bool STG>
+inline hipError_t launch_nr(const LT* links, int nlinks, const DslashArgs<VT>& a, int nr,
+                            dim3 grid, dim3 block, size_t lds, hipStream_t s) {
+    switch (nr) {
+        case 1: hipLaunchKernelGGL((k_dslash<VT, LT, 1, MODE, true, BATCH, STG>), grid, block, lds, s, links, nlinks, a); break;
+        case 2: hipLaunchKernelGGL((k_dslash<VT, LT, 2, MODE, true, BATCH, STG>), grid, block, lds, s, links, nlinks, a); break;
+        case 4: hipLaunchKernelGGL((k_dslash<VT, LT, 4, MODE, true, BATCH, STG>), grid, block, lds, s, links, nlinks, a); break;
+        default: hipLaunchKernelGGL((k_dslash<VT, LT, 8, MODE, true, BATCH, STG>), grid, block, lds, s, links, nlinks, a); break;
+    }
     return hipGetLastError();
 }
 
-template <typename VT, typename LT, int MODE, bool NT>
-inline hipError_t dispatch_batch(const LT* links, int nlinks, const DslashArgs<VT>& a, int batch,
-                                 size_t lds, hipStream_t s) {
+template <typename VT, typename LT, int MODE, bool STG>
+inline hipError_t launch_batch(const LT* links, int nlinks, const DslashArgs<VT>& a, int nr,
+                               int batch, dim3 grid, dim3 block, size_t lds, hipStream_t s) {
     switch (batch) {
-        case 0: return dispatch_nt<VT, LT, MODE, NT, 1>(links, nlinks, a, lds, s);
-        case 1: return dispatch_nt<VT, LT, MODE, NT, 2>(links, nlinks, a, lds, s);
-        case 2: return dispatch_nt<VT, LT, MODE, NT, 4>(links, nlinks, a, lds, s);
-        default: return dispatch_nt<VT, LT, MODE, NT, 8>(links, nlinks, a, lds, s);
+        case 0: return launch_nr<VT, LT, MODE, 1, STG>(links, nlinks, a, nr, grid, block, lds, s);
+        case 1: return launch_nr<VT, LT, MODE, 2, STG>(links, nlinks, a, nr, grid, block, lds, s);
+        default: return launch_nr<VT, LT, MODE, 4, STG>(links, nlinks, a, nr, grid, block, lds, s);
     }
 }
 
+// One hopping launch in the variant a.variant (see kHopVariants).
 template <typename VT, typename LT, int MODE>
 inline hipError_t dispatch(const LT* links, int nlinks, const DslashArgs<VT>& a0, hipStream_t s) {
     DslashArgs<VT> a = a0;
-    int v = a.variant & (kHopVariants - 1);
-    if ((v & 3) == 2 && a.g.Lz % 4 != 0) v = (v & ~3) | 1;   // z-tiles of 4 need Lz % 4 == 0
-    a.variant = v;
-    const bool nt = (v >> 2) & 1;
-    const int batch = (v >> 3) & 3;
-    const size_t lds = (size_t)kOccLds[(v >> 5) & 3];
-    if (nt) return dispatch_batch<VT, LT, MODE, true>(links, nlinks, a, batch, lds, s);
-    return dispatch_batch<VT, LT, MODE, false>(links, nlinks, a, batch, lds, s);
+    const int v = a.variant >= 0 && a.variant < kHopVariants ? a.variant : 0;
+    int zt = kZTile[hop_order(v)];
+    if (zt > 0 && a.g.Lz % zt != 0) zt = 1;
+    a.zt = zt ? make_fastdiv((uint32_t)zt) : FastDiv{0u, 0u, 0u, 0u};
+    const int nr = nr_of_class(nr_class(a.nrhs));
+    const int R = stage_rows(a.g, hop_stage(v), nr, (int)sizeof(VT));
+    const int batch = hop_batch(v);
+    if (R) {
+        const int B = R * a.g.hx;
+        const size_t lds = (size_t)nr * 3 * (R + 2) * a.g.hx * sizeof(VT);
+        return launch_batch<VT, LT, MODE, true>(links, nlinks, a, nr, batch, dim3(a.g.Vh / B),
+                                                dim3(B), lds, s);
+    }
+    return launch_batch<VT, LT, MODE, false>(links, nlinks, a, nr, batch,
+                                             dim3((a.g.Vh + kBlock - 1) / kBlock), dim3(kBlock), 0, s);
 }
 
 }  // namespace rhmc

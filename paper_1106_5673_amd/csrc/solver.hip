@@ -158,7 +158,7 @@ static rhmc_status ensure_workspace(rhmc_gauge* g, int nsys, int nshift, int K) 
         RHMC_TRY(alloc((void**)&w->t64, vb * kMaxSys));
         RHMC_TRY(alloc((void**)&w->rb, vb * kMaxSys));
         RHMC_TRY(alloc((void**)&w->rx, vb * kMaxSys));
-        w->part_stride = w->n / 2 / kBlock + 2;
+        w->part_stride = (size_t)max_hop_grid(g->lat.geom.Vh) + 2;
         RHMC_TRY(alloc((void**)&w->partial, sizeof(double) * 2 * kMaxSys * w->part_stride));
         RHMC_TRY(alloc((void**)&w->sums, sizeof(double) * kMaxSys));
         RHMC_TRY(alloc((void**)&w->st, sizeof(SolverState)));
@@ -237,7 +237,10 @@ static rhmc_status enqueue_block(const rhmc_gauge* g, Workspace* w, const Proble
     DslashArgs<VT> a = d;
     d.out_par = 1;
     a.out_par = 0;
-    const int dgrid = dslash_grid(g->lat.geom.Vh);
+    // blocks of the A-mode launch (partials of <p, Ap>) and of the FP64
+    // residual launch of a reliable update
+    const int dgrid = gauge_hop_grid(g, f32 ? RHMC_PREC_FP32 : RHMC_PREC_FP64, ns);
+    const int rgrid = gauge_hop_grid(g, RHMC_PREC_FP64, ns);
     const int vgrid = vec_blocks(n);
     for (int j = 0; j < ns; ++j) {
         d.in[j] = vec<VT>(w->p, n, j);
@@ -327,7 +330,7 @@ static rhmc_status enqueue_block(const rhmc_gauge* g, Workspace* w, const Proble
         set_variant(r64, g);
         RHMC_HIP_TRY(launch_fp64_op(g, d64, kModeD, s));
         RHMC_HIP_TRY(launch_fp64_op(g, r64, kModeResid, s));
-        RHMC_HIP_TRY(launch_finalize(kFinReliable, w->st, w->partial, dgrid, ns, nullptr, s));
+        RHMC_HIP_TRY(launch_finalize(kFinReliable, w->st, w->partial, rgrid, ns, nullptr, s));
         if (f32) {
             // <r, p> with the replaced r: alpha of the next step (state.h)
             Dot32Args dp{};
@@ -609,7 +612,7 @@ static rhmc_status true_residuals(rhmc_gauge* g, const Problem& pb, const std::v
         set_variant(r, g);
         RHMC_HIP_TRY(launch_fp64_op(g, d, kModeD, s));
         RHMC_HIP_TRY(launch_fp64_op(g, r, kModeResid, s));
-        RHMC_HIP_TRY(launch_finalize(kFinNorms, nullptr, w->partial, dslash_grid(g->lat.geom.Vh), cnt,
+        RHMC_HIP_TRY(launch_finalize(kFinNorms, nullptr, w->partial, gauge_hop_grid(g, RHMC_PREC_FP64, cnt), cnt,
                                      w->sums, s));
         RHMC_HIP_TRY(hipMemcpyAsync(w->sums_host, w->sums, sizeof(double) * cnt,
                                     hipMemcpyDeviceToHost, s));

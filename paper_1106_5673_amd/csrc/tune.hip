@@ -8,19 +8,19 @@
 namespace rhmc {
 
 void default_hop_variants(int (&v)[2][4]) {
-    // index = order | nt << 2 | batch << 3 | occ << 5
-    // measured on MI355X at 48^3 x 12 (rhs classes 1, 2, 4, 8): z-tiles with
-    // t inside a tile keep the neighbour vectors of a wave's sites in L2; the
-    // links, read once, are streamed (non-temporal); loads go in batches of
-    // one to four hops (the one-rhs kernels have registers to spare)
-    const int fp64[4] = {39, 47, 14, 46};    // FP64-12 links (the default FP64 storage)
-    const int fp32[4] = {17, 83, 14, 102};
+    // index = order + 8 * batch + 24 * stage
+    // measured on MI355X at 48^3 x 12 (rhs classes 1, 2, 4, 8): z-tiles of 6
+    // planes (one XCD's share of z at Lz = 48) with t inside a tile; rows
+    // staged in LDS except for eight right-hand sides, whose staged rows do
+    // not fit three blocks per CU; loads in batches of one to four hops
+    const int fp64[4] = {52, 28, 28, 11};    // FP64-12 links (the default FP64 storage)
+    const int fp32[4] = {44, 36, 36, 12};
     for (int k = 0; k < 4; ++k) {
         v[RHMC_PREC_FP64][k] = fp64[k];
         v[RHMC_PREC_FP32][k] = fp32[k];
     }
     if (const char* e = std::getenv("RHMC_HOP_VARIANT")) {
-        const int f = std::atoi(e) & (kHopVariants - 1);
+        const int f = std::abs(std::atoi(e)) % kHopVariants;
         for (auto& row : v)
             for (int& x : row) x = f;
     }

@@ -78,16 +78,15 @@ def test_product_path_has_no_oracle_import():
 
 
 def test_lattice_rejects_too_many_sites(rh):
-    """Site indices are 32-bit: V above 2^28 is refused before any allocation."""
+    """Link planes are addressed with 32-bit byte offsets: V above 2^26 is
+    refused before any allocation."""
     with pytest.raises(rh.RhmcError) as e:
-        rh.rhmc_lattice_create((256, 256, 128, 64))
+        rh.rhmc_lattice_create((128, 128, 64, 128))
     assert e.value.status == rh.RHMC_ERR_INVALID_ARG
 
 
 def test_variant_encoding_limits(rh):
-    """The launch-variant index has 7 bits (order, nt, batch, occ)."""
-    import re
-
+    """The launch-variant index is order + 8 * batch + 24 * stage (72 variants)."""
     hdr = open(os.path.join(ROOT, "include", "rhmc.h")).read()
-    assert "0 <= variant < 128" in hdr
-    assert re.search(r"batch << 3 \| occ << 5", hdr)
+    assert "0 <= variant < 72" in hdr
+    assert "order + 8 * batch + 24 * stage" in hdr
