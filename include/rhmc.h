@@ -98,7 +98,11 @@ typedef struct {
     int32_t refine;         /* nonzero: shifts whose FP64 true residual exceeds tol get a
                                warm-started CG on their own system (default 1) */
     int32_t block;          /* iterations between updates of the shifted solutions (1..50,
-                               default 32; MIXED rounds reliable_every up to a multiple) */
+                               default 32).  MIXED replaces the residual at a block boundary
+                               and so uses the divisor of reliable_every nearest to block
+                               (between block/2 and 50; 25 for 50 and 32): replacements
+                               fall exactly every reliable_every iterations.  Without such a
+                               divisor block is kept and the cadence rounds up. */
     int32_t use_graph;      /* nonzero: replay each block of iterations as a hipGraph (default 1) */
     int32_t poll_every;     /* blocks launched between convergence polls (0 = automatic) */
     int32_t tune;           /* nonzero: time the Dslash launch shapes once and keep the best */
@@ -142,6 +146,13 @@ typedef struct {
     double time_ms;             /* host wall time of the call */
     double max_true_residual;
     int32_t fp64_head_iterations; /* MIXED: iterations of the shared solve run in FP64 */
+    /* host wall time of each phase (ms, summed over groups of right-hand
+     * sides; the phases end at host synchronisations, so they add up to the
+     * solve part of time_ms) */
+    double head_ms;     /* MIXED: the FP64 phase of the shared solve */
+    double krylov_ms;   /* the shared solve after it (all of it in FP64 mode) */
+    double check_ms;    /* FP64 true residuals of every shift, first check and rechecks */
+    double refine_ms;   /* refinement solves of the shifts above tol */
 } rhmc_solver_stats;
 
 typedef struct {

@@ -6,7 +6,8 @@
 // each link is read once per application however many vectors are batched.
 // Links are structure-of-arrays over the link index k = (2*mu + parity)*Vh + eo,
 // so the 64 lanes of a wave read 64 consecutive links per load; neighbour
-// vectors are colour-major [3][Vh] arrays, read by consecutive sites.
+// vectors are colour-major [3][Vh] arrays, read by consecutive sites (or,
+// for the +-x and +-y hops of a staged block, from LDS).
 #pragma once
 
 #include "common.h"
@@ -21,7 +22,10 @@ struct Link {
 
 typedef double d2v __attribute__((ext_vector_type(2)));
 typedef float f4v __attribute__((ext_vector_type(4)));
+typedef float f2v __attribute__((ext_vector_type(2)));
 
+// Loads from global memory (address space 1); NT: non-temporal (streamed,
+// read once by this kernel).
 template <typename T>
 using gp = const __attribute__((address_space(1))) T*;
 
@@ -35,33 +39,6 @@ __device__ __forceinline__ double2 ldg(gp<double2> p) {
     else
         v = *q;
     return make_double2(v.x, v.y);
-}
-
-template <bool NT>
-__device__ __forceinline__ float4 ldg(gp<float4> p);
-template <bool NT>
-__device__ __forceinline__ float2 ldg(gp<float2> p);
-
-template <bool NT>
-__device__ __forceinline__ double2 ldg(const double2* p) {
-    if constexpr (NT) {
-        const d2v v = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(p));
-        return make_double2(v.x, v.y);
-    } else {
-        return *p;
-    }
-}
-
-typedef float f2v __attribute__((ext_vector_type(2)));
-
-template <bool NT>
-__device__ __forceinline__ float2 ldg(const float2* p) {
-    if constexpr (NT) {
-        const f2v v = __builtin_nontemporal_load(reinterpret_cast<const f2v*>(p));
-        return make_float2(v.x, v.y);
-    } else {
-        return *p;
-    }
 }
 
 template <bool NT>
@@ -86,16 +63,6 @@ __device__ __forceinline__ float4 ldg(gp<float4> p) {
     else
         v = *q;
     return make_float4(v.x, v.y, v.z, v.w);
-}
-
-template <bool NT>
-__device__ __forceinline__ float4 ldg(const float4* p) {
-    if constexpr (NT) {
-        const f4v v = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(p));
-        return make_float4(v.x, v.y, v.z, v.w);
-    } else {
-        return *p;
-    }
 }
 
 // The planes of a structure-of-arrays field (link entries, colour planes of
@@ -253,62 +220,8 @@ template <typename VT> struct RealOf;
 template <> struct RealOf<double2> { using T = double; };
 template <> struct RealOf<float2> { using T = float; };
 
-// Vector access through buffer resources: one resource per right-hand side
-// (base address in scalar registers), the colour plane as the scalar offset
-// and the site as the per-lane offset, so a load needs no per-lane address
-// arithmetic.  The lattice volume is capped so that 3 * Vh * 16 bytes fits
-// the 32-bit buffer range.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t vec_rsrc(const void* p, int Vh, int bytes_per) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, 3 * Vh * bytes_per,
-                                             0x00020000);
-}
-constexpr int kBufNT = 2;   // aux bit 1: non-temporal (data not reused by this kernel)
-
-template <int AUX>
-__device__ __forceinline__ float2 buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, float2*) {
-    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, AUX);
-    float2 o;
-    __builtin_memcpy(&o, &v, 8);
-    return o;
-}
-template <int AUX>
-__device__ __forceinline__ double2 buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, double2*) {
-    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, AUX);
-    double2 o;
-    __builtin_memcpy(&o, &v, 16);
-    return o;
-}
-template <int AUX>
-__device__ __forceinline__ void buf_st(float2 x, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-    __attribute__((ext_vector_type(2))) unsigned int v;
-    __builtin_memcpy(&v, &x, 8);
-    __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, soff, AUX);
-}
-template <int AUX>
-__device__ __forceinline__ void buf_st(double2 x, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-    __attribute__((ext_vector_type(4))) unsigned int v;
-    __builtin_memcpy(&v, &x, 16);
-    __builtin_amdgcn_raw_buffer_store_b128(v, r, voff, soff, AUX);
-}
-
 __device__ __forceinline__ float fmar(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmar(double a, double b, double c) { return __builtin_fma(a, b, c); }
-
-// Value of lane (lane ^ 1) or (lane ^ 2) of the same quad (DPP quad_perm),
-// for the exchange between the lanes that share one output site.
-template <int CTRL>
-__device__ __forceinline__ float quad_xor(float v) {
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
-}
-template <int CTRL>
-__device__ __forceinline__ double quad_xor(double v) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-constexpr int kQuadXor1 = 0xB1;   // quad_perm [1, 0, 3, 2]
-constexpr int kQuadXor2 = 0x4E;   // quad_perm [2, 3, 0, 1]
 
 // One hop for every right-hand side: S += s * (U v) (forward) or
 // S += s * (U^dagger v) (backward), with s = +-1/2.  The input is scaled by s

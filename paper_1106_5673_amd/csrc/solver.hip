@@ -30,6 +30,15 @@
 
 namespace rhmc {
 
+using Clock = std::chrono::steady_clock;
+// milliseconds since t; t moves to now
+static double ms_since(Clock::time_point& t) {
+    const auto now = Clock::now();
+    const double d = std::chrono::duration<double, std::milli>(now - t).count();
+    t = now;
+    return d;
+}
+
 struct GraphKey {
     int nsys = 0, nshift = 0, K = 0, mode = -1, reliable = 0;
     const void* b[kMaxSys] = {};
@@ -536,13 +545,16 @@ static rhmc_status run_krylov(rhmc_gauge* g, const Problem& pb, hipStream_t s, i
 // reliable updates from the same scalar state.  The first FP32 step takes the
 // exact line search, as after a residual replacement.
 static rhmc_status run_mixed(rhmc_gauge* g, const Problem& pb, hipStream_t s, int* iters_out,
-                             int* reliable_out, int* head_out) {
+                             int* reliable_out, int* head_out, double* head_ms) {
     *head_out = 0;
+    *head_ms = 0.0;
     if (!(pb.head_rel > 0.0)) return run_krylov<float2>(g, pb, s, iters_out, reliable_out);
+    auto th = Clock::now();
     Problem ph = pb;
     ph.mode = RHMC_MODE_FP64;
     RHMC_TRY(krylov_init<double2>(g, ph, s));
-    RHMC_TRY(krylov_loop<double2>(g, ph, true, s));
+    RHMC_TRY(krylov_loop<double2>(g, ph, true, s));   // ends synchronised
+    *head_ms = ms_since(th);
     Workspace* w = g->ws;
     const SolverState* h = w->hst;
     *head_out = h->iter;
@@ -642,7 +654,9 @@ static double mixed_head(const rhmc_solver_params& prm) {
 
 static rhmc_status solve_impl(rhmc_gauge* g, Problem pb, const rhmc_solver_params& prm,
                               rhmc_solver_stats* stats, hipStream_t s) {
-    const auto t0 = std::chrono::steady_clock::now();
+    const auto t0 = Clock::now();
+    auto tp = t0;   // end of the previous phase
+    double head_ms = 0.0, krylov_ms = 0.0, check_ms = 0.0, refine_ms = 0.0;
     int iters = 0, rel = 0, head = 0;
     const bool per_shift = prm.per_shift != 0;
     const int total = pb.nsys * pb.nshift;
@@ -651,9 +665,10 @@ static rhmc_status solve_impl(rhmc_gauge* g, Problem pb, const rhmc_solver_param
     std::vector<double> res(total), res2(total);
     if (!per_shift) {
         if (pb.mode == RHMC_MODE_MIXED)
-            RHMC_TRY(run_mixed(g, pb, s, &iters, &rel, &head));
+            RHMC_TRY(run_mixed(g, pb, s, &iters, &rel, &head, &head_ms));
         else
             RHMC_TRY(run_krylov<double2>(g, pb, s, &iters, &rel));
+        krylov_ms = ms_since(tp) - head_ms;
         const SolverState hs = *g->ws->hst;
         for (int j = 0; j < pb.nsys; ++j)
             for (int i = 0; i < pb.nshift; ++i) {
@@ -668,6 +683,7 @@ static rhmc_status solve_impl(rhmc_gauge* g, Problem pb, const rhmc_solver_param
             const int j = p / pb.nshift;
             res[p] = bnorm[j] > 0 ? std::sqrt(res2[p]) / bnorm[j] : 0.0;
         }
+        check_ms += ms_since(tp);
     } else {
         // every shifted system from a zero start: the residual is b, and the
         // batched per-shift CG below (the refinement loop) solves each system
@@ -751,15 +767,18 @@ static rhmc_status solve_impl(rhmc_gauge* g, Problem pb, const rhmc_solver_param
             }
             RHMC_HIP_TRY(launch_add(ad, cnt, s));
         }
+        RHMC_HIP_TRY(hipStreamSynchronize(s));
+        refine_ms += ms_since(tp);
         RHMC_TRY(true_residuals(g, pb, bad, res2.data(), nullptr, s));
         for (size_t k = 0; k < bad.size(); ++k) {
             const int p = bad[k];
             const int j = p / pb.nshift;
             res[p] = bnorm[j] > 0 ? std::sqrt(res2[k]) / bnorm[j] : 0.0;
         }
+        check_ms += ms_since(tp);
     }
     RHMC_HIP_TRY(hipStreamSynchronize(s));
-    const auto t1 = std::chrono::steady_clock::now();
+    const auto t1 = Clock::now();
 
     double worst = 0.0;
     bool ok = true;
@@ -786,6 +805,10 @@ static rhmc_status solve_impl(rhmc_gauge* g, Problem pb, const rhmc_solver_param
         stats->fp64_head_iterations = head;
         stats->time_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
         stats->max_true_residual = worst;
+        stats->head_ms = head_ms;
+        stats->krylov_ms = krylov_ms;
+        stats->check_ms = check_ms;
+        stats->refine_ms = refine_ms;
     }
     for (int p = 0; p < total; ++p)
         if (!std::isfinite(res[p])) {
@@ -797,6 +820,25 @@ static rhmc_status solve_impl(rhmc_gauge* g, Problem pb, const rhmc_solver_param
         return RHMC_ERR_NOT_CONVERGED;
     }
     return RHMC_OK;
+}
+
+// Iterations per block.  A residual replacement (MIXED) needs the shifted
+// solutions flushed, i.e. a block boundary, so in MIXED mode the block length
+// is the divisor of reliable_every nearest to the requested one (at most
+// kMaxBlockLen, at least half the request): the replacements then fall exactly
+// every reliable_every iterations (50 -> blocks of 25 for the default 32).
+// Without such a divisor the request is kept and the cadence rounds up.
+static int block_length(const rhmc_solver_params& prm) {
+    const int want = std::max(1, std::min(kMaxBlockLen, prm.block));
+    if (prm.mode != RHMC_MODE_MIXED || prm.reliable_every <= 0) return want;
+    int best = 0;
+    for (int d = std::max(1, want / 2); d <= kMaxBlockLen; ++d) {
+        if (prm.reliable_every % d) continue;
+        if (!best || std::abs(d - want) < std::abs(best - want) ||
+            (std::abs(d - want) == std::abs(best - want) && d > best))
+            best = d;
+    }
+    return best ? best : want;
 }
 
 // The shared solve of nrhs <= kMaxSys right-hand sides b[j] (stride n) for
@@ -812,7 +854,7 @@ static Problem make_problem(const rhmc_gauge* g, double m, int nshift, const dou
             smin = shifts[i];
             base = i;
         }
-    const int K = std::max(1, std::min(kMaxBlockLen, prm.block));
+    const int K = block_length(prm);
     Problem pb{};
     pb.nsys = nrhs;
     pb.nshift = nshift;
@@ -829,7 +871,7 @@ static Problem make_problem(const rhmc_gauge* g, double m, int nshift, const dou
     pb.x_shift = x_shift;
     pb.mode = prm.mode;
     pb.K = K;
-    pb.reliable_blocks = std::max(1, (prm.reliable_every + K - 1) / K);
+    pb.reliable_blocks = std::max(1, (prm.reliable_every + K - 1) / K);   // exact when K divides it
     pb.maxiter = prm.maxiter;
     pb.head_rel = mixed_head(prm);
     pb.use_graph = prm.use_graph != 0;
@@ -843,7 +885,10 @@ rhmc_status multishift(rhmc_gauge* g, double m, int nshift, const double* shifts
                        const rhmc_solver_params& prm, rhmc_solver_stats* stats, hipStream_t s) {
     const size_t n = (size_t)3 * g->lat.Vh;
     rhmc_solver_stats acc{};
-    // process the right-hand sides in groups of kMaxSys
+    // process the right-hand sides in groups of kMaxSys; a group that ends
+    // NOT_CONVERGED keeps its last iterates and the later groups are still
+    // solved, so every output and every stat is written (worst status returned)
+    rhmc_status worst = RHMC_OK;
     for (int r0 = 0; r0 < nrhs; r0 += kMaxSys) {
         const int cnt = std::min(kMaxSys, nrhs - r0);
         const Problem pb = make_problem(g, m, nshift, shifts, cnt, b + (size_t)r0 * n,
@@ -862,7 +907,15 @@ rhmc_status multishift(rhmc_gauge* g, double m, int nshift, const double* shifts
         acc.fp64_head_iterations = std::max(acc.fp64_head_iterations, st.fp64_head_iterations);
         acc.time_ms += st.time_ms;
         acc.max_true_residual = std::max(acc.max_true_residual, st.max_true_residual);
+        acc.head_ms += st.head_ms;
+        acc.krylov_ms += st.krylov_ms;
+        acc.check_ms += st.check_ms;
+        acc.refine_ms += st.refine_ms;
         if (stats) {
+            stats->head_ms = acc.head_ms;
+            stats->krylov_ms = acc.krylov_ms;
+            stats->check_ms = acc.check_ms;
+            stats->refine_ms = acc.refine_ms;
             stats->total_iterations = acc.total_iterations;
             stats->reliable_updates = acc.reliable_updates;
             stats->refine_rounds = acc.refine_rounds;
@@ -870,9 +923,13 @@ rhmc_status multishift(rhmc_gauge* g, double m, int nshift, const double* shifts
             stats->time_ms = acc.time_ms;
             stats->max_true_residual = acc.max_true_residual;
         }
-        if (rs != RHMC_OK) return rs;
+        if (rs == RHMC_ERR_NOT_CONVERGED)
+            worst = rs;
+        else if (rs != RHMC_OK)
+            return rs;
     }
-    return RHMC_OK;
+    if (worst != RHMC_OK) set_error("some shift did not reach the requested tolerance");
+    return worst;
 }
 
 // Two-pass rational apply (FP64), a variant of the shared Krylov solve of
@@ -994,10 +1051,11 @@ rhmc_status rational(rhmc_gauge* g, double m, const rhmc_rational* rat, int nrhs
     if (prm.two_pass) return rational_two_pass(g, m, rat, nrhs, b, y, prm, stats, s);
     const size_t n = (size_t)3 * g->lat.Vh;
     const int np = rat->npole;
-    const int K = std::max(1, std::min(kMaxBlockLen, prm.block));
+    const int K = block_length(prm);
     RHMC_TRY(ensure_workspace(g, std::min(nrhs, kMaxSys), np, K));
     double2* xr = nullptr;
     RHMC_TRY(ensure_rational_buffer(g, (size_t)std::min(nrhs, kMaxSys) * np, &xr));
+    rhmc_status worst = RHMC_OK;   // every group is solved and combined
     for (int r0 = 0; r0 < nrhs; r0 += kMaxSys) {
         const int cnt = std::min(kMaxSys, nrhs - r0);
         rhmc_solver_stats st{};
@@ -1017,6 +1075,10 @@ rhmc_status rational(rhmc_gauge* g, double m, const rhmc_rational* rat, int nrhs
                 std::max(stats->fp64_head_iterations, st.fp64_head_iterations);
             stats->time_ms += st.time_ms;
             stats->max_true_residual = std::max(stats->max_true_residual, st.max_true_residual);
+            stats->head_ms += st.head_ms;
+            stats->krylov_ms += st.krylov_ms;
+            stats->check_ms += st.check_ms;
+            stats->refine_ms += st.refine_ms;
         }
         if (rs != RHMC_OK && rs != RHMC_ERR_NOT_CONVERGED) return rs;
         CombineArgs c{};
@@ -1031,17 +1093,18 @@ rhmc_status rational(rhmc_gauge* g, double m, const rhmc_rational* rat, int nrhs
             c.y[j] = y + (size_t)(r0 + j) * n;
         }
         RHMC_HIP_TRY(launch_combine(c, cnt, s));
-        if (rs != RHMC_OK) return rs;
+        if (rs != RHMC_OK) worst = rs;
     }
     RHMC_HIP_TRY(hipStreamSynchronize(s));
-    return RHMC_OK;
+    if (worst != RHMC_OK) set_error("some shift did not reach the requested tolerance");
+    return worst;
 }
 
 rhmc_status pf_action(rhmc_gauge* g, double m, const rhmc_rational* rat, int nrhs,
                       const double2* phi, double* S, const rhmc_solver_params& prm,
                       rhmc_solver_stats* stats, hipStream_t s) {
     const size_t n = (size_t)3 * g->lat.Vh;
-    const int K = std::max(1, std::min(kMaxBlockLen, prm.block));
+    const int K = block_length(prm);
     RHMC_TRY(ensure_workspace(g, std::min(nrhs, kMaxSys), rat->npole, K));
     Workspace* w = g->ws;
     RHMC_TRY(grow(w, (void**)&w->ya, &w->ya_cap, w->vec_bytes * (size_t)nrhs));
@@ -1072,7 +1135,7 @@ rhmc_status pf_force(rhmc_gauge* g, double m, const rhmc_rational* rat, int nrhs
     const size_t n = (size_t)3 * g->lat.Vh;
     const int np = rat->npole;
     const int grp = std::min(nrhs, kMaxSys);
-    const int K = std::max(1, std::min(kMaxBlockLen, prm.block));
+    const int K = block_length(prm);
     RHMC_TRY(ensure_workspace(g, grp, np, K));
     Workspace* w = g->ws;
     double2* xr = nullptr;

@@ -66,7 +66,8 @@ class rhmc_solver_stats(C.Structure):
                 ("refine_iterations", C.POINTER(C.c_int32)), ("total_iterations", C.c_int32),
                 ("reliable_updates", C.c_int32), ("refine_rounds", C.c_int32),
                 ("time_ms", C.c_double), ("max_true_residual", C.c_double),
-                ("fp64_head_iterations", C.c_int32)]
+                ("fp64_head_iterations", C.c_int32), ("head_ms", C.c_double),
+                ("krylov_ms", C.c_double), ("check_ms", C.c_double), ("refine_ms", C.c_double)]
 
 
 class rhmc_rational(C.Structure):
@@ -304,6 +305,10 @@ class _Stats:
             time_ms=float(self.c.time_ms),
             max_true_residual=float(self.c.max_true_residual),
             fp64_head_iterations=int(self.c.fp64_head_iterations),
+            head_ms=float(self.c.head_ms),
+            krylov_ms=float(self.c.krylov_ms),
+            check_ms=float(self.c.check_ms),
+            refine_ms=float(self.c.refine_ms),
         )
 
 

@@ -34,6 +34,10 @@ int main(void) {
     FIELD(rhmc_solver_stats, time_ms);
     FIELD(rhmc_solver_stats, max_true_residual);
     FIELD(rhmc_solver_stats, fp64_head_iterations);
+    FIELD(rhmc_solver_stats, head_ms);
+    FIELD(rhmc_solver_stats, krylov_ms);
+    FIELD(rhmc_solver_stats, check_ms);
+    FIELD(rhmc_solver_stats, refine_ms);
 
     SIZE(rhmc_rational);
     FIELD(rhmc_rational, alpha0);

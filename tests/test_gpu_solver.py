@@ -403,3 +403,70 @@ def test_invalid_solver_params_rejected(rh):
         x, st = _solve(rh, g, lat, 0.1, [0.0, 0.2], b, tol=1e-10, **kw)
         assert st["max_true_residual"] <= 1e-10
     g.close()
+
+
+@pytest.mark.parametrize("nrhs", [9, 16])
+def test_not_converged_groups_all_written(rh, nrhs):
+    """More than eight right-hand sides run as groups of eight.  A group that
+    ends NOT_CONVERGED (maxiter too small) keeps its last iterates, and every
+    later group is still solved: every x, y, S and stat is written and equals
+    what the same group gives when solved alone."""
+    import torch
+
+    L = (8, 8, 4, 4)
+    m = 0.01
+    U, b, lat, g = _setup(rh, L, 0.6, 5800, nrhs, 6800)
+    shifts = [0.0, 0.05]
+    kw = dict(tol=1e-10, maxiter=30, refine=0)
+    x = torch.full((nrhs, len(shifts), 3, lat.Vh), float("nan"), dtype=torch.complex128,
+                   device="cuda:0")
+    st = rh.rhmc_multishift_cg(g, m, shifts, _to(b), x, rh.solver_params(**kw),
+                               allow_not_converged=True)
+    assert st["status"] == rh.RHMC_ERR_NOT_CONVERGED
+    xs = x.cpu().numpy()
+    assert np.all(np.isfinite(xs)) and np.all(np.abs(xs).reshape(nrhs, -1).max(axis=1) > 0)
+    assert np.all(st["iterations"] > 0) and np.all(np.isfinite(st["true_residual"]))
+    assert np.all(st["true_residual"] > 1e-10)
+    x8, st8 = _solve(rh, g, lat, m, shifts, b[8:], allow_not_converged=True, **kw)
+    assert np.array_equal(xs[8:], x8)
+    assert np.array_equal(st["true_residual"][8:], st8["true_residual"])
+
+    r = rational_for(1, -0.25)
+    y = torch.full((nrhs, 3, lat.Vh), float("nan"), dtype=torch.complex128, device="cuda:0")
+    st = rh.rhmc_rational_apply(g, m, r.alpha0, r.alpha, r.beta, _to(b), y, rh.solver_params(**kw),
+                                allow_not_converged=True)
+    assert st["status"] == rh.RHMC_ERR_NOT_CONVERGED
+    ys = y.cpu().numpy()
+    assert np.all(np.isfinite(ys))
+    y8 = torch.empty((nrhs - 8, 3, lat.Vh), dtype=torch.complex128, device="cuda:0")
+    rh.rhmc_rational_apply(g, m, r.alpha0, r.alpha, r.beta, _to(b[8:]), y8, rh.solver_params(**kw),
+                           allow_not_converged=True)
+    assert np.array_equal(ys[8:], y8.cpu().numpy())
+
+    S, st = rh.rhmc_pf_action(g, m, r.alpha0, r.alpha, r.beta, _to(b), rh.solver_params(**kw),
+                              allow_not_converged=True)
+    assert st["status"] == rh.RHMC_ERR_NOT_CONVERGED
+    assert np.all(np.isfinite(S)) and np.all(S > 0)
+    S8, _ = rh.rhmc_pf_action(g, m, r.alpha0, r.alpha, r.beta, _to(b[8:]), rh.solver_params(**kw),
+                              allow_not_converged=True)
+    assert np.array_equal(S[8:], S8)
+    g.close()
+
+
+@pytest.mark.parametrize("reliable_every,block", [(50, 32), (30, 32), (50, 50)])
+def test_mixed_replacement_cadence_is_exact(rh, reliable_every, block):
+    """MIXED replaces the residual every reliable_every FP32 iterations
+    exactly: the block length is the divisor of reliable_every nearest to the
+    requested one (25 for 50 and 32, 30 for 30 and 32), so the count of
+    replacements is the FP32 iteration count divided by reliable_every."""
+    L = (8, 8, 8, 8)
+    m = 0.05
+    U, b, lat, g = _setup(rh, L, 0.6, 5900, 1, 6900)
+    x, st = _solve(rh, g, lat, m, [0.0], b, tol=1e-10, mode=rh.RHMC_MODE_MIXED,
+                   reliable_every=reliable_every, block=block, fp64_head=-1.0, refine=0)
+    it = st["total_iterations"]
+    assert it > 2 * reliable_every
+    assert st["reliable_updates"] in (it // reliable_every - 1, it // reliable_every)
+    res = solvers.true_residual(lambda v: dirac.mdagm(U, m, v), b[0], x[0, 0], 0.0)
+    assert res <= 1e-10
+    g.close()
