@@ -351,12 +351,14 @@ def test_mixed_fp64_head(rh, head, use_graph, block):
 def test_mixed_fp64_head_below_tol_is_the_fp64_solve(rh):
     """With the FP64 phase threshold below tol the phase runs to convergence:
     the MIXED call then launches exactly the kernels of the plain FP64 solve
-    (deterministic reductions), so the solutions are bit-identical."""
+    with the same block length (MIXED turns the default 32 into 25, a divisor
+    of the 50 iterations between replacements), so with deterministic
+    reductions the solutions are bit-identical."""
     L = (6, 4, 4, 8)
     U, b, lat, g = _setup(rh, L, 0.6, 5252, 3, 6252)
     m = 0.02
     shifts = rational_for(1, -0.25).beta
-    x64, st64 = _solve(rh, g, lat, m, shifts, b, tol=1e-10, mode=rh.RHMC_MODE_FP64)
+    x64, st64 = _solve(rh, g, lat, m, shifts, b, tol=1e-10, mode=rh.RHMC_MODE_FP64, block=25)
     xm, stm = _solve(rh, g, lat, m, shifts, b, tol=1e-10, mode=rh.RHMC_MODE_MIXED, fp64_head=1e-12)
     assert stm["fp64_head_iterations"] == stm["total_iterations"] == st64["total_iterations"]
     assert stm["reliable_updates"] == 0
