@@ -206,6 +206,20 @@ rhmc_status rhmc_dslash_eo(const rhmc_gauge* g, int32_t out_parity, rhmc_prec pr
 rhmc_status rhmc_apply_mdagm(const rhmc_gauge* g, double m, rhmc_prec prec, int32_t nrhs,
                              const void* in, void* out, hipStream_t stream);
 
+/* rhmc_apply_mdagm that allocates nothing, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  The odd-site temporary and the block partial sums
+ * live in a static device array of 64 MiB that each GPU holds for the life of
+ * the process; the call needs 8 * 8 * ceil(Vh/64) bytes (rounded up to 256)
+ * plus nrhs * 3 * Vh * (16 | 8) bytes (FP64 | FP32) of it, and returns
+ * RHMC_ERR_INVALID_ARG with nothing launched when that exceeds 64 MiB (e.g.
+ * 48^3 x 12: up to 4 rhs in FP32, 2 in FP64).  All calls on one GPU share the
+ * array, which keeps the last call's contents (nothing in it needs to start at
+ * zero): calls that overlap on one GPU (other streams or host threads) race.
+ * Same arguments, layouts, result bits and asynchrony as rhmc_apply_mdagm. */
+rhmc_status rhmc_apply_mdagm_static(const rhmc_gauge* g, double m, rhmc_prec prec, int32_t nrhs,
+                                    const void* in, void* out, hipStream_t stream);
+
 /* Multi-shift CG (Sec. 4.3, Eq. shifted): x[r][i] = (A + shifts[i])^-1 b[r] for
  * every right-hand side r < nrhs and shift i < nshift, from the Krylov space of
  * the smallest shift with a zero starting guess.

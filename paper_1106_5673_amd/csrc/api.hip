@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -29,6 +30,46 @@ static rhmc_status use_device(int dev) {
     return RHMC_OK;
 }
 
+// ---------------------------------------------------------------- static scratch
+// Device memory of rhmc_apply_mdagm_static: the odd-parity temporary and the
+// block partial sums of A live in this array instead of buffers the gauge
+// object allocates.  Each GPU holds its own copy for the life of the process;
+// its address is looked up once per device, with that device current, and
+// only that address is passed to kernels.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mutex;
+static void* g_scratch_addr[kMaxDevices] = {};
+
+// Address of this device's scratch (the device must be current).
+static rhmc_status scratch_address(int dev, unsigned char** out) {
+    if (dev < 0 || dev >= kMaxDevices) return invalid("device index out of range for the static scratch");
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_addr[dev]) {
+        void* p = nullptr;
+        RHMC_HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) {
+            set_error("hipGetSymbolAddress returned no address for the static scratch");
+            return RHMC_ERR_HIP;
+        }
+        g_scratch_addr[dev] = p;
+    }
+    *out = static_cast<unsigned char*>(g_scratch_addr[dev]);
+    return RHMC_OK;
+}
+
+// Bytes of scratch rhmc_apply_mdagm_static needs: the partial sums (rounded
+// up to 256 bytes), then nrhs odd-parity vectors.
+static size_t static_mdagm_bytes(const rhmc_gauge* g, rhmc_prec prec, int nrhs, size_t* part_bytes) {
+    const size_t pb = sizeof(double) * kMaxSys * (size_t)max_hop_grid((int)g->lat.Vh);
+    *part_bytes = (pb + 255) & ~size_t(255);
+    const size_t vb = prec == RHMC_PREC_FP64 ? sizeof(double2) : sizeof(float2);
+    return *part_bytes + vb * (size_t)3 * g->lat.Vh * nrhs;
+}
+
+
 // Odd-parity temporary of the gauge object, grown on demand.
 static rhmc_status tmp_odd(rhmc_gauge* g, size_t bytes, void** out) {
     if (g->tmp_odd_bytes < bytes) {
@@ -44,9 +85,11 @@ static rhmc_status tmp_odd(rhmc_gauge* g, size_t bytes, void** out) {
 
 template <typename VT>
 static rhmc_status hop(rhmc_gauge* g, int out_par, rhmc_prec prec, int nrhs, const void* in,
-                       void* out, int mode, const void* self, double c, hipStream_t s) {
+                       void* out, int mode, const void* self, double c, hipStream_t s,
+                       double* partial_buf = nullptr) {
     const size_t n = (size_t)3 * g->lat.Vh;
-    double* partial = g->partial;   // kModeA partial sums nobody reads
+    // kModeA partial sums nobody reads: [kMaxSys][max_hop_grid] doubles
+    double* partial = partial_buf ? partial_buf : g->partial;
     for (int r0 = 0; r0 < nrhs; r0 += kMaxSys) {
         const int cnt = nrhs - r0 < kMaxSys ? nrhs - r0 : kMaxSys;
         DslashArgs<VT> a{};
@@ -296,6 +339,35 @@ rhmc_status rhmc_apply_mdagm(const rhmc_gauge* gc, double m, rhmc_prec prec, int
     }
     RHMC_TRY(hop<float2>(g, 1, prec, nrhs, in, t, kModeD, nullptr, 0.0, stream));
     return hop<float2>(g, 0, prec, nrhs, t, out, kModeA, in, m * m, stream);
+}
+
+rhmc_status rhmc_apply_mdagm_static(const rhmc_gauge* gc, double m, rhmc_prec prec, int32_t nrhs,
+                                    const void* in, void* out, hipStream_t stream) {
+    rhmc_gauge* g = const_cast<rhmc_gauge*>(gc);
+    if (!g || !in || !out) return invalid("null argument");
+    if (nrhs < 1 || nrhs > 64) return invalid("nrhs must be in 1..64");
+    if (in == out) return invalid("in and out must not overlap");
+    if (!std::isfinite(m)) return invalid("m must be finite");
+    RHMC_TRY(check_prec(g, prec));
+    size_t part_bytes = 0;
+    const size_t need = static_mdagm_bytes(g, prec, nrhs, &part_bytes);
+    if (need > kScratchBytes)
+        return invalid("rhmc_apply_mdagm_static needs " + std::to_string(need) +
+                       " bytes of scratch (odd temporary and partial sums), above the " +
+                       std::to_string(kScratchBytes) + " of the static array; use rhmc_apply_mdagm");
+    RHMC_TRY(use_device(g->device));
+    unsigned char* base = nullptr;
+    RHMC_TRY(scratch_address(g->device, &base));
+    double* partial = reinterpret_cast<double*>(base);
+    void* t = base + part_bytes;
+    // nothing in the scratch needs to start at zero: D_oe writes every site
+    // of the temporary and the A launch writes every partial it owns
+    if (prec == RHMC_PREC_FP64) {
+        RHMC_TRY(hop<double2>(g, 1, prec, nrhs, in, t, kModeD, nullptr, 0.0, stream, partial));
+        return hop<double2>(g, 0, prec, nrhs, t, out, kModeA, in, m * m, stream, partial);
+    }
+    RHMC_TRY(hop<float2>(g, 1, prec, nrhs, in, t, kModeD, nullptr, 0.0, stream, partial));
+    return hop<float2>(g, 0, prec, nrhs, t, out, kModeA, in, m * m, stream, partial);
 }
 
 static rhmc_status check_shifts(double m, int nshift, const double* shifts) {

@@ -39,7 +39,8 @@ RHMC_MODE_MIXED = 1
 EXPORTED = (
     "rhmc_solver_params_default", "rhmc_lattice_create", "rhmc_lattice_destroy",
     "rhmc_debug_neighbors", "rhmc_gauge_create", "rhmc_gauge_destroy", "rhmc_dslash_eo",
-    "rhmc_apply_mdagm", "rhmc_multishift_cg", "rhmc_rational_apply", "rhmc_tune_dslash",
+    "rhmc_apply_mdagm", "rhmc_apply_mdagm_static", "rhmc_multishift_cg", "rhmc_rational_apply",
+    "rhmc_tune_dslash",
     "rhmc_dslash_variant", "rhmc_set_dslash_variant", "rhmc_pf_phi", "rhmc_pf_action",
     "rhmc_pf_force", "rhmc_gauge_action", "rhmc_gauge_force_kick", "rhmc_pf_force_kick",
     "rhmc_update_links", "rhmc_kinetic", "rhmc_gauge_links", "rhmc_md_params_default",
@@ -120,6 +121,7 @@ def load():
         "rhmc_gauge_destroy": (None, [vp]),
         "rhmc_dslash_eo": (i32, [vp, i32, i32, i32, vp, vp, vp]),
         "rhmc_apply_mdagm": (i32, [vp, f64, i32, i32, vp, vp, vp]),
+        "rhmc_apply_mdagm_static": (i32, [vp, f64, i32, i32, vp, vp, vp]),
         "rhmc_multishift_cg": (i32, [vp, f64, i32, C.POINTER(C.c_double), i32, vp, vp,
                                      C.POINTER(rhmc_solver_params), C.POINTER(rhmc_solver_stats), vp]),
         "rhmc_rational_apply": (i32, [vp, f64, C.POINTER(rhmc_rational), i32, vp, vp,
@@ -281,6 +283,16 @@ def rhmc_apply_mdagm(g: Gauge, m: float, prec: int, nrhs: int, inp, out, stream=
     _check(load().rhmc_apply_mdagm(g.handle, float(m), int(prec), int(nrhs),
                                    _ptr(inp, dt, (nrhs, 3, Vh), "in"), _ptr(out, dt, (nrhs, 3, Vh), "out"),
                                    _stream(stream)))
+
+
+def rhmc_apply_mdagm_static(g: Gauge, m: float, prec: int, nrhs: int, inp, out, stream=None):
+    """rhmc_apply_mdagm with its temporaries in the library's static device
+    scratch (no allocation)."""
+    Vh = g.lattice.Vh
+    dt = _vec_dtype(prec)
+    _check(load().rhmc_apply_mdagm_static(g.handle, float(m), int(prec), int(nrhs),
+                                          _ptr(inp, dt, (nrhs, 3, Vh), "in"),
+                                          _ptr(out, dt, (nrhs, 3, Vh), "out"), _stream(stream)))
 
 
 class _Stats:
