@@ -433,7 +433,10 @@ def main():
             src = bd[:k]
         else:
             src = torch.randn((k, 3, n), dtype=torch.complex128, device=dev)
-        vin = src.to(dt).contiguous()
+        # the ABI's storage of the set (FP32, k >= 2: pairs of vectors; k is 1
+        # or even here, so the entries are the sources in that storage)
+        assert k == 1 or k % 2 == 0
+        vin = src.to(dt).contiguous().reshape(rhmc.vec_shape(pr, k, n))
         vout = torch.empty_like(vin)
         for _ in range(warm):
             rhmc.rhmc_dslash_eo(gg, 1, pr, k, vin, vout)

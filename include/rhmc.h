@@ -25,10 +25,19 @@
  * Gauge    host complex128 [Lt][Lz][Ly][Lx][mu][row][col], (re, im)
  *          interleaved, each link in SU(3) (det = 1; the 12-real compressed
  *          copy reconstructs row 3 as conj(row1 x row2), Sec. 4.2).
- * Vectors  device colour vectors of one parity, [nrhs][3][Vh] complex, i.e.
- *          element (r, c, eo) at offset (r*3 + c)*Vh + eo; complex128
- *          (double2) for RHMC_PREC_FP64, complex64 (float2) for RHMC_PREC_FP32.
- *          Solver inputs and outputs are always complex128.
+ * Vectors  device colour vectors of one parity.  complex128 (double2) for
+ *          RHMC_PREC_FP64: [nrhs][3][Vh], element (r, c, eo) at offset
+ *          (r*3 + c)*Vh + eo.  complex64 (float2) for RHMC_PREC_FP32: one
+ *          vector is [3][Vh] (offset c*Vh + eo); two or more are interleaved
+ *          in pairs, pair q = (r = 2q, r = 2q + 1) being a [3][Vh] array of
+ *          16-byte (re, im of 2q, re, im of 2q + 1) entries, so element
+ *          (r, c, eo) is the complex64 at offset ((r/2)*3*Vh + c*Vh + eo)*2 +
+ *          r%2 and a set of nrhs vectors occupies 2*ceil(nrhs/2)*3*Vh complex64
+ *          (one 16-byte load then brings one colour of two vectors: the
+ *          hopping kernel is bound by its number of loads).  With odd nrhs
+ *          the second half of the last pair is read and overwritten with
+ *          unspecified values.  Solver inputs and outputs are always
+ *          complex128.
  * Streams  every call is enqueued on the caller's hipStream_t (0 = default
  *          stream).  rhmc_dslash_eo and rhmc_apply_mdagm are asynchronous;
  *          rhmc_multishift_cg and rhmc_rational_apply return after the
@@ -196,8 +205,8 @@ void rhmc_gauge_destroy(rhmc_gauge* g);
  * out_parity 0: out_even = D_eo in_odd;  1: out_odd = D_oe in_even.
  * prec FP64 uses the FP64 operator (FP64-12, FP64-18 or hi + lo links, see
  * rhmc_gauge_create) and complex128 vectors, FP32 the 12-real FP32 links and
- * complex64 vectors.  in and out: device [nrhs][3][Vh], must not
- * overlap.  1 <= nrhs <= 64. */
+ * complex64 vectors (paired when nrhs >= 2).  in and out: device vector sets
+ * of nrhs vectors in the layout above, must not overlap.  1 <= nrhs <= 64. */
 rhmc_status rhmc_dslash_eo(const rhmc_gauge* g, int32_t out_parity, rhmc_prec prec, int32_t nrhs,
                            const void* in, void* out, hipStream_t stream);
 
@@ -211,7 +220,8 @@ rhmc_status rhmc_apply_mdagm(const rhmc_gauge* g, double m, rhmc_prec prec, int3
  * that forbid hipMalloc).  The odd-site temporary and the block partial sums
  * live in a static device array of 64 MiB that each GPU holds for the life of
  * the process; the call needs 8 * 8 * ceil(Vh/64) bytes (rounded up to 256)
- * plus nrhs * 3 * Vh * (16 | 8) bytes (FP64 | FP32) of it, and returns
+ * plus one odd-parity vector set (nrhs * 3 * Vh * 16 bytes in FP64,
+ * 2 * ceil(nrhs/2) * 3 * Vh * 8 in FP32 with nrhs >= 2) of it, and returns
  * RHMC_ERR_INVALID_ARG with nothing launched when that exceeds 64 MiB (e.g.
  * 48^3 x 12: up to 4 rhs in FP32, 2 in FP64).  All calls on one GPU share the
  * array, which keeps the last call's contents (nothing in it needs to start at

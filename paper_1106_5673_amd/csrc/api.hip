@@ -7,6 +7,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "common.h"
@@ -60,13 +61,19 @@ static rhmc_status scratch_address(int dev, unsigned char** out) {
     return RHMC_OK;
 }
 
+// Bytes of a vector set of nrhs vectors of one parity (FP32 sets of two or
+// more are paired, with room for an even count).
+static size_t vec_set_bytes(const rhmc_gauge* g, rhmc_prec prec, int nrhs) {
+    const size_t n = (size_t)3 * g->lat.Vh;
+    return prec == RHMC_PREC_FP64 ? sizeof(double2) * n * nrhs : sizeof(float2) * f32_set_size(nrhs, n);
+}
+
 // Bytes of scratch rhmc_apply_mdagm_static needs: the partial sums (rounded
 // up to 256 bytes), then nrhs odd-parity vectors.
 static size_t static_mdagm_bytes(const rhmc_gauge* g, rhmc_prec prec, int nrhs, size_t* part_bytes) {
     const size_t pb = sizeof(double) * kMaxSys * (size_t)max_hop_grid((int)g->lat.Vh);
     *part_bytes = (pb + 255) & ~size_t(255);
-    const size_t vb = prec == RHMC_PREC_FP64 ? sizeof(double2) : sizeof(float2);
-    return *part_bytes + vb * (size_t)3 * g->lat.Vh * nrhs;
+    return *part_bytes + vec_set_bytes(g, prec, nrhs);
 }
 
 
@@ -90,6 +97,9 @@ static rhmc_status hop(rhmc_gauge* g, int out_par, rhmc_prec prec, int nrhs, con
     const size_t n = (size_t)3 * g->lat.Vh;
     // kModeA partial sums nobody reads: [kMaxSys][max_hop_grid] doubles
     double* partial = partial_buf ? partial_buf : g->partial;
+    // FP32 sets of two or more vectors are paired (f32_offset); launches
+    // over kMaxSys (even) of them at a time start at a pair
+    const bool pr = std::is_same<VT, float2>::value && paired_f32(nrhs);
     for (int r0 = 0; r0 < nrhs; r0 += kMaxSys) {
         const int cnt = nrhs - r0 < kMaxSys ? nrhs - r0 : kMaxSys;
         DslashArgs<VT> a{};
@@ -97,10 +107,12 @@ static rhmc_status hop(rhmc_gauge* g, int out_par, rhmc_prec prec, int nrhs, con
         a.out_par = out_par;
         a.nrhs = cnt;
         a.partial = partial;
+        a.paired = pr;
         for (int k = 0; k < cnt; ++k) {
-            a.in[k] = reinterpret_cast<const VT*>(in) + (size_t)(r0 + k) * n;
-            a.out[k] = reinterpret_cast<VT*>(out) + (size_t)(r0 + k) * n;
-            if (self) a.self[k] = reinterpret_cast<const VT*>(self) + (size_t)(r0 + k) * n;
+            const size_t o = f32_offset(pr, r0 + k, 0, n);
+            a.in[k] = reinterpret_cast<const VT*>(in) + o;
+            a.out[k] = reinterpret_cast<VT*>(out) + o;
+            if (self) a.self[k] = reinterpret_cast<const VT*>(self) + o;
             a.c[k] = c;
         }
         set_variant(a, g);
@@ -329,10 +341,8 @@ rhmc_status rhmc_apply_mdagm(const rhmc_gauge* gc, double m, rhmc_prec prec, int
     if (!std::isfinite(m)) return invalid("m must be finite");
     RHMC_TRY(check_prec(g, prec));
     RHMC_TRY(use_device(g->device));
-    const size_t n = (size_t)3 * g->lat.Vh;
-    const size_t vb = prec == RHMC_PREC_FP64 ? sizeof(double2) : sizeof(float2);
     void* t = nullptr;
-    RHMC_TRY(tmp_odd(g, vb * n * nrhs, &t));
+    RHMC_TRY(tmp_odd(g, vec_set_bytes(g, prec, nrhs), &t));
     if (prec == RHMC_PREC_FP64) {
         RHMC_TRY(hop<double2>(g, 1, prec, nrhs, in, t, kModeD, nullptr, 0.0, stream));
         return hop<double2>(g, 0, prec, nrhs, t, out, kModeA, in, m * m, stream);

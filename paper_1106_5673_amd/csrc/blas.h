@@ -19,6 +19,8 @@ struct VecArgs {
     const double* part2;    // block sums of the A kernel (<p, A p>)
     int nblk2;
     int q;                  // step index inside the current block
+    int paired;             // FP32 only: x, y, z are systems of paired sets (f32_offset);
+                            // k_rupdate / k_pupdate then take one pair per block row
 };
 
 // Deferred update of the shifted solutions at a block boundary.
@@ -29,7 +31,10 @@ struct FlushArgs {
     size_t n;
     int nshift;
     int nsys;
-    VT* ring;               // stored base residuals: r(k0+l) of system j at ring + (l*nsys + j)*n
+    VT* ring;               // stored base residuals: slot l (a set of nsys vectors) at
+                            // ring + l*ring_slot; FP32 sets of two or more systems paired
+    size_t ring_slot;
+    int paired;
     double2* P;             // shifted directions [nsys][nshift][n], FP64 in every mode:
                             // rounding them is what limits a mixed solve's shifted
                             // true residuals, and they move only once per block
@@ -76,7 +81,8 @@ struct AddArgs {
 struct NarrowArgs {
     size_t n;
     const double2* x[kMaxSys];
-    float2* y[kMaxSys];
+    float2* y[kMaxSys];     // systems of an FP32 set
+    int paired;             // y paired (element stride 2)
 };
 
 template <typename VT> hipError_t launch_start(const VecArgs<VT>& a, int nsys, hipStream_t s);
@@ -109,6 +115,7 @@ struct Dot32Args {
     const float2* a[kMaxSys];
     const float2* b[kMaxSys];
     double* partial;
+    int paired;             // a and b are systems of paired sets (element stride 2)
 };
 hipError_t launch_dot32(const Dot32Args& a, int nsys, hipStream_t s);
 

@@ -35,6 +35,29 @@ template <> struct Pair<double2> {
     }
 };
 
+// Entries i and i + 1 of one system of an FP32 set whose systems are paired
+// (every other complex64, f32_offset); FP64 sets are never paired.
+template <typename VT>
+__device__ __forceinline__ void load_sys(Pair<VT>& u, const VT* p, size_t i, int paired) {
+    if (!paired) {
+        u.load(p, i);
+        return;
+    }
+    const VT a = p[i << 1], b = p[(i + 1) << 1];
+    u.re[0] = a.x; u.im[0] = a.y; u.re[1] = b.x; u.im[1] = b.y;
+}
+template <typename VT>
+__device__ __forceinline__ void store_sys(const Pair<VT>& v, VT* p, size_t i, int paired) {
+    if (!paired) {
+        v.store(p, i);
+        return;
+    }
+    VT a, b;
+    a.x = v.re[0]; a.y = v.im[0]; b.x = v.re[1]; b.y = v.im[1];
+    p[i << 1] = a;
+    p[(i + 1) << 1] = b;
+}
+
 // Block-reduce up to two doubles and store them as partial[r*gridDim.x + bx]
 // (r0, r1 >= 0).  The sums are finished by a one-block finalize kernel: the
 // kernel boundary makes every partial visible, with no per-block fence.
@@ -90,8 +113,8 @@ __global__ __launch_bounds__(kBlock) void k_start(VecArgs<VT> a) {
             b2 += b.re[k] * b.re[k] + b.im[k] * b.im[k];
             r2 += (double)r.re[k] * r.re[k] + (double)r.im[k] * r.im[k];
         }
-        r.store(a.x[j], i);
-        r.store(a.y[j], i);
+        store_sys(r, a.x[j], i, a.paired);
+        store_sys(r, a.y[j], i, a.paired);
     }
     reduce_store(b2, r2, j, st->nsys + j, a.partial);
 }
@@ -206,6 +229,119 @@ __global__ __launch_bounds__(kBlock) void k_pupdate(VecArgs<VT> a) {
     }
 }
 
+// ------------------------------------------------------------------ paired FP32 updates
+// The same two updates on paired FP32 sets (f32_offset): block row y takes
+// systems 2y and 2y + 1, a thread one float4 (one complex entry of both) per
+// element; the arithmetic of each entry is that of k_rupdate / k_pupdate.
+// The half of a finished system (or the absent partner of an odd count) is
+// stored back unchanged.
+__global__ __launch_bounds__(kBlock) void k_rupdate_pair(VecArgs<float2> a) {
+    SolverState* st = reinterpret_cast<SolverState*>(a.state);
+    if (st->all_done) return;
+    __shared__ double sums[kMaxSys];
+    const int j0 = 2 * (int)blockIdx.y, j1 = j0 + 1;
+    const bool has1 = j1 < st->nsys;
+    const bool live0 = !st->sys[j0].done, live1 = has1 && !st->sys[j1].done;
+    double r2a = 0.0, r2b = 0.0;
+    if (live0 || live1) {
+        block_sum_rows(a.part2 + (size_t)j0 * a.nblk2, has1 ? 2 : 1, a.nblk2, sums);
+        const double pap0 = sums[0], pap1 = has1 ? sums[1] : 1.0;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            if (live0) st->sys[j0].pap = pap0;
+            if (live1) st->sys[j1].pap = pap1;
+        }
+        const double al0 = live0 ? step_alpha_num(st->sys[j0], a.q) / pap0 : 0.0;
+        const double al1 = live1 ? step_alpha_num(st->sys[j1], a.q) / pap1 : 0.0;
+        const float4* __restrict__ x = reinterpret_cast<const float4*>(a.x[j0]);
+        const float4* __restrict__ y = reinterpret_cast<const float4*>(a.y[j0]);
+        float4* __restrict__ z = reinterpret_cast<float4*>(a.z[j0]);
+        const size_t stride = (size_t)gridDim.x * kBlock;
+        for (size_t i0 = (size_t)blockIdx.x * kBlock + threadIdx.x; i0 < a.n; i0 += stride * kUnroll) {
+            float4 r[kUnroll], ap[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const size_t i = i0 + u * stride;
+                if (i < a.n) {
+                    r[u] = x[i];
+                    ap[u] = y[i];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const size_t i = i0 + u * stride;
+                if (i < a.n) {
+                    if (live0) {
+                        r[u].x = (float)((double)r[u].x - al0 * (double)ap[u].x);
+                        r[u].y = (float)((double)r[u].y - al0 * (double)ap[u].y);
+                        r2a += (double)r[u].x * r[u].x + (double)r[u].y * r[u].y;
+                    }
+                    if (live1) {
+                        r[u].z = (float)((double)r[u].z - al1 * (double)ap[u].z);
+                        r[u].w = (float)((double)r[u].w - al1 * (double)ap[u].w);
+                        r2b += (double)r[u].z * r[u].z + (double)r[u].w * r[u].w;
+                    }
+                    z[i] = r[u];
+                }
+            }
+        }
+    }
+    reduce_store(r2a, r2b, j0, has1 ? j1 : -1, a.partial);
+}
+
+__global__ __launch_bounds__(kBlock) void k_pupdate_pair(VecArgs<float2> a) {
+    SolverState* st = reinterpret_cast<SolverState*>(a.state);
+    __shared__ double sums[kMaxSys];
+    __shared__ int flags[3];
+    const int j0 = 2 * (int)blockIdx.y, j1 = j0 + 1;
+    const bool has1 = j1 < st->nsys;
+    // done flags change during this kernel (the recurrence block): read once
+    if (threadIdx.x == 0) {
+        flags[0] = st->all_done;
+        flags[1] = st->sys[j0].done;
+        flags[2] = has1 ? st->sys[j1].done : 1;
+    }
+    __syncthreads();
+    if (flags[0]) return;
+    if (blockIdx.x == 0) {
+        if (blockIdx.y == 0) iteration_update(st, a.partial, a.nblk, a.q);
+        return;
+    }
+    const bool live0 = !flags[1], live1 = !flags[2];
+    if (!live0 && !live1) return;
+    block_sum_rows(a.partial + (size_t)j0 * a.nblk, has1 ? 2 : 1, a.nblk, sums);
+    const double beta0 = live0 ? sums[0] / st->sys[j0].rr[a.q & 1] : 0.0;
+    const double beta1 = live1 ? sums[1] / st->sys[j1].rr[a.q & 1] : 0.0;
+    const float4* __restrict__ x = reinterpret_cast<const float4*>(a.x[j0]);
+    float4* __restrict__ y = reinterpret_cast<float4*>(a.y[j0]);
+    const size_t stride = (size_t)(gridDim.x - 1) * kBlock;
+    for (size_t i0 = (size_t)(blockIdx.x - 1) * kBlock + threadIdx.x; i0 < a.n; i0 += stride * kUnroll) {
+        float4 r[kUnroll], p[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const size_t i = i0 + u * stride;
+            if (i < a.n) {
+                r[u] = x[i];
+                p[u] = y[i];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const size_t i = i0 + u * stride;
+            if (i < a.n) {
+                if (live0) {
+                    p[u].x = (float)((double)r[u].x + beta0 * (double)p[u].x);
+                    p[u].y = (float)((double)r[u].y + beta0 * (double)p[u].y);
+                }
+                if (live1) {
+                    p[u].z = (float)((double)r[u].z + beta1 * (double)p[u].z);
+                    p[u].w = (float)((double)r[u].w + beta1 * (double)p[u].w);
+                }
+                y[i] = p[u];
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ flush
 // Block coefficients of every shift that took part in the block (one block,
 // one thread per (system, shift)); run before k_flush.
@@ -244,7 +380,7 @@ __global__ __launch_bounds__(kBlock) void k_flush(FlushArgs<VT> a,
     for (int l = 0; l <= Q; ++l) {
         rre[l] = rim[l] = 0.0;
         if (l <= q) {
-            const VT v = a.ring[((size_t)l * a.nsys + j) * a.n + i];
+            const VT v = a.ring[(size_t)l * a.ring_slot + f32_offset(a.paired, j, i, a.n)];
             rre[l] = v.x;
             rim[l] = v.y;
         }
@@ -314,7 +450,7 @@ __global__ __launch_bounds__(kBlock) void k_flush(FlushArgs<VT> a,
             VT v;
             v.x = rre[l];
             v.y = rim[l];
-            a.ring[(size_t)j * a.n + i] = v;
+            a.ring[f32_offset(a.paired, j, i, a.n)] = v;
         }
 }
 
@@ -386,8 +522,8 @@ __global__ __launch_bounds__(kBlock) void k_dot32(Dot32Args a) {
     for (size_t i = ((size_t)blockIdx.x * kBlock + threadIdx.x) * 2; i < a.n;
          i += (size_t)gridDim.x * kBlock * 2) {
         Pair<float2> u, v;
-        u.load(a.a[j], i);
-        v.load(a.b[j], i);
+        load_sys(u, a.a[j], i, a.paired);
+        load_sys(v, a.b[j], i, a.paired);
         for (int k = 0; k < 2; ++k)
             d += (double)u.re[k] * (double)v.re[k] + (double)u.im[k] * (double)v.im[k];
     }
@@ -467,7 +603,7 @@ __global__ __launch_bounds__(kBlock) void k_narrow(NarrowArgs a) {
     const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= a.n) return;
     const double2 v = a.x[j][i];
-    a.y[j][i] = make_float2((float)v.x, (float)v.y);
+    a.y[j][i << a.paired] = make_float2((float)v.x, (float)v.y);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -485,14 +621,29 @@ hipError_t launch_start(const VecArgs<VT>& a, int nsys, hipStream_t s) {
     hipLaunchKernelGGL(k_start<VT>, red_grid(a.n, nsys), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
+// Paired FP32 sets run one block row per pair with the same number of blocks
+// per row (and so of partial sums per system) as the unpaired kernels.
 template <typename VT>
 hipError_t launch_rupdate(const VecArgs<VT>& a, int nsys, hipStream_t s) {
+    if constexpr (std::is_same<VT, float2>::value) {
+        if (a.paired) {
+            hipLaunchKernelGGL(k_rupdate_pair, red_grid(a.n, (nsys + 1) / 2), dim3(kBlock), 0, s, a);
+            return hipGetLastError();
+        }
+    }
     hipLaunchKernelGGL(k_rupdate<VT>, red_grid(a.n, nsys), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 template <typename VT>
 hipError_t launch_pupdate(const VecArgs<VT>& a, int nsys, hipStream_t s) {
     // one extra block column: x = 0 runs the scalar recurrences
+    if constexpr (std::is_same<VT, float2>::value) {
+        if (a.paired) {
+            const dim3 g(vec_blocks(a.n) + 1, (unsigned)((nsys + 1) / 2));
+            hipLaunchKernelGGL(k_pupdate_pair, g, dim3(kBlock), 0, s, a);
+            return hipGetLastError();
+        }
+    }
     const dim3 g(vec_blocks(a.n) + 1, (unsigned)nsys);
     hipLaunchKernelGGL(k_pupdate<VT>, g, dim3(kBlock), 0, s, a);
     return hipGetLastError();

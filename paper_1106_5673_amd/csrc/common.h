@@ -240,6 +240,22 @@ enum DslashMode {
     kModeResid = 2   // out = rhs - c*self + D in (FP64); partial ||out||^2 per rhs
 };
 
+// FP32 vector sets of two or more right-hand sides are stored in pairs: pair
+// q = (rhs 2q, rhs 2q + 1) is a [3][Vh] array of float4 (re, im of rhs 2q,
+// re, im of rhs 2q + 1), so element (r, c, eo) of a set is the complex64 at
+// ((r/2)*3*Vh + c*Vh + eo)*2 + r%2.  A set of an odd count holds a last pair
+// with an unused second half.  One right-hand side alone is a plain [3][Vh]
+// array (FP64 sets are always plain [nrhs][3][Vh]).
+inline bool paired_f32(int nrhs) { return nrhs >= 2; }
+// complex64 offset of element i (< 3*Vh) of rhs r in an FP32 set
+__host__ __device__ inline size_t f32_offset(bool paired, int r, size_t i, size_t n) {
+    return paired ? (((size_t)(r >> 1) * n + i) << 1) + (size_t)(r & 1) : (size_t)r * n + i;
+}
+// complex64 entries an FP32 set of nrhs vectors of n entries occupies
+inline size_t f32_set_size(int nrhs, size_t n) {
+    return (size_t)(paired_f32(nrhs) ? (nrhs + 1) / 2 * 2 : nrhs) * n;
+}
+
 // Arguments of one hopping launch over up to kMaxSys right-hand sides.
 template <typename VT>
 struct DslashArgs {
@@ -251,6 +267,8 @@ struct DslashArgs {
     const VT* self[kMaxSys];      // kModeA: p; kModeResid: x (output parity)
     const double2* rhs[kMaxSys];  // kModeResid: b
     float2* out32[kMaxSys];       // kModeResid: optional FP32 copy of the result
+    int out32_paired;             // 1: out32 is a paired FP32 set (element stride 2)
+    int paired;                   // FP32: in/out/self are paired sets (f32_offset)
     double c[kMaxSys];            // diagonal coefficient m^2 + sigma
     const int* skip;              // if non-null: skip[r*skip_stride] != 0 -> rhs r finished
     int skip_stride;

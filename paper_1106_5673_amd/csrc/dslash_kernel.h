@@ -6,9 +6,12 @@
 // each link is read once per application however many vectors are batched.
 // Links are structure-of-arrays over the link index k = (2*mu + parity)*Vh + eo,
 // so the 64 lanes of a wave read 64 consecutive links per load; neighbour
-// vectors are colour-major [3][Vh] arrays, read by consecutive sites (or,
-// for the +-x and +-y hops of a staged block, from LDS).
+// vectors are colour-major [3][Vh] arrays (FP32 sets of several right-hand
+// sides: one [3][Vh] array of float4 per pair of them), read by consecutive
+// sites (or, for the +-x and +-y hops of a staged block, from LDS).
 #pragma once
+
+#include <type_traits>
 
 #include "common.h"
 
@@ -265,6 +268,18 @@ __device__ __forceinline__ void hop_apply(const Link<RT>& U, const VT (&v)[NR][3
     }
 }
 
+// One loaded element into the per-rhs colour components: a vector entry of
+// one right-hand side, or (float4) one colour of the pair q of them.
+template <typename VT, int NR>
+__device__ __forceinline__ void unpack(const VT& w, VT (&v)[NR][3], int q, int c) {
+    v[q][c] = w;
+}
+template <int NR>
+__device__ __forceinline__ void unpack(const float4& w, float2 (&v)[NR][3], int q, int c) {
+    v[2 * q][c] = make_float2(w.x, w.y);
+    v[2 * q + 1][c] = make_float2(w.z, w.w);
+}
+
 // ------------------------------------------------------------------ hopping kernel
 // One lane owns one output site and every right-hand side of the launch, so
 // each link is read once per application however many vectors are batched.
@@ -279,11 +294,22 @@ __device__ __forceinline__ void hop_apply(const Link<RT>& U, const VT (&v)[NR][3
 // read their neighbours from LDS.  Every neighbour vector otherwise passes
 // through the per-CU vector-memory pipeline (address unit and L1) once per
 // hop, eight times per site; staging takes half of those accesses off it.
+//
+// FP32 with NR >= 2 (PR): the vectors come in pairs of right-hand sides
+// (f32_offset), so one 16-byte load brings one colour of two of them and the
+// kernel issues half as many vector loads (the pipeline above is limited by
+// load instructions more than by bytes).  Pair q is in[2q] / out[2q] / self[2q];
+// a pair with one live member is stored whole (the other half, a finished or
+// absent right-hand side, receives values nobody reads).
 template <typename VT, typename LT, int NR, int MODE, bool NT, int BATCH, bool STG>
 __global__ __launch_bounds__(STG ? 512 : kBlock) void k_dslash(const LT* __restrict__ links,
                                                                int nlinks, DslashArgs<VT> a) {
 #pragma clang fp contract(off)
     using RT = typename RealOf<VT>::T;
+    constexpr bool PR = std::is_same<VT, float2>::value && NR >= 2;
+    constexpr int NP = PR ? NR / 2 : NR;                             // vector planes sets
+    using LVT = typename std::conditional<PR, float4, VT>::type;    // one load
+    static_assert(!PR || MODE != kModeResid, "the residual mode is FP64");
     if (a.all_done && *a.all_done) return;
     const int nblk = gridDim.x;
     const int blk = xcd_remap(blockIdx.x, nblk);
@@ -299,11 +325,14 @@ __global__ __launch_bounds__(STG ? 512 : kBlock) void k_dslash(const LT* __restr
     // finished or absent right-hand sides read rhs 0 (valid, cached) and only
     // their stores are suppressed.
     bool act[NR];
-    Planes<VT, 3> vin[NR];   // colour planes of every input
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        act[r] = in_range && (r < a.nrhs) && !(a.skip && a.skip[r * a.skip_stride]);
-        vin[r] = make_planes<VT, 3>((r < a.nrhs) ? a.in[r] : a.in[0], (size_t)Vh);
+    for (int r = 0; r < NR; ++r) act[r] = in_range && (r < a.nrhs) && !(a.skip && a.skip[r * a.skip_stride]);
+    Planes<LVT, 3> vin[NP];   // colour planes of every input (pair)
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+        const int r = PR ? 2 * q : q;
+        vin[q] = make_planes<LVT, 3>(reinterpret_cast<const LVT*>((r < a.nrhs) ? a.in[r] : a.in[0]),
+                                     (size_t)Vh);
     }
     const LinkPlanes<LT> lp = link_planes(links, nlinks);
 
@@ -313,7 +342,7 @@ __global__ __launch_bounds__(STG ? 512 : kBlock) void k_dslash(const LT* __restr
 
     // staged rows: LDS [NR][3][R + 2][hx], row 0 = y0 - 1, row R + 1 = y0 + R
     extern __shared__ unsigned char lds_stage[];
-    VT* stage = reinterpret_cast<VT*>(lds_stage);
+    LVT* stage = reinterpret_cast<LVT*>(lds_stage);
     int srow = 0, shx = 0, sR2 = 0;   // this site's staged row, hx, R + 2
     if (STG) {
         const int hx = a.g.hx, Ly = a.g.Ly;
@@ -329,10 +358,12 @@ __global__ __launch_bounds__(STG ? 512 : kBlock) void k_dslash(const LT* __restr
             yy = yy < 0 ? yy + Ly : (yy >= Ly ? yy - Ly : yy);
             const int src = base + hx * yy + xs;
 #pragma unroll
-            for (int r = 0; r < NR; ++r) {
+            for (int q = 0; q < NP; ++q) {
+                const int r = PR ? 2 * q : q;
                 if (r >= a.nrhs) break;
+                const LVT* in = reinterpret_cast<const LVT*>(a.in[r]);
 #pragma unroll
-                for (int c = 0; c < 3; ++c) stage[(r * 3 + c) * rows + idx] = a.in[r][c * Vh + src];
+                for (int c = 0; c < 3; ++c) stage[(q * 3 + c) * rows + idx] = in[c * Vh + src];
             }
         }
         srow = y - y0 + 1;
@@ -367,15 +398,15 @@ __global__ __launch_bounds__(STG ? 512 : kBlock) void k_dslash(const LT* __restr
             const int li = row * shx + col;
             const int rows = sR2 * shx;
 #pragma unroll
-            for (int r = 0; r < NR; ++r)
+            for (int q = 0; q < NP; ++q)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) v[r][c] = stage[(r * 3 + c) * rows + li];
+                for (int c = 0; c < 3; ++c) unpack(stage[(q * 3 + c) * rows + li], v, q, c);
         } else {
-            const uint32_t o = byte_off(nb, (uint32_t)sizeof(VT));
+            const uint32_t o = byte_off(nb, (uint32_t)sizeof(LVT));
 #pragma unroll
-            for (int r = 0; r < NR; ++r)
+            for (int q = 0; q < NP; ++q)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) v[r][c] = ldg<false>(vin[r].at(c, o));
+                for (int c = 0; c < 3; ++c) unpack(ldg<false>(vin[q].at(c, o)), v, q, c);
         }
         const RT s = (RT)h.coef[slot];
         if (hop == 0)
@@ -406,9 +437,43 @@ __global__ __launch_bounds__(STG ? 512 : kBlock) void k_dslash(const LT* __restr
 
     double dot[NR];
 #pragma unroll
+    for (int r = 0; r < NR; ++r) dot[r] = 0.0;
+    if constexpr (PR) {
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+            const int r0 = 2 * q, r1 = 2 * q + 1;
+            if (!act[r0] && !act[r1]) continue;
+            float4* out = reinterpret_cast<float4*>(a.out[r0]);
+            if (MODE == kModeD) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    out[c * Vh + eo] = make_float4(ar[r0][c], ai[r0][c], ar[r1][c], ai[r1][c]);
+            } else {
+                const float4* self = reinterpret_cast<const float4*>(a.self[r0]);
+                const RT c0 = (RT)a.c[r0], c1 = (RT)a.c[r1];
+                double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const float4 pv = self[c * Vh + eo];
+                    float4 o;
+                    o.x = c0 * pv.x - ar[r0][c];
+                    o.y = c0 * pv.y - ai[r0][c];
+                    o.z = c1 * pv.z - ar[r1][c];
+                    o.w = c1 * pv.w - ai[r1][c];
+                    out[c * Vh + eo] = o;
+                    d0 = d0 + (double)pv.x * (double)o.x;
+                    d0 = d0 + (double)pv.y * (double)o.y;
+                    d1 = d1 + (double)pv.z * (double)o.z;
+                    d1 = d1 + (double)pv.w * (double)o.w;
+                }
+                dot[r0] = act[r0] ? d0 : 0.0;
+                dot[r1] = act[r1] ? d1 : 0.0;
+            }
+        }
+    }
+#pragma unroll
     for (int r = 0; r < NR; ++r) {
-        dot[r] = 0.0;
-        if (!act[r]) continue;
+        if (PR || !act[r]) continue;
         if (MODE == kModeD) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
@@ -447,7 +512,8 @@ __global__ __launch_bounds__(STG ? 512 : kBlock) void k_dslash(const LT* __restr
                     w.y = o.y;
                     a.out[r][c * Vh + eo] = w;
                 }
-                if (a.out32[r]) a.out32[r][c * Vh + eo] = make_float2((float)o.x, (float)o.y);
+                if (a.out32[r])
+                    a.out32[r][(size_t)(c * Vh + eo) << a.out32_paired] = make_float2((float)o.x, (float)o.y);
                 d = d + o.x * o.x;
                 d = d + o.y * o.y;
             }
@@ -506,7 +572,13 @@ inline hipError_t dispatch(const LT* links, int nlinks, const DslashArgs<VT>& a0
     int zt = kZTile[hop_order(v)];
     if (zt > 0 && a.g.Lz % zt != 0) zt = 1;
     a.zt = zt ? make_fastdiv((uint32_t)zt) : FastDiv{0u, 0u, 0u, 0u};
-    const int nr = nr_of_class(nr_class(a.nrhs));
+    int nr = nr_of_class(nr_class(a.nrhs));
+    if (std::is_same<VT, float2>::value) {
+        // FP32 sets of two or more right-hand sides are paired; a launch over
+        // the last, unpaired member of such a set runs the pair kernel
+        if (a.paired && nr == 1) nr = 2;
+        if (!a.paired && nr > 1) return hipErrorInvalidValue;
+    }
     const int R = stage_rows(a.g, hop_stage(v), nr, (int)sizeof(VT));
     const int batch = hop_batch(v);
     if (R) {

@@ -228,6 +228,28 @@ static VT* vec(void* base, size_t n, size_t idx) {
     return reinterpret_cast<VT*>(base) + idx * n;
 }
 
+// Iteration vectors come in sets of ns systems: FP32 sets of two or more
+// systems are paired (f32_offset), FP64 sets are plain [ns][n].  Both fit the
+// buffers, which are sized for FP64 sets.
+template <typename VT>
+static bool set_paired(int ns) {
+    return std::is_same<VT, float2>::value && paired_f32(ns);
+}
+template <typename VT>
+static size_t set_len(int ns, size_t n) {
+    return set_paired<VT>(ns) ? f32_set_size(ns, n) : (size_t)ns * n;
+}
+// system j of the set at `set`
+template <typename VT>
+static VT* sys_vec(void* set, size_t n, int ns, int j) {
+    return reinterpret_cast<VT*>(set) + f32_offset(set_paired<VT>(ns), j, 0, n);
+}
+// system j of slot l of the residual ring (one set per slot)
+template <typename VT>
+static VT* ring_vec(void* ring, size_t n, int ns, int l, int j) {
+    return sys_vec<VT>(reinterpret_cast<VT*>(ring) + (size_t)l * set_len<VT>(ns, n), n, ns, j);
+}
+
 // Enqueue one block of K iterations (+ flush, + optional reliable update).
 template <typename VT>
 static rhmc_status enqueue_block(const rhmc_gauge* g, Workspace* w, const Problem& pb,
@@ -251,12 +273,14 @@ static rhmc_status enqueue_block(const rhmc_gauge* g, Workspace* w, const Proble
     const int dgrid = gauge_hop_grid(g, f32 ? RHMC_PREC_FP32 : RHMC_PREC_FP64, ns);
     const int rgrid = gauge_hop_grid(g, RHMC_PREC_FP64, ns);
     const int vgrid = vec_blocks(n);
+    const bool pr = set_paired<VT>(ns);
+    d.paired = a.paired = pr;
     for (int j = 0; j < ns; ++j) {
-        d.in[j] = vec<VT>(w->p, n, j);
-        d.out[j] = vec<VT>(w->t, n, j);
-        a.in[j] = vec<VT>(w->t, n, j);
-        a.self[j] = vec<VT>(w->p, n, j);
-        a.out[j] = vec<VT>(w->Ap, n, j);
+        d.in[j] = sys_vec<VT>(w->p, n, ns, j);
+        d.out[j] = sys_vec<VT>(w->t, n, ns, j);
+        a.in[j] = sys_vec<VT>(w->t, n, ns, j);
+        a.self[j] = sys_vec<VT>(w->p, n, ns, j);
+        a.out[j] = sys_vec<VT>(w->Ap, n, ns, j);
         a.c[j] = pb.m2 + pb.sigma0[j];
     }
     set_variant(d, g);
@@ -279,17 +303,18 @@ static rhmc_status enqueue_block(const rhmc_gauge* g, Workspace* w, const Proble
         r.part2 = w->partial;
         r.nblk2 = dgrid;
         r.q = q;
+        r.paired = pr;
         for (int j = 0; j < ns; ++j) {
-            r.x[j] = vec<VT>(w->ring, n, (size_t)q * ns + j);
-            r.y[j] = vec<VT>(w->Ap, n, j);
-            r.z[j] = vec<VT>(w->ring, n, (size_t)(q + 1) * ns + j);
+            r.x[j] = ring_vec<VT>(w->ring, n, ns, q, j);
+            r.y[j] = sys_vec<VT>(w->Ap, n, ns, j);
+            r.z[j] = ring_vec<VT>(w->ring, n, ns, q + 1, j);
         }
         RHMC_HIP_TRY(launch_rupdate<VT>(r, ns, s));
         // p = r' + beta p, and the FP64 recurrences of this step
         VecArgs<VT> p = r;
         for (int j = 0; j < ns; ++j) {
-            p.x[j] = vec<VT>(w->ring, n, (size_t)(q + 1) * ns + j);
-            p.y[j] = vec<VT>(w->p, n, j);
+            p.x[j] = ring_vec<VT>(w->ring, n, ns, q + 1, j);
+            p.y[j] = sys_vec<VT>(w->p, n, ns, j);
             p.z[j] = nullptr;
         }
         RHMC_HIP_TRY(launch_pupdate<VT>(p, ns, s));
@@ -304,6 +329,8 @@ static rhmc_status enqueue_block(const rhmc_gauge* g, Workspace* w, const Proble
     f.w_stride = pb.w_stride;
     f.y = pb.yacc;
     f.ring = reinterpret_cast<VT*>(w->ring);
+    f.ring_slot = set_len<VT>(ns, n);
+    f.paired = pr;
     f.P = reinterpret_cast<double2*>(w->P);
     f.X = pb.X;
     f.x_sys = pb.x_sys;
@@ -331,10 +358,11 @@ static rhmc_status enqueue_block(const rhmc_gauge* g, Workspace* w, const Proble
             r64.rhs[j] = pb.b[j];
             r64.c[j] = pb.m2 + pb.sigma0[j];
             r64.out[j] = nullptr;
-            if (f32) r64.out32[j] = reinterpret_cast<float2*>(vec<VT>(w->ring, n, j));
+            if (f32) r64.out32[j] = reinterpret_cast<float2*>(ring_vec<VT>(w->ring, n, ns, 0, j));
         }
+        r64.out32_paired = f32 && pr;
         if (!f32)
-            for (int j = 0; j < ns; ++j) r64.out[j] = reinterpret_cast<double2*>(vec<VT>(w->ring, n, j));
+            for (int j = 0; j < ns; ++j) r64.out[j] = reinterpret_cast<double2*>(ring_vec<VT>(w->ring, n, ns, 0, j));
         set_variant(d64, g);
         set_variant(r64, g);
         RHMC_HIP_TRY(launch_fp64_op(g, d64, kModeD, s));
@@ -345,9 +373,10 @@ static rhmc_status enqueue_block(const rhmc_gauge* g, Workspace* w, const Proble
             Dot32Args dp{};
             dp.n = n;
             dp.partial = w->partial + kMaxSys * w->part_stride;
+            dp.paired = pr;
             for (int j = 0; j < ns; ++j) {
-                dp.a[j] = reinterpret_cast<const float2*>(vec<VT>(w->ring, n, j));
-                dp.b[j] = reinterpret_cast<const float2*>(vec<VT>(w->p, n, j));
+                dp.a[j] = reinterpret_cast<const float2*>(ring_vec<VT>(w->ring, n, ns, 0, j));
+                dp.b[j] = reinterpret_cast<const float2*>(sys_vec<VT>(w->p, n, ns, j));
             }
             RHMC_HIP_TRY(launch_dot32(dp, ns, s));
             RHMC_HIP_TRY(launch_finalize(kFinReliableDot, w->st, dp.partial, vgrid, ns, nullptr, s));
@@ -437,10 +466,11 @@ static rhmc_status krylov_init(rhmc_gauge* g, const Problem& pb, hipStream_t s) 
     st.state = w->st;
     st.n = n;
     st.partial = w->partial;
+    st.paired = set_paired<VT>(pb.nsys);
     for (int j = 0; j < pb.nsys; ++j) {
         st.b64[j] = pb.b[j];
-        st.x[j] = vec<VT>(w->ring, n, j);
-        st.y[j] = vec<VT>(w->p, n, j);
+        st.x[j] = ring_vec<VT>(w->ring, n, pb.nsys, 0, j);
+        st.y[j] = sys_vec<VT>(w->p, n, pb.nsys, j);
     }
     RHMC_HIP_TRY(launch_start<VT>(st, pb.nsys, s));
     RHMC_HIP_TRY(launch_finalize(kFinInit, w->st, w->partial, vec_blocks(n), pb.nsys, nullptr, s));
@@ -562,26 +592,28 @@ static rhmc_status run_mixed(rhmc_gauge* g, const Problem& pb, hipStream_t s, in
         // r (ring slot j) and p to FP32, through the Ap and t buffers
         const size_t n = w->n;
         const int ns = pb.nsys;
+        const bool pr = set_paired<float2>(ns);
         NarrowArgs nr{}, np{};
         nr.n = np.n = n;
+        nr.paired = np.paired = pr;
         for (int j = 0; j < ns; ++j) {
             nr.x[j] = vec<double2>(w->ring, n, j);
-            nr.y[j] = vec<float2>(w->Ap, n, j);
+            nr.y[j] = sys_vec<float2>(w->Ap, n, ns, j);
             np.x[j] = vec<double2>(w->p, n, j);
-            np.y[j] = vec<float2>(w->t, n, j);
+            np.y[j] = sys_vec<float2>(w->t, n, ns, j);
         }
         RHMC_HIP_TRY(launch_narrow(nr, ns, s));
         RHMC_HIP_TRY(launch_narrow(np, ns, s));
-        RHMC_HIP_TRY(hipMemcpyAsync(w->ring, w->Ap, ns * n * sizeof(float2),
-                                    hipMemcpyDeviceToDevice, s));
-        RHMC_HIP_TRY(hipMemcpyAsync(w->p, w->t, ns * n * sizeof(float2),
-                                    hipMemcpyDeviceToDevice, s));
+        const size_t set_bytes = set_len<float2>(ns, n) * sizeof(float2);
+        RHMC_HIP_TRY(hipMemcpyAsync(w->ring, w->Ap, set_bytes, hipMemcpyDeviceToDevice, s));
+        RHMC_HIP_TRY(hipMemcpyAsync(w->p, w->t, set_bytes, hipMemcpyDeviceToDevice, s));
         Dot32Args dp{};
         dp.n = n;
         dp.partial = w->partial + kMaxSys * w->part_stride;
+        dp.paired = pr;
         for (int j = 0; j < ns; ++j) {
-            dp.a[j] = vec<float2>(w->ring, n, j);
-            dp.b[j] = vec<float2>(w->p, n, j);
+            dp.a[j] = ring_vec<float2>(w->ring, n, ns, 0, j);
+            dp.b[j] = sys_vec<float2>(w->p, n, ns, j);
         }
         RHMC_HIP_TRY(launch_dot32(dp, ns, s));
         RHMC_HIP_TRY(launch_finalize(kFinReliableDot, w->st, dp.partial, vec_blocks(n), ns,

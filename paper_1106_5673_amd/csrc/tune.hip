@@ -14,7 +14,7 @@ void default_hop_variants(int (&v)[2][4]) {
     // staged in LDS except for eight right-hand sides, whose staged rows do
     // not fit three blocks per CU; loads in batches of one to four hops
     const int fp64[4] = {52, 28, 28, 11};    // FP64-12 links (the default FP64 storage)
-    const int fp32[4] = {44, 36, 36, 12};
+    const int fp32[4] = {44, 36, 36, 36};
     for (int k = 0; k < 4; ++k) {
         v[RHMC_PREC_FP64][k] = fp64[k];
         v[RHMC_PREC_FP32][k] = fp32[k];
@@ -55,9 +55,10 @@ rhmc_status tune_hop(rhmc_gauge* g, rhmc_prec prec, int nrhs, const void* in, vo
                 a.out_par = 1;
                 a.nrhs = nrhs;
                 a.variant = v;
+                a.paired = paired_f32(nrhs);
                 for (int r = 0; r < nrhs; ++r) {
-                    a.in[r] = reinterpret_cast<const float2*>(in) + r * n;
-                    a.out[r] = reinterpret_cast<float2*>(out) + r * n;
+                    a.in[r] = reinterpret_cast<const float2*>(in) + f32_offset(a.paired, r, 0, n);
+                    a.out[r] = reinterpret_cast<float2*>(out) + f32_offset(a.paired, r, 0, n);
                 }
                 err = launch_fp32_op(g, a, kModeD, s);
             }

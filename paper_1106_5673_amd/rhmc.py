@@ -269,30 +269,38 @@ def _vec_dtype(prec):
     return torch.complex128 if prec == RHMC_PREC_FP64 else torch.complex64
 
 
+def vec_shape(prec: int, nrhs: int, Vh: int):
+    """Tensor shape of a vector set at the ABI: complex128 [nrhs][3][Vh]; complex64
+    [3][Vh] for one vector and [ceil(nrhs/2)][3][Vh][2] (pairs) for two or more."""
+    if prec == RHMC_PREC_FP32 and nrhs >= 2:
+        return ((nrhs + 1) // 2, 3, Vh, 2)
+    return (nrhs, 3, Vh)
+
+
 def rhmc_dslash_eo(g: Gauge, out_parity: int, prec: int, nrhs: int, inp, out, stream=None):
-    Vh = g.lattice.Vh
+    shape = vec_shape(prec, nrhs, g.lattice.Vh)
     dt = _vec_dtype(prec)
     _check(load().rhmc_dslash_eo(g.handle, int(out_parity), int(prec), int(nrhs),
-                                 _ptr(inp, dt, (nrhs, 3, Vh), "in"), _ptr(out, dt, (nrhs, 3, Vh), "out"),
+                                 _ptr(inp, dt, shape, "in"), _ptr(out, dt, shape, "out"),
                                  _stream(stream)))
 
 
 def rhmc_apply_mdagm(g: Gauge, m: float, prec: int, nrhs: int, inp, out, stream=None):
-    Vh = g.lattice.Vh
+    shape = vec_shape(prec, nrhs, g.lattice.Vh)
     dt = _vec_dtype(prec)
     _check(load().rhmc_apply_mdagm(g.handle, float(m), int(prec), int(nrhs),
-                                   _ptr(inp, dt, (nrhs, 3, Vh), "in"), _ptr(out, dt, (nrhs, 3, Vh), "out"),
+                                   _ptr(inp, dt, shape, "in"), _ptr(out, dt, shape, "out"),
                                    _stream(stream)))
 
 
 def rhmc_apply_mdagm_static(g: Gauge, m: float, prec: int, nrhs: int, inp, out, stream=None):
     """rhmc_apply_mdagm with its temporaries in the library's static device
     scratch (no allocation)."""
-    Vh = g.lattice.Vh
+    shape = vec_shape(prec, nrhs, g.lattice.Vh)
     dt = _vec_dtype(prec)
     _check(load().rhmc_apply_mdagm_static(g.handle, float(m), int(prec), int(nrhs),
-                                          _ptr(inp, dt, (nrhs, 3, Vh), "in"),
-                                          _ptr(out, dt, (nrhs, 3, Vh), "out"), _stream(stream)))
+                                          _ptr(inp, dt, shape, "in"),
+                                          _ptr(out, dt, shape, "out"), _stream(stream)))
 
 
 class _Stats:
@@ -432,10 +440,10 @@ def rhmc_pf_force(g: Gauge, m: float, alpha0: float, alpha, beta, phi, force, pa
 
 def rhmc_tune_dslash(g: Gauge, prec: int, nrhs: int, inp, out, stream=None):
     """Time every launch variant of the hopping kernel and keep the fastest."""
-    Vh = g.lattice.Vh
+    shape = vec_shape(prec, nrhs, g.lattice.Vh)
     dt = _vec_dtype(prec)
-    _check(load().rhmc_tune_dslash(g.handle, int(prec), int(nrhs), _ptr(inp, dt, (nrhs, 3, Vh), "in"),
-                                   _ptr(out, dt, (nrhs, 3, Vh), "out"), _stream(stream)))
+    _check(load().rhmc_tune_dslash(g.handle, int(prec), int(nrhs), _ptr(inp, dt, shape, "in"),
+                                   _ptr(out, dt, shape, "out"), _stream(stream)))
 
 
 def rhmc_dslash_variant(g: Gauge, prec: int, nrhs: int) -> int:

@@ -7,6 +7,8 @@ that touch no device are exercised.
 import os
 import re
 
+import numpy as np
+
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -90,3 +92,26 @@ def test_variant_encoding_limits(rh):
     hdr = open(os.path.join(ROOT, "include", "rhmc.h")).read()
     assert "0 <= variant < 72" in hdr
     assert "order + 8 * batch + 24 * stage" in hdr
+
+
+def test_fp32_pair_storage_layout():
+    """The paired FP32 storage the header defines: element (r, c, eo) of a set
+    of nrhs >= 2 vectors is the complex64 at ((r/2)*3*Vh + c*Vh + eo)*2 + r%2;
+    the test helper's pack / unpack follow that formula and round-trip."""
+    import f32layout
+
+    with open(os.path.join(ROOT, "include", "rhmc.h")) as fh:
+        header = fh.read()
+    assert "((r/2)*3*Vh + c*Vh + eo)*2 +" in header
+    Vh = 12
+    rng = np.random.default_rng(3)
+    for nrhs in (1, 2, 3, 8, 11):
+        v = (rng.standard_normal((nrhs, 3, Vh)) + 1j * rng.standard_normal((nrhs, 3, Vh))).astype(np.complex64)
+        flat = f32layout.pack(v).reshape(-1)
+        assert flat.size == f32layout.size(nrhs, Vh)
+        for r in range(nrhs):
+            for c in range(3):
+                for eo in range(Vh):
+                    off = c * Vh + eo if nrhs == 1 else ((r // 2) * 3 * Vh + c * Vh + eo) * 2 + r % 2
+                    assert flat[off] == v[r, c, eo]
+        assert np.array_equal(f32layout.unpack(flat, nrhs, Vh), v)

@@ -10,11 +10,14 @@ FP64 CPU oracle on the same seeded inputs:
   * FP32 path with 12-real links: |gpu - oracle| <= 32 * 2^-24 * scale per
     element, scale = 1/2 sum over the 8 hops of |U| |psi| (rounding of links,
     vectors, the third-row rebuild and 24 accumulations).
+FP32 sets of two or more right-hand sides are passed in the ABI's paired
+storage (f32layout).
 """
 
 import numpy as np
 import pytest
 
+import f32layout
 import synth
 from oracle import dirac, lattice
 
@@ -80,12 +83,15 @@ def test_point_sources_unit_links_bit_exact(rh, prec):
         v = np.zeros((len(srcs), 3, Vh), dtype=cdt)
         for k, (c, _, eo) in enumerate(srcs):
             v[k, c, eo] = 1.0
-        vin = _to(v)
+        vin = _to(v if prec == "fp64" else f32layout.pack(v))
         vout = torch.empty_like(vin)
         rh.rhmc_dslash_eo(g, out_par, p, len(srcs), vin, vout)
         torch.cuda.synchronize()
         ref = dirac.dslash(U, v.astype(np.complex128), out_par)
-        assert np.array_equal(vout.cpu().numpy().astype(np.complex128), ref)
+        got = vout.cpu().numpy()
+        if prec == "fp32":
+            got = f32layout.unpack(got, len(srcs), Vh)
+        assert np.array_equal(got.astype(np.complex128), ref)
     g.close()
 
 
@@ -125,11 +131,11 @@ def test_dslash_random_fields(rh, L, nrhs):
         # FP32 with 12-real links
         v32 = v.astype(np.complex64)
         ref32 = dirac.dslash(U, v32.astype(np.complex128), out_par, t_bc)
-        vin = _to(v32)
+        vin = _to(f32layout.pack(v32))
         vout = torch.empty_like(vin)
         rh.rhmc_dslash_eo(g, out_par, rh.RHMC_PREC_FP32, nrhs, vin, vout)
         torch.cuda.synchronize()
-        got32 = vout.cpu().numpy().astype(np.complex128)
+        got32 = f32layout.unpack(vout.cpu().numpy(), nrhs, lat.Vh).astype(np.complex128)
         scale = _abs_scale(U, v32.astype(np.complex128), out_par)
         err = np.abs(got32 - ref32)
         assert np.all(err.real <= 32 * 2.0 ** -24 * scale + 1e-30)
@@ -147,19 +153,21 @@ def test_multi_rhs_matches_single(rh, nrhs):
     g = rh.rhmc_gauge_create(lat, U)
     rng = np.random.default_rng(12)
     v = _rand_vec(rng, nrhs, lat.Vh)
-    for prec, cdt, tol in ((rh.RHMC_PREC_FP64, np.complex128, 0.0),
-                           (rh.RHMC_PREC_FP32, np.complex64, 0.0)):
-        vin = _to(v.astype(cdt))
+    for prec, cdt in ((rh.RHMC_PREC_FP64, np.complex128), (rh.RHMC_PREC_FP32, np.complex64)):
+        vc = v.astype(cdt)
+        vin = _to(vc if cdt == np.complex128 else f32layout.pack(vc))
         vout = torch.empty_like(vin)
         rh.rhmc_dslash_eo(g, 0, prec, nrhs, vin, vout)
-        one = torch.empty_like(vin[0:1])
         torch.cuda.synchronize()
+        got = vout.cpu().numpy()
+        if cdt == np.complex64:
+            got = f32layout.unpack(got, nrhs, lat.Vh)
+        one = torch.empty((1, 3, lat.Vh), dtype=vin.dtype, device=_dev())
         for r in range(nrhs):
-            rh.rhmc_dslash_eo(g, 0, prec, 1, vin[r:r + 1].contiguous(), one)
+            rh.rhmc_dslash_eo(g, 0, prec, 1, _to(vc[r:r + 1]), one)
             torch.cuda.synchronize()
-            d = (vout[r] - one[0]).abs().max().item()
-            s = one.abs().max().item()
-            assert d <= max(tol, 1e-15 if cdt == np.complex128 else 1e-6) * s
+            # the same arithmetic per site and rhs: identical bits
+            assert np.array_equal(got[r], one[0].cpu().numpy()), (prec, r)
     g.close()
 
 
@@ -180,11 +188,11 @@ def test_mdagm_matches_oracle(rh, L):
     torch.cuda.synchronize()
     got = vout.cpu().numpy()
     assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
-    vin32 = _to(v.astype(np.complex64))
+    vin32 = _to(f32layout.pack(v.astype(np.complex64)))
     vout32 = torch.empty_like(vin32)
     rh.rhmc_apply_mdagm(g, m, rh.RHMC_PREC_FP32, 2, vin32, vout32)
     torch.cuda.synchronize()
-    got32 = vout32.cpu().numpy().astype(np.complex128)
+    got32 = f32layout.unpack(vout32.cpu().numpy(), 2, lat.Vh).astype(np.complex128)
     assert np.linalg.norm(got32 - ref) <= 1e-5 * np.linalg.norm(ref)
     g.close()
 
@@ -222,9 +230,10 @@ def test_every_launch_variant_gives_identical_bits(rh, L):
     g = rh.rhmc_gauge_create(lat, U)
     rng = np.random.default_rng(14)
     for prec, cdt in ((rh.RHMC_PREC_FP64, np.complex128), (rh.RHMC_PREC_FP32, np.complex64)):
+        f32 = cdt == np.complex64
         for nrhs in (1, 3, 8):
             v = _rand_vec(rng, nrhs, lat.Vh).astype(cdt)
-            vin = _to(v)
+            vin = _to(f32layout.pack(v) if f32 else v)
             ref = {}
             for var in range(72):
                 rh.rhmc_set_dslash_variant(g, prec, nrhs, var)
@@ -233,6 +242,8 @@ def test_every_launch_variant_gives_identical_bits(rh, L):
                     vout = torch.empty_like(vin)
                     rh.rhmc_dslash_eo(g, out_par, prec, nrhs, vin, vout)
                     got = vout.cpu().numpy()
+                    if f32:
+                        got = f32layout.unpack(got, nrhs, lat.Vh)
                     if var == 0:
                         ref[out_par] = got
                         v64 = v.astype(np.complex128)
@@ -247,6 +258,8 @@ def test_every_launch_variant_gives_identical_bits(rh, L):
                 vA = torch.empty_like(vin)
                 rh.rhmc_apply_mdagm(g, m, prec, nrhs, vin, vA)
                 gotA = vA.cpu().numpy()
+                if f32:
+                    gotA = f32layout.unpack(gotA, nrhs, lat.Vh)
                 if var == 0:
                     ref["A"] = gotA
                 else:
@@ -280,11 +293,12 @@ def test_hilo_links_fp64_operator(rh):
         scale = np.abs(want).max()
         assert np.abs(got - want).max() <= 1e-13 * scale
         assert np.abs(got - o18.cpu().numpy()).max() <= 2.0 ** -45 * scale
-        v32 = _to(v.astype(np.complex64))
+        v32 = _to(f32layout.pack(v.astype(np.complex64)))
         a32, b32 = torch.empty_like(v32), torch.empty_like(v32)
         rh.rhmc_dslash_eo(g18, out_par, rh.RHMC_PREC_FP32, 3, v32, a32)
         rh.rhmc_dslash_eo(ghl, out_par, rh.RHMC_PREC_FP32, 3, v32, b32)
-        assert torch.equal(a32, b32)
+        assert np.array_equal(f32layout.unpack(a32.cpu().numpy(), 3, lat.Vh),
+                              f32layout.unpack(b32.cpu().numpy(), 3, lat.Vh))
     g18.close()
     ghl.close()
 
@@ -361,7 +375,7 @@ def test_max_rhs_and_direct_tuning(rh):
     for r in (0, 7, 8, 63):
         rh.rhmc_dslash_eo(g, 0, rh.RHMC_PREC_FP64, 1, v[r:r + 1].contiguous(), one)
         assert (one[0] - out[r]).abs().max().item() <= 1e-15 * one.abs().max().item()
-    v32 = v[:4].to(torch.complex64).contiguous()
+    v32 = _to(f32layout.pack(v[:4].cpu().numpy().astype(np.complex64)))
     a, b = torch.empty_like(v32), torch.empty_like(v32)
     rh.rhmc_dslash_eo(g, 1, rh.RHMC_PREC_FP32, 4, v32, a)
     rh.rhmc_tune_dslash(g, rh.RHMC_PREC_FP32, 4, v32, b)
@@ -402,11 +416,11 @@ def test_fp32_18_links(rh, su3, nrhs):
         v32 = _rand_vec(rng, nrhs, lat.Vh).astype(np.complex64)
         v = v32.astype(np.complex128)
         ref = dirac.dslash(U, v, out_par, -1)
-        vin = _to(v32)
+        vin = _to(f32layout.pack(v32))
         vout = torch.empty_like(vin)
         rh.rhmc_dslash_eo(g, out_par, rh.RHMC_PREC_FP32, nrhs, vin, vout)
         torch.cuda.synchronize()
-        got = vout.cpu().numpy().astype(np.complex128)
+        got = f32layout.unpack(vout.cpu().numpy(), nrhs, lat.Vh).astype(np.complex128)
         scale = _abs_scale(U, v, out_par)
         err = np.abs(got - ref)
         assert np.all(err.real <= 32 * 2.0 ** -24 * scale + 1e-30)

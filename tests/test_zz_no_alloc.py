@@ -24,11 +24,13 @@ def rh():
     return rhmc
 
 
-def _vec(rng, nrhs, Vh, dtype):
+def _vec(rh, rng, prec, nrhs, Vh, dtype):
+    """Random vector set in the ABI storage (even nrhs: the paired FP32 form
+    holds as many entries as [nrhs][3][Vh])."""
     import torch
 
     v = rng.standard_normal((nrhs, 3, Vh)) + 1j * rng.standard_normal((nrhs, 3, Vh))
-    return torch.from_numpy(v.astype(dtype)).to("cuda:0")
+    return torch.from_numpy(v.astype(dtype).reshape(rh.vec_shape(prec, nrhs, Vh))).to("cuda:0")
 
 
 @pytest.mark.parametrize("prec_name", ["fp64", "fp32"])
@@ -45,7 +47,7 @@ def test_static_mdagm_matches_mdagm(rh, prec_name):
         U = synth.gauge_field(L, 0.6, seed)
         lat = rh.rhmc_lattice_create(L, -1)
         g = rh.rhmc_gauge_create(lat, U)
-        v = _vec(rng, nrhs, lat.Vh, dtype)
+        v = _vec(rh, rng, prec, nrhs, lat.Vh, dtype)
         ref = torch.empty_like(v)
         rh.rhmc_apply_mdagm(g, m, prec, nrhs, v, ref)
         for _ in range(2):
