@@ -471,6 +471,8 @@ def main():
     log(f"hopping fp32-12 x{nrhs}: {avg * 1e6:.1f} us ({achieved:.0f} GB/s); "
         f"fp64-12 x{nrhs}: {t64_4 * 1e6:.1f} us ({byts64_4 / t64_4 / 1e9:.0f} GB/s)")
     if args.only_dslash:
+        time_dslash("fp32", 8, args.dslash_reps)
+        log("hopping fp32-12 x8 timed")
         # a plain copy of known size for calibrating the HBM byte counters
         src = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)

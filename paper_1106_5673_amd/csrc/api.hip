@@ -524,7 +524,7 @@ rhmc_status rhmc_set_dslash_variant(rhmc_gauge* g, rhmc_prec prec, int32_t nrhs,
                                     int32_t variant) {
     if (!g) return invalid("null argument");
     if (nrhs < 1 || nrhs > 64) return invalid("nrhs must be in 1..64");
-    if (variant < 0 || variant >= kHopVariants) return invalid("variant must be in 0..71");
+    if (variant < 0 || variant >= kHopVariants) return invalid("variant must be in 0.." + std::to_string(kHopVariants - 1));
     RHMC_TRY(check_prec(g, prec));
     const int cls = nr_class(nrhs < kMaxSys ? nrhs : kMaxSys);
     g->hop_variant[prec][cls] = variant;

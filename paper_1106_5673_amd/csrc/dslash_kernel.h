@@ -68,6 +68,19 @@ __device__ __forceinline__ float4 ldg(gp<float4> p) {
     return make_float4(v.x, v.y, v.z, v.w);
 }
 
+// Stores of a kernel's output that nothing reads again while the kernel
+// runs: non-temporal, so they do not push inputs that neighbouring sites still
+// need out of the L2.
+__device__ __forceinline__ void stnt(float2* p, float2 v) {
+    __builtin_nontemporal_store(f2v{v.x, v.y}, reinterpret_cast<f2v*>(p));
+}
+__device__ __forceinline__ void stnt(float4* p, float4 v) {
+    __builtin_nontemporal_store(f4v{v.x, v.y, v.z, v.w}, reinterpret_cast<f4v*>(p));
+}
+__device__ __forceinline__ void stnt(double2* p, double2 v) {
+    __builtin_nontemporal_store(d2v{v.x, v.y}, reinterpret_cast<d2v*>(p));
+}
+
 // The planes of a structure-of-arrays field (link entries, colour planes of
 // a vector): every plane's base address is uniform and held in scalar
 // registers (readfirstlane keeps the compiler from folding it into per-lane
@@ -447,7 +460,7 @@ __global__ __launch_bounds__(STG ? 512 : kBlock) void k_dslash(const LT* __restr
             if (MODE == kModeD) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
-                    out[c * Vh + eo] = make_float4(ar[r0][c], ai[r0][c], ar[r1][c], ai[r1][c]);
+                    stnt(out + c * Vh + eo, make_float4(ar[r0][c], ai[r0][c], ar[r1][c], ai[r1][c]));
             } else {
                 const float4* self = reinterpret_cast<const float4*>(a.self[r0]);
                 const RT c0 = (RT)a.c[r0], c1 = (RT)a.c[r1];
@@ -460,7 +473,7 @@ __global__ __launch_bounds__(STG ? 512 : kBlock) void k_dslash(const LT* __restr
                     o.y = c0 * pv.y - ai[r0][c];
                     o.z = c1 * pv.z - ar[r1][c];
                     o.w = c1 * pv.w - ai[r1][c];
-                    out[c * Vh + eo] = o;
+                    stnt(out + c * Vh + eo, o);
                     d0 = d0 + (double)pv.x * (double)o.x;
                     d0 = d0 + (double)pv.y * (double)o.y;
                     d1 = d1 + (double)pv.z * (double)o.z;
@@ -480,7 +493,7 @@ __global__ __launch_bounds__(STG ? 512 : kBlock) void k_dslash(const LT* __restr
                 VT o;
                 o.x = ar[r][c];
                 o.y = ai[r][c];
-                a.out[r][c * Vh + eo] = o;
+                stnt(a.out[r] + c * Vh + eo, o);
             }
         } else if (MODE == kModeA) {
             const RT cr = (RT)a.c[r];
@@ -491,7 +504,7 @@ __global__ __launch_bounds__(STG ? 512 : kBlock) void k_dslash(const LT* __restr
                 VT o;
                 o.x = cr * pv.x - ar[r][c];
                 o.y = cr * pv.y - ai[r][c];
-                a.out[r][c * Vh + eo] = o;
+                stnt(a.out[r] + c * Vh + eo, o);
                 d = d + (double)pv.x * (double)o.x;
                 d = d + (double)pv.y * (double)o.y;
             }

@@ -9,12 +9,13 @@ namespace rhmc {
 
 void default_hop_variants(int (&v)[2][4]) {
     // index = order + 8 * batch + 24 * stage
-    // measured on MI355X at 48^3 x 12 (rhs classes 1, 2, 4, 8): z-tiles of 6
-    // planes (one XCD's share of z at Lz = 48) with t inside a tile; rows
-    // staged in LDS except for eight right-hand sides, whose staged rows do
-    // not fit three blocks per CU; loads in batches of one to four hops
-    const int fp64[4] = {52, 28, 28, 11};    // FP64-12 links (the default FP64 storage)
-    const int fp32[4] = {44, 36, 36, 36};
+    // measured on MI355X at 48^3 x 12 (rhs classes 1, 2, 4, 8; every variant
+    // timed): z-tiles of 4 or 6 planes (6: one XCD's share of z at Lz = 48)
+    // with t inside a tile; rows staged in LDS except for eight FP64
+    // right-hand sides, whose staged rows do not fit the LDS budget; loads in
+    // batches of one to four hops
+    const int fp64[4] = {68, 60, 36, 14};    // FP64-12 links (the default FP64 storage)
+    const int fp32[4] = {36, 44, 36, 28};
     for (int k = 0; k < 4; ++k) {
         v[RHMC_PREC_FP64][k] = fp64[k];
         v[RHMC_PREC_FP32][k] = fp32[k];
