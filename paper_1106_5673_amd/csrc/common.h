@@ -225,6 +225,7 @@ struct rhmc_gauge {
     size_t tmp_odd_bytes;
     double* partial;         // [kMaxSys][hopping grid] block sums of rhmc_apply_mdagm
     rhmc::Workspace* ws;     // solver workspace (lazily created)
+    int solver_depth;        // solver calls in progress on this object (nested)
     int hop_variant[2][4];   // launch variant per [RHMC_PREC_*][rhs class]
     int hop_tuned[2][4];     // 1 once the autotuner has timed that case
     void* md;                // molecular-dynamics buffers (md.hip, lazily created)

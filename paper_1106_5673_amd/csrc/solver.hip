@@ -105,6 +105,9 @@ struct Workspace {
     // without replacement; the same two per refinement chunk of up to 8 systems)
     CachedGraph graphs[kGraphSlots];
     int graph_next = 0;
+    // buffers replaced by grow() during a solver call, freed when the
+    // outermost call returns (SolverCall)
+    std::vector<void*> retired;
 };
 
 static void free_graphs(Workspace* w) {
@@ -118,6 +121,7 @@ static void free_graphs(Workspace* w) {
 void workspace_destroy(Workspace* w) {
     if (!w) return;
     free_graphs(w);
+    for (void* p : w->retired) hipFree(p);
     for (void* p : {w->ring, w->p, w->Ap, w->t, w->P, (void*)w->t64, (void*)w->rb, (void*)w->rx,
                     (void*)w->xr, (void*)w->ya, (void*)w->yf, (void*)w->hist, (void*)w->tp,
                     (void*)w->partial, (void*)w->sums,
@@ -139,18 +143,34 @@ static rhmc_status alloc(void** p, size_t bytes) {
 }
 
 // Grow one buffer to at least `need` bytes.  Captured graphs hold the old
-// address, so they are dropped; pointers held by a caller of this function
-// into *other* buffers stay valid.
+// address, so they are dropped.  The old buffer is retired, not freed: code
+// of the same solver call may still hold pointers into it (or have kernels
+// queued on it), so it stays allocated until the outermost call returns.
 static rhmc_status grow(Workspace* w, void** buf, size_t* cap, size_t need) {
     if (*cap >= need) return RHMC_OK;
     free_graphs(w);
-    hipFree(*buf);
+    if (*buf) w->retired.push_back(*buf);
     *buf = nullptr;
     *cap = 0;
     RHMC_TRY(alloc(buf, need));
     *cap = need;
     return RHMC_OK;
 }
+
+// Scope of one solver entry point (calls nest: a rational apply runs
+// multi-shift solves).  When the outermost one returns, every result has
+// been waited for, and the buffers grow() retired during it are freed.
+struct SolverCall {
+    rhmc_gauge* g;
+    explicit SolverCall(rhmc_gauge* g_) : g(g_) { ++g->solver_depth; }
+    ~SolverCall() {
+        if (--g->solver_depth > 0 || !g->ws) return;
+        for (void* p : g->ws->retired) hipFree(p);
+        g->ws->retired.clear();
+    }
+    SolverCall(const SolverCall&) = delete;
+    SolverCall& operator=(const SolverCall&) = delete;
+};
 
 // Ensure room for nsys systems x nshift shifts with blocks of K.  The
 // workspace object and its fixed-size buffers are created once per gauge
@@ -915,6 +935,7 @@ static Problem make_problem(const rhmc_gauge* g, double m, int nshift, const dou
 rhmc_status multishift(rhmc_gauge* g, double m, int nshift, const double* shifts, int nrhs,
                        const double2* b, double2* x, size_t x_sys, size_t x_shift,
                        const rhmc_solver_params& prm, rhmc_solver_stats* stats, hipStream_t s) {
+    SolverCall scope(g);
     const size_t n = (size_t)3 * g->lat.Vh;
     rhmc_solver_stats acc{};
     // process the right-hand sides in groups of kMaxSys; a group that ends
@@ -1080,6 +1101,7 @@ static rhmc_status rational_two_pass(rhmc_gauge* g, double m, const rhmc_rationa
 rhmc_status rational(rhmc_gauge* g, double m, const rhmc_rational* rat, int nrhs,
                      const double2* b, double2* y, const rhmc_solver_params& prm,
                      rhmc_solver_stats* stats, hipStream_t s) {
+    SolverCall scope(g);
     if (prm.two_pass) return rational_two_pass(g, m, rat, nrhs, b, y, prm, stats, s);
     const size_t n = (size_t)3 * g->lat.Vh;
     const int np = rat->npole;
@@ -1135,6 +1157,7 @@ rhmc_status rational(rhmc_gauge* g, double m, const rhmc_rational* rat, int nrhs
 rhmc_status pf_action(rhmc_gauge* g, double m, const rhmc_rational* rat, int nrhs,
                       const double2* phi, double* S, const rhmc_solver_params& prm,
                       rhmc_solver_stats* stats, hipStream_t s) {
+    SolverCall scope(g);
     const size_t n = (size_t)3 * g->lat.Vh;
     const int K = block_length(prm);
     RHMC_TRY(ensure_workspace(g, std::min(nrhs, kMaxSys), rat->npole, K));
@@ -1164,6 +1187,7 @@ rhmc_status pf_action(rhmc_gauge* g, double m, const rhmc_rational* rat, int nrh
 rhmc_status pf_force(rhmc_gauge* g, double m, const rhmc_rational* rat, int nrhs,
                      const double2* phi, double2* force, double* mom, double eps,
                      const rhmc_solver_params& prm, rhmc_solver_stats* stats, hipStream_t s) {
+    SolverCall scope(g);
     const size_t n = (size_t)3 * g->lat.Vh;
     const int np = rat->npole;
     const int grp = std::min(nrhs, kMaxSys);

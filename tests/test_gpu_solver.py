@@ -472,3 +472,28 @@ def test_mixed_replacement_cadence_is_exact(rh, reliable_every, block):
     res = solvers.true_residual(lambda v: dirac.mdagm(U, m, v), b[0], x[0, 0], 0.0)
     assert res <= 1e-10
     g.close()
+
+
+def test_mixed_pairs_with_finished_and_equal_members(rh):
+    """FP32 iteration vectors of several systems are stored in pairs: a pair
+    whose first member is finished from the start (a zero source) must keep
+    iterating its second member, and equal sources solved in different pairs
+    and pair halves must give the same solutions.  Sources: 0: random, 1:
+    zero, 2 and 4: copies of 0, 3: random (five systems: the last pair has an
+    absent partner)."""
+    L = (6, 4, 4, 8)
+    m = 0.05
+    U, b, lat, g = _setup(rh, L, 0.6, 5900, 5, 6900)
+    b[1] = 0.0
+    b[2] = b[0]
+    b[4] = b[0]
+    shifts = np.array([0.0, 0.01, 0.3, 2.0])
+    x, st = _solve(rh, g, lat, m, shifts, b, tol=1e-10, mode=rh.RHMC_MODE_MIXED)
+    A = lambda v: dirac.mdagm(U, m, v)  # noqa: E731
+    assert np.all(x[1] == 0)
+    for r in (0, 2, 3, 4):
+        for i, s in enumerate(shifts):
+            assert solvers.true_residual(A, b[r], x[r, i], s) <= 1e-10, (r, i)
+    for r in (2, 4):
+        assert np.linalg.norm(x[r] - x[0]) <= 1e-13 * np.linalg.norm(x[0]), r
+    g.close()
