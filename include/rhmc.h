@@ -298,26 +298,29 @@ rhmc_status rhmc_pf_force(const rhmc_gauge* g, double m, const rhmc_rational* ra
  * every launch variant (site processing order, hops per load batch, rows staged
  * in LDS per block) of one application D_oe on the given vectors
  * and keeps the fastest for this precision and rhs count in the gauge object;
- * later calls of every entry point use it.  in: device [nrhs][3][Vh] even
- * sites; out: device [nrhs][3][Vh], overwritten.  Blocks until timed.
+ * later calls of every entry point use it.  in: device vector set of nrhs
+ * even-site vectors (layout above); out: the same, overwritten.  Blocks until
+ * timed.
  * rhmc_multishift_cg and rhmc_rational_apply do the same when params->tune is set. */
 rhmc_status rhmc_tune_dslash(rhmc_gauge* g, rhmc_prec prec, int32_t nrhs, const void* in,
                              void* out, hipStream_t stream);
 
 /* The launch variant the hopping kernel currently uses for this precision and
  * rhs count (the measured default, or the autotuner's choice), for reports:
- * variant (host int32) = order + 8 * batch + 24 * stage, with order the site
- * processing order 0..7 (0 even-odd index; 1..7 z-tiles of 1, 2, 4, 6, 8, 3, 12
- * planes with t inside a tile, a tile that does not divide Lz read as 1), batch
- * the number of hops whose loads are issued together (1, 2, 4 for 0..2) and
- * stage the rows of an xy-plane a block stages in LDS for its +-x and +-y hops
- * (0 none, 1 the fewest, 2 the most rows that fit: whole waves of 64..512 sites
- * and 48 KB of LDS; none where no row count fits). */
+ * variant (host int32) = order + 8 * batch + 24 * shape + 96 * tile, with
+ * order the site processing order 0..7 (0 even-odd index; 1..7 z-tiles of 1,
+ * 2, 4, 6, 8, 3, 12 planes with t inside a tile, a tile that does not divide
+ * Lz read as 1), batch the number of hops whose loads are issued together (1,
+ * 2, 4 for 0..2), shape the block (0 256 sites; 1, 2 whole rows of an
+ * xy-plane staged in LDS for the +-x and +-y hops, the fewest or the most
+ * rows that fit whole waves of 64..512 sites and 48 KB of LDS, 256 sites
+ * where none fits; 3 128 sites) and tile the right-hand sides per launch (0
+ * all of them; 1 half of a class of four or eight, in two launches). */
 rhmc_status rhmc_dslash_variant(const rhmc_gauge* g, rhmc_prec prec, int32_t nrhs,
                                 int32_t* variant);
 
 /* Pin the launch variant of the hopping kernel for this precision and rhs
- * count (0 <= variant < 72, layout as above).  Every variant computes the
+ * count (0 <= variant < 192, layout as above).  Every variant computes the
  * same result bit for bit; they differ only in speed.  Marks the class as
  * tuned, so tune = 1 in later solver calls keeps it. */
 rhmc_status rhmc_set_dslash_variant(rhmc_gauge* g, rhmc_prec prec, int32_t nrhs,

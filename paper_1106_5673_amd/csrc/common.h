@@ -279,22 +279,33 @@ struct DslashArgs {
     FastDiv zt;                   // site order: z-tile planes (d == 0: eo order), set at launch
 };
 
-// Launch variants of the hopping kernel, index = order + 8 * batch + 24 * stage:
+// Launch variants of the hopping kernel,
+// index = order + 8 * batch + 24 * shape + 96 * tile:
 //   order  site processing order (process_site): 0 the eo index; 1..7 z-tiles
 //          of kZTile[order] planes with t inside a tile (a tile size that does
 //          not divide Lz falls back to 1)
 //   batch  hops whose loads are issued together: 1, 2 or 4
-//   stage  rows of the xy-plane staged in LDS per block (none, fewest, most;
-//          stage_rows), so the +-x and +-y hops read LDS; falls back to none
-//          where no row count fits
+//   shape  block shape: 0 blocks of 256 sites; 1, 2 blocks of whole rows of
+//          the xy-plane staged in LDS (the fewest, the most rows that fit;
+//          stage_rows), so the +-x and +-y hops read LDS (falls back to 0
+//          where no row count fits); 3 blocks of 128 sites
+//   tile   right-hand sides per launch: 0 all of the launch's class; 1 half
+//          of a class of four or eight, i.e. two launches (each link then read
+//          twice, each launch holding half the rhs registers)
 // Link loads are non-temporal (read once per application).  Every variant
 // computes the same bits.
-constexpr int kHopOrders = 8, kHopBatches = 3, kHopStages = 3;
-constexpr int kHopVariants = kHopOrders * kHopBatches * kHopStages;
+constexpr int kHopOrders = 8, kHopBatches = 3, kHopShapes = 4, kHopTiles = 2;
+constexpr int kHopVariants = kHopOrders * kHopBatches * kHopShapes * kHopTiles;
 constexpr int kZTile[kHopOrders] = {0, 1, 2, 4, 6, 8, 3, 12};
 inline int hop_order(int v) { return v % kHopOrders; }
 inline int hop_batch(int v) { return (v / kHopOrders) % kHopBatches; }
-inline int hop_stage(int v) { return v / (kHopOrders * kHopBatches); }
+inline int hop_stage(int v) { return (v / (kHopOrders * kHopBatches)) % kHopShapes; }
+inline int hop_tile(int v) { return v / (kHopOrders * kHopBatches * kHopShapes); }
+// sites per block of an unstaged launch of this shape
+inline int hop_block(int shape) { return shape == 3 ? 128 : kBlock; }
+// rhs per launch of this variant in a launch class of nr rhs (tiles stay
+// even, so FP32 pairs stay whole)
+inline int hop_tile_nr(int variant, int nr) { return (hop_tile(variant) && nr >= 4) ? nr / 2 : nr; }
 // right-hand-side classes of the kernel templates: 1, 2, 4, 8
 inline int nr_class(int nrhs) { return nrhs <= 1 ? 0 : nrhs <= 2 ? 1 : nrhs <= 4 ? 2 : 3; }
 inline int nr_of_class(int cls) { return 1 << cls; }
@@ -307,9 +318,9 @@ constexpr size_t kStageLdsMax = 48 * 1024;
 // Rows per block of a staged launch (0: staging not possible): R divides Ly,
 // the block of R * Lx/2 sites is a whole number of waves (64..512 sites), and
 // the staged input [NR][3][R + 2][Lx/2] fits the LDS budget; stage 1 takes
-// the smallest such R, stage 2 the largest.
+// the smallest such R, stage 2 the largest; other shapes stage nothing.
 inline int stage_rows(const Geom& g, int stage, int nr, int vt_bytes) {
-    if (stage == 0) return 0;
+    if (stage != 1 && stage != 2) return 0;
     int best = 0;
     for (int R = 1; R <= g.Ly; ++R) {
         const int B = R * g.hx;
@@ -324,9 +335,13 @@ inline int stage_rows(const Geom& g, int stage, int nr, int vt_bytes) {
 
 // Blocks of a hopping launch of this variant (one partial sum per block and
 // rhs in the reducing modes); at most max_hop_grid(Vh).
+// (Both launches of a tiled variant have this grid.)
 inline int hop_grid(const Geom& g, int variant, int nr, int vt_bytes) {
+    nr = hop_tile_nr(variant, nr);
     const int R = stage_rows(g, hop_stage(variant), nr, vt_bytes);
-    return R ? g.Vh / (R * g.hx) : (g.Vh + kBlock - 1) / kBlock;
+    if (R) return g.Vh / (R * g.hx);
+    const int B = hop_block(hop_stage(variant));
+    return (g.Vh + B - 1) / B;
 }
 inline int max_hop_grid(int Vh) { return (Vh + 63) / 64; }
 

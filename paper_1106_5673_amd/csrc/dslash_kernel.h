@@ -327,7 +327,7 @@ __global__ __launch_bounds__(STG ? 512 : kBlock) void k_dslash(const LT* __restr
     const int nblk = gridDim.x;
     const int blk = xcd_remap(blockIdx.x, nblk);
     const int Vh = a.g.Vh;
-    const int bsites = STG ? (int)blockDim.x : kBlock;   // sites per block
+    const int bsites = (int)blockDim.x;   // sites per block
     const int p_raw = blk * bsites + (int)threadIdx.x;
     if (p_raw >= Vh && MODE == kModeD) return;   // (staged blocks are never partial)
     const bool in_range = p_raw < Vh;
@@ -577,7 +577,25 @@ inline hipError_t launch_batch(const LT* links, int nlinks, const DslashArgs<VT>
     }
 }
 
-// One hopping launch in the variant a.variant (see kHopVariants).
+// One launch of the kernel for nr right-hand sides in the shape of variant v.
+template <typename VT, typename LT, int MODE>
+inline hipError_t launch_shape(const LT* links, int nlinks, const DslashArgs<VT>& a, int nr, int v,
+                               hipStream_t s) {
+    const int shape = hop_stage(v);
+    const int R = stage_rows(a.g, shape, nr, (int)sizeof(VT));
+    const int batch = hop_batch(v);
+    if (R) {
+        const int B = R * a.g.hx;
+        const size_t lds = (size_t)nr * 3 * (R + 2) * a.g.hx * sizeof(VT);
+        return launch_batch<VT, LT, MODE, true>(links, nlinks, a, nr, batch, dim3(a.g.Vh / B),
+                                                dim3(B), lds, s);
+    }
+    const int B = hop_block(shape);
+    return launch_batch<VT, LT, MODE, false>(links, nlinks, a, nr, batch,
+                                             dim3((a.g.Vh + B - 1) / B), dim3(B), 0, s);
+}
+
+// One hopping application in the variant a.variant (see kHopVariants).
 template <typename VT, typename LT, int MODE>
 inline hipError_t dispatch(const LT* links, int nlinks, const DslashArgs<VT>& a0, hipStream_t s) {
     DslashArgs<VT> a = a0;
@@ -592,16 +610,28 @@ inline hipError_t dispatch(const LT* links, int nlinks, const DslashArgs<VT>& a0
         if (a.paired && nr == 1) nr = 2;
         if (!a.paired && nr > 1) return hipErrorInvalidValue;
     }
-    const int R = stage_rows(a.g, hop_stage(v), nr, (int)sizeof(VT));
-    const int batch = hop_batch(v);
-    if (R) {
-        const int B = R * a.g.hx;
-        const size_t lds = (size_t)nr * 3 * (R + 2) * a.g.hx * sizeof(VT);
-        return launch_batch<VT, LT, MODE, true>(links, nlinks, a, nr, batch, dim3(a.g.Vh / B),
-                                                dim3(B), lds, s);
+    const int nt = hop_tile_nr(v, nr);
+    if (nt == nr) return launch_shape<VT, LT, MODE>(links, nlinks, a, nr, v, s);
+    // rhs tile: launches over rhs [0, nt) and [nt, nrhs), both with the
+    // template (and so the grid) for nt rhs, so that the partial sums of a
+    // reducing mode keep one layout; nt is even, so FP32 pairs stay whole
+    const int grid = hop_grid(a.g, v, nr, (int)sizeof(VT));
+    DslashArgs<VT> hi = a;
+    hi.nrhs = a.nrhs - nt;
+    for (int r = 0; r < hi.nrhs; ++r) {
+        hi.in[r] = a.in[nt + r];
+        hi.out[r] = a.out[nt + r];
+        hi.self[r] = a.self[nt + r];
+        hi.rhs[r] = a.rhs[nt + r];
+        hi.out32[r] = a.out32[nt + r];
+        hi.c[r] = a.c[nt + r];
     }
-    return launch_batch<VT, LT, MODE, false>(links, nlinks, a, nr, batch,
-                                             dim3((a.g.Vh + kBlock - 1) / kBlock), dim3(kBlock), 0, s);
+    if (a.skip) hi.skip = a.skip + (size_t)nt * a.skip_stride;
+    if (a.partial) hi.partial = a.partial + (size_t)nt * grid;
+    a.nrhs = nt;
+    const hipError_t e = launch_shape<VT, LT, MODE>(links, nlinks, a, nt, v, s);
+    if (e != hipSuccess) return e;
+    return launch_shape<VT, LT, MODE>(links, nlinks, hi, nt, v, s);
 }
 
 }  // namespace rhmc

@@ -8,14 +8,14 @@
 namespace rhmc {
 
 void default_hop_variants(int (&v)[2][4]) {
-    // index = order + 8 * batch + 24 * stage
+    // index = order + 8 * batch + 24 * shape + 96 * tile
     // measured on MI355X at 48^3 x 12 (rhs classes 1, 2, 4, 8; every variant
     // timed): z-tiles of 4 or 6 planes (6: one XCD's share of z at Lz = 48)
-    // with t inside a tile; rows staged in LDS except for eight FP64
-    // right-hand sides, whose staged rows do not fit the LDS budget; loads in
-    // batches of one to four hops
-    const int fp64[4] = {68, 60, 36, 14};    // FP64-12 links (the default FP64 storage)
-    const int fp32[4] = {36, 44, 36, 28};
+    // with t inside a tile; rows staged in LDS except for eight right-hand
+    // sides (128-site blocks); loads in batches of one to four hops; no rhs
+    // tile (splitting four or eight rhs over two launches reads the links twice)
+    const int fp64[4] = {68, 60, 36, 83};    // FP64-12 links (the default FP64 storage)
+    const int fp32[4] = {36, 44, 36, 84};
     for (int k = 0; k < 4; ++k) {
         v[RHMC_PREC_FP64][k] = fp64[k];
         v[RHMC_PREC_FP32][k] = fp32[k];

@@ -88,10 +88,10 @@ def test_lattice_rejects_too_many_sites(rh):
 
 
 def test_variant_encoding_limits(rh):
-    """The launch-variant index is order + 8 * batch + 24 * stage (72 variants)."""
+    """The launch-variant index is order + 8 * batch + 24 * shape + 96 * tile (192 variants)."""
     hdr = open(os.path.join(ROOT, "include", "rhmc.h")).read()
-    assert "0 <= variant < 72" in hdr
-    assert "order + 8 * batch + 24 * stage" in hdr
+    assert "0 <= variant < 192" in hdr
+    assert "order + 8 * batch + 24 * shape + 96 * tile" in hdr
 
 
 def test_fp32_pair_storage_layout():

@@ -215,7 +215,8 @@ def test_invalid_arguments(rh):
 
 @pytest.mark.parametrize("L", [(4, 6, 8, 4), (6, 4, 6, 8), (16, 8, 4, 6), (32, 8, 6, 4)])
 def test_every_launch_variant_gives_identical_bits(rh, L):
-    """All 72 launch variants (site order, load batching, rows staged in LDS)
+    """All 192 launch variants (site order, load batching, block shape with or
+    without rows staged in LDS, rhs tile)
     compute every output site with the same arithmetic: D_eo, D_oe and A agree
     bit for bit with variant 0, which is checked against the oracle.  z-tiles
     that do not divide Lz exercise the fallback; the last two lattices admit
@@ -235,7 +236,7 @@ def test_every_launch_variant_gives_identical_bits(rh, L):
             v = _rand_vec(rng, nrhs, lat.Vh).astype(cdt)
             vin = _to(f32layout.pack(v) if f32 else v)
             ref = {}
-            for var in range(72):
+            for var in range(192):
                 rh.rhmc_set_dslash_variant(g, prec, nrhs, var)
                 assert rh.rhmc_dslash_variant(g, prec, nrhs) == var
                 for out_par in (0, 1):
@@ -265,7 +266,7 @@ def test_every_launch_variant_gives_identical_bits(rh, L):
                 else:
                     assert np.array_equal(gotA, ref["A"]), (var, "A")
     with pytest.raises(rh.RhmcError):
-        rh.rhmc_set_dslash_variant(g, rh.RHMC_PREC_FP64, 1, 72)
+        rh.rhmc_set_dslash_variant(g, rh.RHMC_PREC_FP64, 1, 192)
     g.close()
 
 
@@ -380,7 +381,7 @@ def test_max_rhs_and_direct_tuning(rh):
     rh.rhmc_dslash_eo(g, 1, rh.RHMC_PREC_FP32, 4, v32, a)
     rh.rhmc_tune_dslash(g, rh.RHMC_PREC_FP32, 4, v32, b)
     var = rh.rhmc_dslash_variant(g, rh.RHMC_PREC_FP32, 4)
-    assert 0 <= var < 72
+    assert 0 <= var < 192
     rh.rhmc_dslash_eo(g, 1, rh.RHMC_PREC_FP32, 4, v32, b)
     assert torch.equal(a, b)
     g.close()

@@ -497,3 +497,28 @@ def test_mixed_pairs_with_finished_and_equal_members(rh):
     for r in (2, 4):
         assert np.linalg.norm(x[r] - x[0]) <= 1e-13 * np.linalg.norm(x[0]), r
     g.close()
+
+
+@pytest.mark.parametrize("nrhs", [3, 5, 8])
+def test_rhs_tiled_launch_variants_in_the_solver(rh, nrhs):
+    """Launch variants with an rhs tile (a class of four or eight right-hand
+    sides split into two launches) keep one layout of the block partial sums:
+    a MIXED solve with tiled FP32 and FP64 variants pinned reaches the
+    tolerance for every system and shift, and agrees with the untiled solve to
+    the tolerance scale."""
+    L = (6, 4, 4, 8)
+    m = 0.05
+    U, b, lat, g = _setup(rh, L, 0.6, 6100, nrhs, 7100)
+    shifts = np.array([0.0, 0.01, 0.3])
+    x0, _ = _solve(rh, g, lat, m, shifts, b, tol=1e-10, mode=rh.RHMC_MODE_MIXED)
+    tiled = 96 + 36   # staged rows, two-hop batches, z-tiles of 6, rhs tile
+    for prec in (rh.RHMC_PREC_FP32, rh.RHMC_PREC_FP64):
+        rh.rhmc_set_dslash_variant(g, prec, nrhs, tiled)
+        rh.rhmc_set_dslash_variant(g, prec, 1, 96 + 12)   # refinement systems one at a time
+    x, st = _solve(rh, g, lat, m, shifts, b, tol=1e-10, mode=rh.RHMC_MODE_MIXED)
+    A = lambda v: dirac.mdagm(U, m, v)  # noqa: E731
+    for r in range(nrhs):
+        for i, s in enumerate(shifts):
+            assert solvers.true_residual(A, b[r], x[r, i], s) <= 1e-10, (r, i)
+    assert np.linalg.norm(x - x0) <= 1e-7 * np.linalg.norm(x0)
+    g.close()
