@@ -17,6 +17,7 @@ storage (f32layout).
 import numpy as np
 import pytest
 
+import dslash_bound
 import f32layout
 import synth
 from oracle import dirac, lattice
@@ -95,18 +96,7 @@ def test_point_sources_unit_links_bit_exact(rh, prec):
     g.close()
 
 
-def _abs_scale(U, v, out_par):
-    """1/2 sum over the 8 hops of |U| |psi| per output element (error scale)."""
-    L = dirac.lattice_of(U)
-    full = np.abs(lattice.embed(v, L, 1 - out_par))
-    A = np.abs(U)
-    out = np.zeros(full.shape)
-    for mu in range(4):
-        ax = lattice.AXIS[mu]
-        out += np.einsum("...ij,...j->...i", A[..., mu, :, :], np.roll(full, -1, axis=ax))
-        Ab = np.roll(A[..., mu, :, :], 1, axis=ax - 1)
-        out += np.einsum("...ji,...j->...i", Ab, np.roll(full, 1, axis=ax))
-    return 0.5 * lattice.restrict(out, L, out_par)
+_abs_scale = dslash_bound.abs_scale
 
 
 @pytest.mark.parametrize("L", LATTICES)

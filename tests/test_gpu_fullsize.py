@@ -15,6 +15,8 @@ certified by properties that hold at any size:
 import numpy as np
 import pytest
 
+import dslash_bound
+import f32layout
 import synth
 from oracle import dirac, solvers
 from synth.make_rational import rational_for
@@ -154,6 +156,36 @@ def test_c4_fullsize_mixed_batched(rh):
     for (rr, i) in ((0, 0), (7, 14), (3, 7)):
         xi = x[rr, i].cpu().numpy()
         assert solvers.true_residual(A, b[rr], xi, r.beta[i]) <= tol
+    g.close()
+
+
+def test_c5_hopping_kernels_fullsize(rh):
+    """48^3x12, the four sources of the workload: the FP32-12 (paired vectors)
+    and FP64-12 hopping launches in the library's default launch variants,
+    which the bench times, against the oracle on every output element: FP32
+    within its rounding bound (32 * 2^-24 of 1/2 sum |U| |psi|), FP64 to 1e-13
+    of the largest element."""
+    import torch
+
+    c, U, b, lat, g = _workload(rh, 5)
+    U = np.asarray(U)
+    for out_par in (1, 0):
+        want = dirac.dslash(U, b, out_par)
+        vin = _dev(b)
+        out = torch.empty_like(vin)
+        rh.rhmc_dslash_eo(g, out_par, rh.RHMC_PREC_FP64, 4, vin, out)
+        got = out.cpu().numpy()
+        assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max()
+        b32 = b.astype(np.complex64)
+        vin = _dev(f32layout.pack(b32))
+        out = torch.empty_like(vin)
+        rh.rhmc_dslash_eo(g, out_par, rh.RHMC_PREC_FP32, 4, vin, out)
+        got = f32layout.unpack(out.cpu().numpy(), 4, lat.Vh).astype(np.complex128)
+        b64 = b32.astype(np.complex128)
+        want = dirac.dslash(U, b64, out_par)
+        bound = 32 * 2.0 ** -24 * dslash_bound.abs_scale(U, b64, out_par) + 1e-30
+        err = np.abs(got - want)
+        assert np.all(err <= bound), float((err / bound).max())
     g.close()
 
 
