@@ -356,31 +356,51 @@ __global__ __launch_bounds__(kBlock) void k_flush_coef(void* state) {
 }
 
 // One thread per complex element of one system's vectors: the stored base
-// residuals r(k0+l), l <= q, are widened to FP64 once and stay in registers
-// while every shift's X and P stream through once.  The coefficients d_l, f_l
-// of a shift are zero beyond its last step (k_flush_coef), so the inner loop
-// is straight-line code over l = 1..Q with wave-uniform coefficients (scalar
-// registers).  Shifts go in pairs whose loads are issued together.
+// residuals r(k0+l), l <= q, stay in registers while every shift's X and P
+// stream through once, a pair of shifts per pass.  The coefficients of a pass
+// (e, c, f_l, d_l of both shifts, for each system of the block) are staged in
+// LDS and read by broadcast: in scalar registers they would not fit.  The
+// coefficients are zero beyond a shift's last step (k_flush_coef), so the
+// step loop is straight-line code over l = 1..Q; ring slots beyond q are read
+// as slot q (finite values times zero).  Paired FP32 rings: block row y takes
+// systems 2y and 2y + 1, the two halves of a block the same elements of both,
+// so each 16-byte ring entry is fetched from memory once.
 template <typename VT, int Q>
 __global__ __launch_bounds__(kBlock) void k_flush(FlushArgs<VT> a,
                                                   const BlockCoef* __restrict__ coef) {
     constexpr int U = 2;
+    constexpr int H = kBlock / 2;
+    __shared__ double2 cs[2][U][Q + 1];   // [system of the block][u][l]: (f_l, d_l); l = 0: (e, c)
     const SolverState* st = reinterpret_cast<const SolverState*>(a.state);
-    const int j = blockIdx.y;
-    const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
-    const int q = st->sys[j].blk_steps;
-    if (q == 0 || i >= a.n) return;
-    // Long blocks keep an FP32 ring in FP32 registers (widened exactly where
-    // used); below 32 steps that form makes the compiler spill, so the
-    // residuals are widened on load instead.
+    const int nsb = a.paired ? 2 : 1;    // systems per block
+    int hs = 0;                          // this thread's system within the block
+    size_t i;
+    if (a.paired) {
+        hs = (int)threadIdx.x >= H;
+        i = (size_t)blockIdx.x * H + (threadIdx.x - hs * H);
+    } else {
+        i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    }
+    // uniform over a wave (half a block is two whole waves): scalar registers
+    hs = __builtin_amdgcn_readfirstlane(hs);
+    auto sys_of = [&](int h) { return a.paired ? 2 * (int)blockIdx.y + h : (int)blockIdx.y; };
+    auto steps_of = [&](int h) { return sys_of(h) < a.nsys ? st->sys[sys_of(h)].blk_steps : 0; };
+    const int j = sys_of(hs);
+    const int q = steps_of(hs);
+    if (steps_of(0) == 0 && (nsb == 1 || steps_of(1) == 0)) return;   // the whole block
+    const bool live = q != 0 && i < a.n;
+    // Long blocks keep an FP32 ring in FP32 registers, widened where it is
+    // used (below); for 16 to 25 steps that form makes the compiler spill, so
+    // shorter rings are widened on load instead.
     using RR = typename std::conditional<std::is_same<VT, float2>::value && (Q >= 32), float,
                                          double>::type;
     RR rre[Q + 1], rim[Q + 1];
+    const size_t off = live ? f32_offset(a.paired, j, i, a.n) : 0;
 #pragma unroll
     for (int l = 0; l <= Q; ++l) {
         rre[l] = rim[l] = 0.0;
-        if (l <= q) {
-            const VT v = a.ring[(size_t)l * a.ring_slot + f32_offset(a.paired, j, i, a.n)];
+        if (live) {
+            const VT v = a.ring[(size_t)(l < q ? l : q) * a.ring_slot + off];
             rre[l] = v.x;
             rim[l] = v.y;
         }
@@ -391,42 +411,82 @@ __global__ __launch_bounds__(kBlock) void k_flush(FlushArgs<VT> a,
     double2* __restrict__ P = a.P;
 #pragma unroll 1
     for (int s0 = 0; s0 < nsh; s0 += U) {
+        // skip (block-uniformly) a pair with no active shift in any system of the block
+        bool any = false;
+        for (int h = 0; h < nsb; ++h)
+            for (int u = 0; u < U; ++u)
+                any = any || (steps_of(h) != 0 && s0 + u < nsh && st->sh[sys_of(h)][s0 + u].block_active);
+        if (!any) continue;
+        __syncthreads();   // the previous pair's coefficients have been read
+        for (int e = threadIdx.x; e < nsb * U * (Q + 1); e += kBlock) {
+            const int h = e / (U * (Q + 1)), r = e - h * U * (Q + 1);
+            const int u = r / (Q + 1), l = r - u * (Q + 1);
+            const int jj = sys_of(h);
+            const int sh = s0 + u < nsh ? s0 + u : s0;   // the absent partner: any valid shift
+            if (jj < a.nsys) {
+                const BlockCoef& bc = coef[jj * kMaxShift + sh];
+                cs[h][u][l] = l == 0 ? make_double2(bc.e, bc.c) : make_double2(bc.f[l], bc.d[l]);
+            }
+        }
+        __syncthreads();
         bool act[U];
-        double2 xv[U];
-        double p0r[U], p0i[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) act[u] = q != 0 && s0 + u < nsh && st->sh[j][s0 + u].block_active;
+        if (!live || !(act[0] || act[1])) continue;
+        double xr[U], xi[U], pr[U], pi[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int sh = s0 + u;
-            act[u] = sh < nsh && st->sh[j][sh].block_active;
-            xv[u] = make_double2(0.0, 0.0);
-            p0r[u] = rre[0];
-            p0i[u] = rim[0];
+            double2 xv = make_double2(0.0, 0.0);
+            double p0r = rre[0], p0i = rim[0];
             if (act[u] && !first) {
-                xv[u] = X[j * a.x_sys + sh * a.x_shift + i];
+                xv = X[j * a.x_sys + sh * a.x_shift + i];
                 const double2 pv = P[((size_t)j * nsh + sh) * a.n + i];
-                p0r[u] = (double)pv.x;
-                p0i[u] = (double)pv.y;
+                p0r = pv.x;
+                p0i = pv.y;
+            }
+            const double2 ec = cs[hs][u][0];
+            xr[u] = xv.x + ec.x * p0r;
+            xi[u] = xv.y + ec.x * p0i;
+            pr[u] = ec.y * p0r;
+            pi[u] = ec.y * p0i;
+        }
+        // Each stored residual is widened once per pair of shifts, where it
+        // is used, and the coefficients are read a few steps at a time: the
+        // empty asms keep the compiler from widening the whole ring or
+        // reading every coefficient up front, which would not fit the
+        // registers.
+        constexpr int kChunk = std::is_same<RR, float>::value ? 4 : 2;
+#pragma unroll
+        for (int l0 = 1; l0 <= Q; l0 += kChunk) {
+            // the previous chunk's sums are complete here, and no load of
+            // this chunk moves above this point
+            asm volatile("" : "+v"(xr[0]), "+v"(xi[0]), "+v"(pr[0]), "+v"(pi[0]), "+v"(xr[1]),
+                         "+v"(xi[1]), "+v"(pr[1]), "+v"(pi[1])::"memory");
+#pragma unroll
+            for (int l = l0; l < l0 + kChunk && l <= Q; ++l) {
+                RR re = rre[l], im = rim[l];
+                if constexpr (std::is_same<RR, float>::value) asm volatile("" : "+v"(re), "+v"(im));
+                const double dre = re, dim = im;
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const double2 fd = cs[hs][u][l];
+                    xr[u] += fd.x * dre;
+                    xi[u] += fd.x * dim;
+                    pr[u] += fd.y * dre;
+                    pi[u] += fd.y * dim;
+                }
             }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (!act[u]) continue;
             const int sh = s0 + u;
-            const BlockCoef& bc = coef[j * kMaxShift + sh];
-            double xr = xv[u].x + bc.e * p0r[u], xi = xv[u].y + bc.e * p0i[u];
-            double pr = bc.c * p0r[u], pi = bc.c * p0i[u];
-#pragma unroll
-            for (int l = 1; l <= Q; ++l) {
-                const double f = bc.f[l], d = bc.d[l];
-                xr += f * (double)rre[l];
-                xi += f * (double)rim[l];
-                pr += d * (double)rre[l];
-                pi += d * (double)rim[l];
-            }
-            X[j * a.x_sys + sh * a.x_shift + i] = make_double2(xr, xi);
-            if (st->sh[j][sh].active) P[((size_t)j * nsh + sh) * a.n + i] = make_double2(pr, pi);
+            X[j * a.x_sys + sh * a.x_shift + i] = make_double2(xr[u], xi[u]);
+            if (st->sh[j][sh].active) P[((size_t)j * nsh + sh) * a.n + i] = make_double2(pr[u], pi[u]);
         }
     }
+    if (!live) return;
     if (a.y) {
         // two-pass rational apply: residuals r(k0)..r(k0+q-1) of this block
         // (the host checks that this pass repeats the first one; the bound
@@ -450,7 +510,7 @@ __global__ __launch_bounds__(kBlock) void k_flush(FlushArgs<VT> a,
             VT v;
             v.x = rre[l];
             v.y = rim[l];
-            a.ring[f32_offset(a.paired, j, i, a.n)] = v;
+            a.ring[off] = v;
         }
 }
 
@@ -664,10 +724,16 @@ template <typename VT>
 hipError_t launch_flush(const FlushArgs<VT>& a, int nsys, int qmax, hipStream_t s) {
     hipLaunchKernelGGL(k_flush_coef, dim3(1), dim3(kBlock), 0, s, a.state);
     const BlockCoef* coef = reinterpret_cast<const BlockCoef*>(a.coef);
-    const dim3 g((unsigned)((a.n + kBlock - 1) / kBlock), (unsigned)nsys), b(kBlock);
+    const int per = a.paired ? kBlock / 2 : kBlock;   // elements per block
+    const dim3 g((unsigned)((a.n + per - 1) / per), (unsigned)(a.paired ? (nsys + 1) / 2 : nsys)),
+        b(kBlock);
     // register arrays sized by the block length (coefficients beyond a
-    // shift's last step are zero, so rounding up only adds idle terms)
-    if (qmax <= 4)
+    // shift's last step are zero, so rounding up only adds idle terms); an
+    // FP32 ring of 5 to 32 steps takes the 32-step form, the shortest that
+    // keeps it in FP32 registers without spilling
+    if (std::is_same<VT, float2>::value && qmax > 4 && qmax <= 32)
+        hipLaunchKernelGGL((k_flush<VT, 32>), g, b, 0, s, a, coef);
+    else if (qmax <= 4)
         hipLaunchKernelGGL((k_flush<VT, 4>), g, b, 0, s, a, coef);
     else if (qmax <= 16)
         hipLaunchKernelGGL((k_flush<VT, 16>), g, b, 0, s, a, coef);

@@ -1,7 +1,10 @@
 // Launch-variant defaults and the autotuner of the hopping kernel (the
 // batching form of the solver: the launch shape of each (precision, rhs
 // count) is picked by timing, kept per gauge object).
+#include <algorithm>
 #include <cstdlib>
+#include <utility>
+#include <vector>
 
 #include "common.h"
 
@@ -27,6 +30,10 @@ void default_hop_variants(int (&v)[2][4]) {
     }
 }
 
+// Every variant is timed over a few launches; the fastest eight are timed
+// again, three rounds of ten launches each, interleaved, and the one with the
+// smallest median round wins (a single short pass picks among variants a few
+// percent apart by noise).
 rhmc_status tune_hop(rhmc_gauge* g, rhmc_prec prec, int nrhs, const void* in, void* out,
                      hipStream_t s) {
     const int cls = nr_class(nrhs);
@@ -34,9 +41,9 @@ rhmc_status tune_hop(rhmc_gauge* g, rhmc_prec prec, int nrhs, const void* in, vo
     hipEvent_t e0 = nullptr, e1 = nullptr;
     RHMC_HIP_TRY(hipEventCreate(&e0));
     RHMC_HIP_TRY(hipEventCreate(&e1));
-    float best = 1e30f;
-    int best_v = g->hop_variant[prec][cls];
-    for (int v = 0; v < kHopVariants; ++v) {
+    std::vector<std::pair<float, int>> pass1;
+    // time `reps` launches of variant v after `warm` untimed ones (ms per launch)
+    auto time_variant = [&](int v, int warm, int reps, float* ms_out) -> hipError_t {
         hipError_t err = hipSuccess;
         auto launch = [&]() {
             if (prec == RHMC_PREC_FP64) {
@@ -64,25 +71,46 @@ rhmc_status tune_hop(rhmc_gauge* g, rhmc_prec prec, int nrhs, const void* in, vo
                 err = launch_fp32_op(g, a, kModeD, s);
             }
         };
-        for (int w = 0; w < 2 && err == hipSuccess; ++w) launch();
+        for (int w = 0; w < warm && err == hipSuccess; ++w) launch();
         if (err == hipSuccess) err = hipEventRecord(e0, s);
-        for (int w = 0; w < 5 && err == hipSuccess; ++w) launch();
+        for (int w = 0; w < reps && err == hipSuccess; ++w) launch();
         if (err == hipSuccess) err = hipEventRecord(e1, s);
         if (err == hipSuccess) err = hipEventSynchronize(e1);
         float ms = 0.f;
         if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
-        if (err != hipSuccess) {
-            hipEventDestroy(e0);
-            hipEventDestroy(e1);
-            RHMC_HIP_TRY(err);
-        }
-        if (ms < best) {
-            best = ms;
-            best_v = v;
+        *ms_out = ms / reps;
+        return err;
+    };
+    hipError_t err = hipSuccess;
+    for (int v = 0; v < kHopVariants && err == hipSuccess; ++v) {
+        float ms = 0.f;
+        err = time_variant(v, 2, 5, &ms);
+        pass1.push_back({ms, v});
+    }
+    int best_v = g->hop_variant[prec][cls];
+    if (err == hipSuccess) {
+        std::sort(pass1.begin(), pass1.end());
+        const int nc = std::min<int>(8, (int)pass1.size());
+        std::vector<std::vector<float>> rounds(nc);
+        for (int r = 0; r < 3 && err == hipSuccess; ++r)
+            for (int c = 0; c < nc && err == hipSuccess; ++c) {
+                float ms = 0.f;
+                err = time_variant(pass1[c].second, 2, 10, &ms);
+                rounds[c].push_back(ms);
+            }
+        float best = 1e30f;
+        for (int c = 0; c < nc && err == hipSuccess; ++c) {
+            std::sort(rounds[c].begin(), rounds[c].end());
+            const float med = rounds[c][rounds[c].size() / 2];
+            if (med < best) {
+                best = med;
+                best_v = pass1[c].second;
+            }
         }
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
+    RHMC_HIP_TRY(err);
     g->hop_variant[prec][cls] = best_v;
     g->hop_tuned[prec][cls] = 1;
     return RHMC_OK;
