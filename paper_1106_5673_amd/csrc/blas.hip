@@ -456,7 +456,7 @@ __global__ __launch_bounds__(kBlock) void k_flush(FlushArgs<VT> a,
         // empty asms keep the compiler from widening the whole ring or
         // reading every coefficient up front, which would not fit the
         // registers.
-        constexpr int kChunk = std::is_same<RR, float>::value ? 4 : 2;
+        constexpr int kChunk = 2;
 #pragma unroll
         for (int l0 = 1; l0 <= Q; l0 += kChunk) {
             // the previous chunk's sums are complete here, and no load of
