@@ -247,6 +247,39 @@ def kernel_entry(t, t_min, nbytes, nflops):
     return e
 
 
+def time_call(torch, fn, reps, warm=3):
+    """Median and minimum of reps launches of fn, each between its own pair of
+    HIP events on the current stream."""
+    for _ in range(warm):
+        fn()
+    s = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for e0, e1 in ev:
+        e0.record(s)
+        fn()
+        e1.record(s)
+    ev[-1][1].synchronize()
+    ts = sorted(e0.elapsed_time(e1) / 1e3 for e0, e1 in ev)
+    return ts[len(ts) // 2], ts[0]
+
+
+def time_md_kernels(rhmc, torch, dev, g, lat, L):
+    """Gauge-force kick and link update on the headline lattice (50 timed
+    launches each after 3 untimed)."""
+    import synth
+
+    mom = torch.from_numpy(synth.momenta(L, 4000 + HEADLINE_CFG)).to(dev)
+    beta_g, eps_g = synth.MD_WORKLOAD["beta"], 0.004
+    t_gf, t_gf_min = time_call(torch, lambda: rhmc.rhmc_gauge_force_kick(g, beta_g, 1e-9, mom), 50)
+    t_up, t_up_min = time_call(torch, lambda: rhmc.rhmc_update_links(g, eps_g, mom), 50)
+    nl = 4 * lat.V
+    del mom
+    return {"gauge_force_kick": kernel_entry(t_gf, t_gf_min, GF_BYTES_PER_LINK * nl, GF_FLOPS_PER_LINK * nl),
+            "link_update": kernel_entry(t_up, t_up_min, UP_BYTES_PER_LINK * nl, None),
+            "note": "HIP events around each launch; GB/s counts each FP64-12 link, momentum and "
+                    "written storage once"}
+
+
 def run_md_trajectory(rhmc, torch, dev, ntraj):
     """Trajectories of the molecular-dynamics workload of the algorithm tests
     (4 x 16^3, beta 5.264, am 0.01335, 2 pseudofermions, n_md 12,
@@ -372,6 +405,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only-dslash", action="store_true",
                     help="only the hopping-kernel timing and a copy of known size (counter runs)")
+    ap.add_argument("--only-md", action="store_true",
+                    help="only the molecular-dynamics kernels on the headline lattice and "
+                         "trajectories of the 4x16^3 workload (profiler runs)")
+    ap.add_argument("--md-trajectories", type=int, default=2,
+                    help="timed 4x16^3 trajectories (after one untimed)")
     ap.add_argument("--cpu-baseline-child", metavar="DIR", help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.cpu_baseline_child:
@@ -396,7 +434,7 @@ def main():
     b = synth.source(L, synth.fields.seed_source(HEADLINE_CFG), nrhs)
     rat = rational_for(HEADLINE_CFG, -0.25)
     extra_inputs = {}
-    if not args.only_dslash and not args.no_extras:
+    if not args.only_dslash and not args.no_extras and not args.only_md:
         for cfg in (1, 2, 3, 4):
             cc = synth.CONFIGS[cfg]
             extra_inputs[cfg] = (synth.gauge_field(cc["L"], cc["eps"], synth.fields.seed_gauge(cfg)),
@@ -418,6 +456,12 @@ def main():
     log("gauge packed on the device")
     # average plaquette Re Tr P / 3 of the field: S_g at beta = 1 is sum (1 - Re Tr P / 3)
     plaquette = 1.0 - rhmc.rhmc_gauge_action(g, 1.0) / (6.0 * lat.V)
+    if args.only_md:
+        md = {"md_kernels": time_md_kernels(rhmc, torch, dev, g, lat, L),
+              "md_trajectory_16x16x16x4": run_md_trajectory(rhmc, torch, dev, args.md_trajectories)}
+        log("molecular-dynamics kernels and trajectories done")
+        print(json.dumps({"lattice": list(L), "plaquette": round(plaquette, 6), **md}))
+        return
 
     def time_dslash(prec, k, reps, gauge=None, vh=None, warm=20, flush=None):
         """Median and min launch time of D_oe over `reps` launches, each
@@ -639,31 +683,7 @@ def main():
                                    "force_s": round(t_force, 4),
                                    "max_abs_S_over_RR_minus_1": float(np.max(np.abs(S / R2 - 1)))}
         # molecular-dynamics kernels on this lattice
-        mom = torch.from_numpy(synth.momenta(L, 4000 + HEADLINE_CFG)).to(dev)
-        beta_g, eps_g = synth.MD_WORKLOAD["beta"], 0.004
-
-        def time_call(fn, reps, warm=3):
-            for _ in range(warm):
-                fn()
-            s = torch.cuda.current_stream()
-            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
-            for e0, e1 in ev:
-                e0.record(s)
-                fn()
-                e1.record(s)
-            ev[-1][1].synchronize()
-            ts = sorted(e0.elapsed_time(e1) / 1e3 for e0, e1 in ev)
-            return ts[len(ts) // 2], ts[0]
-
-        t_gf, t_gf_min = time_call(lambda: rhmc.rhmc_gauge_force_kick(g, beta_g, 1e-9, mom), 50)
-        t_up, t_up_min = time_call(lambda: rhmc.rhmc_update_links(g, eps_g, mom), 50)
-        nl = 4 * lat.V
-        extras["md_kernels"] = {
-            "gauge_force_kick": kernel_entry(t_gf, t_gf_min, GF_BYTES_PER_LINK * nl, GF_FLOPS_PER_LINK * nl),
-            "link_update": kernel_entry(t_up, t_up_min, UP_BYTES_PER_LINK * nl, None),
-            "note": "HIP events around each launch; GB/s counts each FP64-12 link, momentum and "
-                    "written storage once"}
-        del mom
+        extras["md_kernels"] = time_md_kernels(rhmc, torch, dev, g, lat, L)
     # link storages other than the defaults, same lattice
     if not args.no_extras:
         ghl = rhmc.rhmc_gauge_create(lat, U, flags=rhmc.RHMC_LINKS_HILO_12)
@@ -781,7 +801,7 @@ def main():
                                  "fp64": rhmc.rhmc_dslash_variant(gc, rhmc.RHMC_PREC_FP64, nr)}}
             del xm, x64
             gc.close()
-        extras["md_trajectory_16x16x16x4"] = run_md_trajectory(rhmc, torch, dev, 2)
+        extras["md_trajectory_16x16x16x4"] = run_md_trajectory(rhmc, torch, dev, args.md_trajectories)
 
     out = {
         "metric": METRIC,

@@ -22,22 +22,32 @@ __device__ __forceinline__ void mat_identity(Mat3& a) {
     a.re[0][0] = a.re[1][1] = a.re[2][2] = 1.0;
 }
 
-// c = a b (DA, DB select a^dagger, b^dagger)
-template <bool DA, bool DB>
+// c = a b (DA, DB select a^dagger, b^dagger); ACC: c += a b.  Each real and
+// imaginary part is one chain of fused multiply-adds over k (four per complex
+// product instead of a multiply, a fused multiply-add and an add).  c must
+// not alias a or b.
+template <bool DA, bool DB, bool ACC = false>
 __device__ __forceinline__ void mat_mul(const Mat3& a, const Mat3& b, Mat3& c) {
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            double sr = 0.0, si = 0.0;
+            double sr = ACC ? c.re[i][j] : 0.0, si = ACC ? c.im[i][j] : 0.0;
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 const double ar = DA ? a.re[k][i] : a.re[i][k];
                 const double ai = DA ? -a.im[k][i] : a.im[i][k];
                 const double br = DB ? b.re[j][k] : b.re[k][j];
                 const double bi = DB ? -b.im[j][k] : b.im[k][j];
-                sr += ar * br - ai * bi;
-                si += ar * bi + ai * br;
+                if (!ACC && k == 0) {
+                    sr = ar * br;
+                    si = ar * bi;
+                } else {
+                    sr = __builtin_fma(ar, br, sr);
+                    si = __builtin_fma(ar, bi, si);
+                }
+                sr = __builtin_fma(-ai, bi, sr);
+                si = __builtin_fma(ai, br, si);
             }
             c.re[i][j] = sr;
             c.im[i][j] = si;

@@ -39,6 +39,36 @@ __device__ __forceinline__ void load(const LT* links, int nlinks, int k, Mat3& U
     load_link<false>(links, nlinks, k, U);
 }
 
+// FP64-12: rows 1-2 as stored, row 3 = conj(row1 x row2) in chains of fused
+// multiply-adds (the hopping term rebuilds it without contraction so that its
+// launch variants agree bit for bit; these kernels have one variant each).
+template <>
+__device__ __forceinline__ void load<Fp64x12Link>(const Fp64x12Link* links, int nlinks, int k,
+                                                  Mat3& U) {
+    const LinkPlanes<Fp64x12Link> P = link_planes(links, nlinks);
+    const uint32_t o = byte_off(k, 16);
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+        const double2 v = ldg<false>(P.at(e, o));
+        U.re[e / 3][e % 3] = v.x;
+        U.im[e / 3][e % 3] = v.y;
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const int j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+        double pr = U.re[0][j1] * U.re[1][j2];
+        pr = __builtin_fma(-U.im[0][j1], U.im[1][j2], pr);
+        pr = __builtin_fma(-U.re[0][j2], U.re[1][j1], pr);
+        pr = __builtin_fma(U.im[0][j2], U.im[1][j1], pr);
+        double pi = U.re[0][j1] * U.im[1][j2];
+        pi = __builtin_fma(U.im[0][j1], U.re[1][j2], pi);
+        pi = __builtin_fma(-U.re[0][j2], U.im[1][j1], pi);
+        pi = __builtin_fma(-U.im[0][j2], U.re[1][j1], pi);
+        U.re[2][j] = pr;
+        U.im[2][j] = -pi;
+    }
+}
+
 // E = exp(i Q) for Hermitian Q: the series of the matrix scaled to Frobenius
 // norm <= 1/2 (terms fall below 1e-17 within 16 orders), then squared back.
 __device__ void exp_i(const Mat3& Q, Mat3& E) {
@@ -170,19 +200,31 @@ __device__ __forceinline__ void store_link(const Mat3& U, int k, int nlinks, dou
 // One lane per link: the six staples, X = U Sigma, and
 // mom^a -= eps * scale * i Tr(T^a TA(X)).  The 8 (mu, parity) link classes
 // of one range of sites are consecutive blocks, and each XCD takes a
-// contiguous run of blocks, so the 18 neighbour links a lane reads were
-// mostly just read by a nearby lane of the same XCD (its L2).
+// contiguous run of blocks.  Within a class the sites run x fastest, then t,
+// then z inside a slab of sz planes, then y, then slab, so that the t and z
+// neighbours of a wave's links are a few blocks away and each XCD holds
+// whole slabs.  The kernel is bound by its FP64 arithmetic and load latency
+// more than by its bytes: the products are fused multiply-add chains.
 template <typename LT>
 __global__ __launch_bounds__(kBlock) void k_gauge_force(const LT* links, int nlinks, Geom g,
-                                                        double scale, double eps,
+                                                        FastDiv dsz, double scale, double eps,
                                                         double* __restrict__ mom) {
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int cls = blk & 7;
     const int mu = cls >> 1, par = cls & 1;
-    const int eo = (blk >> 3) * kBlock + threadIdx.x;
-    if (eo >= g.Vh) return;
+    const int p = (blk >> 3) * kBlock + threadIdx.x;
+    if (p >= g.Vh) return;
     int n[4];
-    site_coords(g, eo, par, n[0], n[1], n[2], n[3]);
+    {
+        int xh, r, zz, slab;
+        fdivmod(p, g.dhx, r, xh);
+        fdivmod(r, g.dLt, r, n[3]);
+        fdivmod(r, dsz, r, zz);
+        fdivmod(r, g.dLy, slab, n[1]);
+        n[2] = slab * (int)dsz.d + zz;
+        n[0] = 2 * xh + ((par + n[1] + n[2] + n[3]) & 1);
+    }
+    const int eo = (n[0] >> 1) + g.hx * (n[1] + g.Ly * (n[2] + g.Lz * n[3]));
     Mat3 S, A, B, C;
     mat_zero(S);
 #pragma unroll 1
@@ -201,15 +243,13 @@ __global__ __launch_bounds__(kBlock) void k_gauge_force(const LT* links, int nli
         load(links, nlinks, link_at(g, b, mu), B);
         mat_mul<false, true>(A, B, C);
         load(links, nlinks, link_at(g, n, nu), A);
-        mat_mul<false, true>(C, A, B);
-        mat_add(S, B);
+        mat_mul<false, true, true>(C, A, S);
         // lower: U_nu(n+mu-nu)^dagger U_mu(n-nu)^dagger U_nu(n-nu)
         load(links, nlinks, link_at(g, d, nu), A);
         load(links, nlinks, link_at(g, c, mu), B);
         mat_mul<true, true>(A, B, C);
         load(links, nlinks, link_at(g, c, nu), A);
-        mat_mul<false, false>(C, A, B);
-        mat_add(S, B);
+        mat_mul<false, false, true>(C, A, S);
     }
     const int k = (2 * mu + par) * g.Vh + eo;
     load(links, nlinks, k, A);
@@ -327,7 +367,13 @@ static dim3 link_grid(const rhmc_gauge* g) {
 hipError_t launch_gauge_force_mom(const rhmc_gauge* g, double beta, double eps, double* mom,
                                   hipStream_t s) {
     const dim3 grid((unsigned)(8 * ((g->lat.Vh + kBlock - 1) / kBlock)));
-    RHMC_GAUGE_DISPATCH(k_gauge_force, grid, g->lat.geom, -beta / 3.0, eps, mom);
+    // z slabs: Lz / 8 planes (one slab per XCD) when that divides Lz, else the
+    // largest divisor of Lz below it (any divisor gives the same momenta)
+    const int Lz = g->lat.geom.Lz;
+    int sz = Lz / 8 > 0 ? Lz / 8 : 1;
+    while (Lz % sz) --sz;
+    RHMC_GAUGE_DISPATCH(k_gauge_force, grid, g->lat.geom, make_fastdiv((uint32_t)sz), -beta / 3.0,
+                        eps, mom);
     return hipGetLastError();
 }
 
