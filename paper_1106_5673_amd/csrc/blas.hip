@@ -134,20 +134,13 @@ __global__ __launch_bounds__(kBlock) void k_rupdate(VecArgs<VT> a) {
     const bool live = !st->sys[j].done;
     double r2 = 0.0;
     if (live) {
-        // alpha = rr / <p, A p> (<r, p> / <p, A p> right after a residual
-        // replacement); every block adds the A-kernel partials itself, in the
-        // same fixed order, so all blocks use the same alpha bits
-        block_sum_rows(a.part2 + (size_t)j * a.nblk2, 1, a.nblk2, sums);
-        const double pap = sums[0];
-        if (blockIdx.x == 0 && threadIdx.x == 0) st->sys[j].pap = pap;
-        const double alpha = step_alpha_num(st->sys[j], a.q) / pap;
         const VT* __restrict__ x = a.x[j];
         const VT* __restrict__ y = a.y[j];
         VT* __restrict__ z = a.z[j];
         const size_t stride = (size_t)gridDim.x * kBlock * 2;
-        for (size_t i0 = ((size_t)blockIdx.x * kBlock + threadIdx.x) * 2; i0 < a.n;
-             i0 += stride * kUnroll) {
-            Pair<VT> r[kUnroll], ap[kUnroll];
+        size_t i0 = ((size_t)blockIdx.x * kBlock + threadIdx.x) * 2;
+        Pair<VT> r[kUnroll], ap[kUnroll];
+        auto load_pass = [&]() {
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
                 const size_t i = i0 + u * stride;
@@ -156,6 +149,19 @@ __global__ __launch_bounds__(kBlock) void k_rupdate(VecArgs<VT> a) {
                     ap[u].load(y, i);
                 }
             }
+        };
+        // the first pass's loads do not depend on alpha: they go out before
+        // the block sums, so the two memory round trips overlap
+        load_pass();
+        // alpha = rr / <p, A p> (<r, p> / <p, A p> right after a residual
+        // replacement); every block adds the A-kernel partials itself, in the
+        // same fixed order, so all blocks use the same alpha bits
+        block_sum_rows<1>(a.part2 + (size_t)j * a.nblk2, 1, a.nblk2, sums);
+        const double pap = sums[0];
+        if (blockIdx.x == 0 && threadIdx.x == 0) st->sys[j].pap = pap;
+        const double alpha = step_alpha_num(st->sys[j], a.q) / pap;
+        for (bool first = true; i0 < a.n; i0 += stride * kUnroll, first = false) {
+            if (!first) load_pass();
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
                 const size_t i = i0 + u * stride;
@@ -199,14 +205,12 @@ __global__ __launch_bounds__(kBlock) void k_pupdate(VecArgs<VT> a) {
         return;
     }
     if (flags[1]) return;
-    block_sum_rows(a.partial + (size_t)j * a.nblk, 1, a.nblk, sums);
-    const double beta = sums[0] / st->sys[j].rr[a.q & 1];
     const VT* __restrict__ x = a.x[j];
     VT* __restrict__ y = a.y[j];
     const size_t stride = (size_t)(gridDim.x - 1) * kBlock * 2;
-    for (size_t i0 = ((size_t)(blockIdx.x - 1) * kBlock + threadIdx.x) * 2; i0 < a.n;
-         i0 += stride * kUnroll) {
-        Pair<VT> r[kUnroll], p[kUnroll];
+    size_t i0 = ((size_t)(blockIdx.x - 1) * kBlock + threadIdx.x) * 2;
+    Pair<VT> r[kUnroll], p[kUnroll];
+    auto load_pass = [&]() {
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
             const size_t i = i0 + u * stride;
@@ -215,6 +219,12 @@ __global__ __launch_bounds__(kBlock) void k_pupdate(VecArgs<VT> a) {
                 p[u].load(y, i);
             }
         }
+    };
+    load_pass();   // independent of beta: overlaps the block sums
+    block_sum_rows<1>(a.partial + (size_t)j * a.nblk, 1, a.nblk, sums);
+    const double beta = sums[0] / st->sys[j].rr[a.q & 1];
+    for (bool first = true; i0 < a.n; i0 += stride * kUnroll, first = false) {
+        if (!first) load_pass();
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
             const size_t i = i0 + u * stride;
@@ -244,20 +254,13 @@ __global__ __launch_bounds__(kBlock) void k_rupdate_pair(VecArgs<float2> a) {
     const bool live0 = !st->sys[j0].done, live1 = has1 && !st->sys[j1].done;
     double r2a = 0.0, r2b = 0.0;
     if (live0 || live1) {
-        block_sum_rows(a.part2 + (size_t)j0 * a.nblk2, has1 ? 2 : 1, a.nblk2, sums);
-        const double pap0 = sums[0], pap1 = has1 ? sums[1] : 1.0;
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            if (live0) st->sys[j0].pap = pap0;
-            if (live1) st->sys[j1].pap = pap1;
-        }
-        const double al0 = live0 ? step_alpha_num(st->sys[j0], a.q) / pap0 : 0.0;
-        const double al1 = live1 ? step_alpha_num(st->sys[j1], a.q) / pap1 : 0.0;
         const float4* __restrict__ x = reinterpret_cast<const float4*>(a.x[j0]);
         const float4* __restrict__ y = reinterpret_cast<const float4*>(a.y[j0]);
         float4* __restrict__ z = reinterpret_cast<float4*>(a.z[j0]);
         const size_t stride = (size_t)gridDim.x * kBlock;
-        for (size_t i0 = (size_t)blockIdx.x * kBlock + threadIdx.x; i0 < a.n; i0 += stride * kUnroll) {
-            float4 r[kUnroll], ap[kUnroll];
+        size_t i0 = (size_t)blockIdx.x * kBlock + threadIdx.x;
+        float4 r[kUnroll], ap[kUnroll];
+        auto load_pass = [&]() {
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
                 const size_t i = i0 + u * stride;
@@ -266,6 +269,18 @@ __global__ __launch_bounds__(kBlock) void k_rupdate_pair(VecArgs<float2> a) {
                     ap[u] = y[i];
                 }
             }
+        };
+        load_pass();   // independent of alpha: overlaps the block sums
+        block_sum_rows<2>(a.part2 + (size_t)j0 * a.nblk2, has1 ? 2 : 1, a.nblk2, sums);
+        const double pap0 = sums[0], pap1 = has1 ? sums[1] : 1.0;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            if (live0) st->sys[j0].pap = pap0;
+            if (live1) st->sys[j1].pap = pap1;
+        }
+        const double al0 = live0 ? step_alpha_num(st->sys[j0], a.q) / pap0 : 0.0;
+        const double al1 = live1 ? step_alpha_num(st->sys[j1], a.q) / pap1 : 0.0;
+        for (bool first = true; i0 < a.n; i0 += stride * kUnroll, first = false) {
+            if (!first) load_pass();
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
                 const size_t i = i0 + u * stride;
@@ -308,14 +323,12 @@ __global__ __launch_bounds__(kBlock) void k_pupdate_pair(VecArgs<float2> a) {
     }
     const bool live0 = !flags[1], live1 = !flags[2];
     if (!live0 && !live1) return;
-    block_sum_rows(a.partial + (size_t)j0 * a.nblk, has1 ? 2 : 1, a.nblk, sums);
-    const double beta0 = live0 ? sums[0] / st->sys[j0].rr[a.q & 1] : 0.0;
-    const double beta1 = live1 ? sums[1] / st->sys[j1].rr[a.q & 1] : 0.0;
     const float4* __restrict__ x = reinterpret_cast<const float4*>(a.x[j0]);
     float4* __restrict__ y = reinterpret_cast<float4*>(a.y[j0]);
     const size_t stride = (size_t)(gridDim.x - 1) * kBlock;
-    for (size_t i0 = (size_t)(blockIdx.x - 1) * kBlock + threadIdx.x; i0 < a.n; i0 += stride * kUnroll) {
-        float4 r[kUnroll], p[kUnroll];
+    size_t i0 = (size_t)(blockIdx.x - 1) * kBlock + threadIdx.x;
+    float4 r[kUnroll], p[kUnroll];
+    auto load_pass = [&]() {
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
             const size_t i = i0 + u * stride;
@@ -324,6 +337,13 @@ __global__ __launch_bounds__(kBlock) void k_pupdate_pair(VecArgs<float2> a) {
                 p[u] = y[i];
             }
         }
+    };
+    load_pass();   // independent of beta: overlaps the block sums
+    block_sum_rows<2>(a.partial + (size_t)j0 * a.nblk, has1 ? 2 : 1, a.nblk, sums);
+    const double beta0 = live0 ? sums[0] / st->sys[j0].rr[a.q & 1] : 0.0;
+    const double beta1 = live1 ? sums[1] / st->sys[j1].rr[a.q & 1] : 0.0;
+    for (bool first = true; i0 < a.n; i0 += stride * kUnroll, first = false) {
+        if (!first) load_pass();
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
             const size_t i = i0 + u * stride;

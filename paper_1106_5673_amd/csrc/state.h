@@ -129,20 +129,34 @@ __device__ inline double block_sum_partials(const double* partial, int r, int nb
 
 // Sum rows 0..nrows-1 of partial[r*nblk + b] over b for all rows in one pass
 // (fixed order: the same bits in every block that calls it); out[r] in shared
-// memory holds the sums on return.  nrows <= kMaxSys.
+// memory holds the sums on return.  nrows <= MAXR <= kMaxSys.  A thread adds
+// its entries b = tid, tid + blockDim, ... in that order; the loads of U of
+// them are issued together before they are added, so one memory round trip
+// serves U entries (the update kernels sum thousands of operator-block
+// partials per system; the many-row form keeps U = 1 for its registers).
+template <int MAXR = kMaxSys, int U = (MAXR <= 2 ? 8 : 1)>
 __device__ inline void block_sum_rows(const double* partial, int nrows, int nblk, double* out) {
-    __shared__ double wsum[kMaxSys][16];
-    double acc[kMaxSys];
+    __shared__ double wsum[MAXR][16];
+    double acc[MAXR];
 #pragma unroll
-    for (int r = 0; r < kMaxSys; ++r) acc[r] = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+    for (int r = 0; r < MAXR; ++r) acc[r] = 0.0;
+    const int bd = (int)blockDim.x;
+    for (int b = threadIdx.x; b < nblk; b += U * bd) {
+        double v[U][MAXR];
 #pragma unroll
-        for (int r = 0; r < kMaxSys; ++r)
-            if (r < nrows) acc[r] += partial[(size_t)r * nblk + b];
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int r = 0; r < MAXR; ++r)
+                v[u][r] = (r < nrows && b + u * bd < nblk) ? partial[(size_t)r * nblk + b + u * bd] : 0.0;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int r = 0; r < MAXR; ++r)
+                if (r < nrows && b + u * bd < nblk) acc[r] += v[u][r];
     }
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
-    for (int r = 0; r < kMaxSys; ++r) {
+    for (int r = 0; r < MAXR; ++r) {
         if (r < nrows) {
             double v = acc[r];
             for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
