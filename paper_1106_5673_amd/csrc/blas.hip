@@ -1,7 +1,8 @@
 // BLAS-1 kernels of the multi-shift CG (Sec. 4.3) and the rational combine
 // (Eq. system_r).  Each kernel streams one or more colour vectors once; the
-// ones that feed a CG scalar also emit one partial sum per block and let the
-// last block run the FP64 recurrences (state.h).
+// ones that feed a CG scalar also emit one partial sum per block, which the
+// blocks of the next kernel add up themselves (block 0 of the p-update runs
+// the FP64 recurrences, state.h).
 //
 // Vectors of a system are flat arrays of n = 3*Vh complex numbers; a thread
 // handles two consecutive complex numbers (one 16-byte load in FP32).
@@ -59,8 +60,9 @@ __device__ __forceinline__ void store_sys(const Pair<VT>& v, VT* p, size_t i, in
 }
 
 // Block-reduce up to two doubles and store them as partial[r*gridDim.x + bx]
-// (r0, r1 >= 0).  The sums are finished by a one-block finalize kernel: the
-// kernel boundary makes every partial visible, with no per-block fence.
+// (r0, r1 >= 0).  The sums are finished in a later kernel (the next update's
+// blocks or a one-block finalize): the kernel boundary makes every partial
+// visible, with no per-block fence.
 __device__ __forceinline__ void reduce_store(double v0, double v1, int r0, int r1,
                                              double* partial) {
     __shared__ double sm[2][kBlock / 64];
