@@ -617,6 +617,9 @@ def main():
         "mixed_phases": phases_entry(Vh, nrhs, len(rat.beta), K_mixed, st),
         "fp64_phases": phases_entry(Vh, nrhs, len(rat.beta), 32, st64),
         "mixed_vs_gpu_fp64_rel_error_per_shift": err_c5,
+        # launch variants the solver's tuner kept for the solves
+        "hop_variants": {"fp32": rhmc.rhmc_dslash_variant(g, rhmc.RHMC_PREC_FP32, nrhs),
+                         "fp64": rhmc.rhmc_dslash_variant(g, rhmc.RHMC_PREC_FP64, nrhs)},
         "note": ("mixed: mean wall time of the timed steps (mixed_batched) and median of the "
                  "per-step host times (mixed_batched_median); fp64: median of the listed runs after "
                  "one untimed run; speedup from the two medians; per-shift error = max over rhs of ||x_mixed - x_fp64|| / ||x_fp64|| "

@@ -87,26 +87,36 @@ rhmc_status tune_hop(rhmc_gauge* g, rhmc_prec prec, int nrhs, const void* in, vo
         err = time_variant(v, 2, 5, &ms);
         pass1.push_back({ms, v});
     }
-    int best_v = g->hop_variant[prec][cls];
+    const int cur_v = g->hop_variant[prec][cls];
+    int best_v = cur_v;
     if (err == hipSuccess) {
         std::sort(pass1.begin(), pass1.end());
-        const int nc = std::min<int>(8, (int)pass1.size());
+        // the fastest eight of the first pass, and the current variant (the
+        // measured default unless a caller pinned another): five back-to-back
+        // launches can misorder variants a few per cent apart
+        std::vector<int> cand;
+        for (int c = 0; c < std::min<int>(8, (int)pass1.size()); ++c) cand.push_back(pass1[c].second);
+        if (std::find(cand.begin(), cand.end(), cur_v) == cand.end()) cand.push_back(cur_v);
+        const int nc = (int)cand.size();
         std::vector<std::vector<float>> rounds(nc);
         for (int r = 0; r < 3 && err == hipSuccess; ++r)
             for (int c = 0; c < nc && err == hipSuccess; ++c) {
                 float ms = 0.f;
-                err = time_variant(pass1[c].second, 2, 10, &ms);
+                err = time_variant(cand[c], 2, 10, &ms);
                 rounds[c].push_back(ms);
             }
-        float best = 1e30f;
+        float best = 1e30f, cur = 1e30f;
         for (int c = 0; c < nc && err == hipSuccess; ++c) {
             std::sort(rounds[c].begin(), rounds[c].end());
             const float med = rounds[c][rounds[c].size() / 2];
+            if (cand[c] == cur_v) cur = med;
             if (med < best) {
                 best = med;
-                best_v = pass1[c].second;
+                best_v = cand[c];
             }
         }
+        // a variant replaces the current one only if it is more than 1% faster
+        if (err == hipSuccess && cur <= 1.01f * best) best_v = cur_v;
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
