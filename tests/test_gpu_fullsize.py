@@ -6,7 +6,12 @@ certified by properties that hold at any size:
   * the FP64 true residual ||b - (A + sigma_i) x_i|| / ||b|| <= tol, with A the
     oracle's operator for a sample of (rhs, shift) pairs and the library's FP64
     operator for all of them; the library's FP64 operator is itself compared
-    with the oracle's element by element on one full-size vector;
+    with the oracle's element by element on one full-size vector, and the
+    library's outputs A x_ri used for the residuals are tied to the oracle all
+    at once: sum_ri c_ri (A x_ri) from the library must equal the oracle's A
+    applied to sum_ri c_ri x_ri for random complex c_ri, so (by linearity) a
+    wrong output for any single pair fails with probability one, at the cost
+    of one oracle application;
   * the rational apply equals alpha0 b + sum alpha_i x_i of the separately
     returned shifted solutions, and r_{+1/4}(A) r_{-1/4}(A) b = b within the two
     approximation errors plus the solver tolerance.
@@ -51,18 +56,37 @@ def _workload(rh, cfg):
     return c, U, b, lat, g
 
 
-def _gpu_true_residuals(rh, g, m, shifts, b_dev, x_dev):
-    """||b - (A + s) x|| / ||b|| for every (rhs, shift) with the FP64 library operator."""
+def _gpu_true_residuals(rh, g, m, shifts, b_dev, x_dev, U=None):
+    """||b - (A + s) x|| / ||b|| for every (rhs, shift) with the FP64 library
+    operator.  With U, also checks sum c_ri (A x_ri) (library) against the
+    oracle's A (sum c_ri x_ri) for seeded random complex c_ri."""
     import torch
 
     nrhs, nshift = x_dev.shape[:2]
     out = torch.empty_like(x_dev[0])
     res = np.zeros((nrhs, nshift))
+    # weights c_ri = (standard complex normal) / max|x_ri|, so every pair counts
+    # alike; the two sides differ by rounding only, bounded element-wise by
+    # (about 100 operations per element of A v, on terms of at most 50 max|v|,
+    # both sides) 1e4 * eps * sum_ri |c_ri| max|x_ri|
+    rng = np.random.default_rng(4242)
+    c = rng.standard_normal((nrhs, nshift)) + 1j * rng.standard_normal((nrhs, nshift))
+    xmax = torch.amax(torch.abs(x_dev), dim=(2, 3)).cpu().numpy()
+    c = c / xmax
+    acc_ax = torch.zeros_like(x_dev[0, 0])
+    acc_x = torch.zeros_like(x_dev[0, 0])
     for r in range(nrhs):
         rh.rhmc_apply_mdagm(g, m, rh.RHMC_PREC_FP64, nshift, x_dev[r], out)
         for i, s in enumerate(shifts):
             d = b_dev[r] - out[i] - s * x_dev[r, i]
             res[r, i] = (torch.linalg.vector_norm(d) / torch.linalg.vector_norm(b_dev[r])).item()
+            acc_ax += complex(c[r, i]) * out[i]
+            acc_x += complex(c[r, i]) * x_dev[r, i]
+    if U is not None:
+        want = dirac.mdagm(U, m, acc_x.cpu().numpy())
+        got = acc_ax.cpu().numpy()
+        bound = 1e4 * np.finfo(np.float64).eps * float(np.sum(np.abs(c) * xmax))
+        assert np.abs(got - want).max() <= bound
     return res
 
 
@@ -150,7 +174,7 @@ def test_c4_fullsize_mixed_batched(rh):
     x = torch.empty((8, 15, 3, lat.Vh), dtype=torch.complex128, device="cuda:0")
     rh.rhmc_multishift_cg(g, m, r.beta, bd, x,
                           rh.solver_params(tol=tol, mode=rh.RHMC_MODE_MIXED, tune=1))
-    res = _gpu_true_residuals(rh, g, m, r.beta, bd, x)
+    res = _gpu_true_residuals(rh, g, m, r.beta, bd, x, U)
     assert res.max() <= tol * (1 + 1e-6)
     A = lambda v: dirac.mdagm(U, m, v)  # noqa: E731
     for (rr, i) in ((0, 0), (7, 14), (3, 7)):
@@ -194,6 +218,7 @@ def test_c5_fullsize_mixed_batched(rh):
     import torch
 
     c, U, b, lat, g = _workload(rh, 5)
+    U = np.asarray(U)
     m, tol = c["m"], c["tol"]
     r = rational_for(5, -0.25)
     bd = _dev(b)
@@ -201,7 +226,7 @@ def test_c5_fullsize_mixed_batched(rh):
     st = rh.rhmc_multishift_cg(g, m, r.beta, bd, x,
                                rh.solver_params(tol=tol, mode=rh.RHMC_MODE_MIXED, tune=1))
     assert st["max_true_residual"] <= tol
-    res = _gpu_true_residuals(rh, g, m, r.beta, bd, x)
+    res = _gpu_true_residuals(rh, g, m, r.beta, bd, x, U)
     assert res.max() <= tol * (1 + 1e-6)
     # the rational apply in the same configuration equals the combination
     y = torch.empty_like(bd)
@@ -214,7 +239,6 @@ def test_c5_fullsize_mixed_batched(rh):
     d = (torch.linalg.vector_norm(y - comb) / torch.linalg.vector_norm(comb)).item()
     assert d <= 1e-12
     # the oracle's operator on a sample, and the library's FP64 operator against it
-    U = np.asarray(U)
     A = lambda v: dirac.mdagm(U, m, v)  # noqa: E731
     for (rr, i) in ((0, 0), (2, 19)):
         xi = x[rr, i].cpu().numpy()
