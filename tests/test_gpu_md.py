@@ -102,7 +102,10 @@ def test_links_action_kinetic(rh, L, storage):
 
 
 @pytest.mark.parametrize("storage", STORAGES)
-@pytest.mark.parametrize("L", LATS + [(4, 6, 6, 4)])   # Lz % 4 != 0: the other site order
+# the kick's lane order takes z-slabs of Lz / 8 planes when that divides Lz,
+# else of the largest divisor below it: widths 1 (the first four), 3 (Lz = 24)
+# and 2 (Lz = 28, by the fallback)
+@pytest.mark.parametrize("L", LATS + [(4, 6, 6, 4), (4, 4, 24, 4), (4, 2, 28, 4)])
 def test_gauge_force_kick(rh, L, storage):
     U, lat, g = _setup(rh, L, storage, 7200 + sum(L), eps=0.7)
     beta, eps = 5.3, 0.37
