@@ -464,11 +464,13 @@ def main():
         return
 
     def time_dslash(prec, k, reps, gauge=None, vh=None, warm=20, flush=None):
-        """Median and min launch time of D_oe over `reps` launches, each
-        bracketed by its own pair of HIP events on the launching stream;
-        with `flush` (a device buffer) the buffer is streamed through a
-        reduction between launches, outside the events, so no cache holds the
-        operands."""
+        """Launch time of D_oe: the average over `reps` back-to-back launches
+        between one pair of HIP events on the launching stream (the timed
+        region), then the median and min of `reps` launches each bracketed by
+        its own pair of events (which adds the events' own few microseconds
+        to every sample).  With `flush` (a device buffer) the buffer is
+        streamed through a reduction between launches, outside the events, so
+        no cache holds the operands; there is no region average then."""
         gg = gauge if gauge is not None else g
         n = vh if vh is not None else Vh
         dt = torch.complex64 if prec == "fp32" else torch.complex128
@@ -485,6 +487,15 @@ def main():
         for _ in range(warm):
             rhmc.rhmc_dslash_eo(gg, 1, pr, k, vin, vout)
         s = torch.cuda.current_stream()
+        region = None
+        if flush is None:
+            r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            r0.record(s)
+            for _ in range(reps):
+                rhmc.rhmc_dslash_eo(gg, 1, pr, k, vin, vout)
+            r1.record(s)
+            r1.synchronize()
+            region = r0.elapsed_time(r1) / 1e3 / reps
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
         for e0, e1 in ev:
             if flush is not None:
@@ -494,10 +505,12 @@ def main():
             e1.record(s)
         ev[-1][1].synchronize()
         ts = sorted(e0.elapsed_time(e1) / 1e3 for e0, e1 in ev)
-        return ts[len(ts) // 2], ts[0]
+        return region, ts[len(ts) // 2], ts[0]
 
-    def dentry(t, tmin, nbytes, nsite, k):
-        return {"us_median": round(t * 1e6, 2), "us_min": round(tmin * 1e6, 2),
+    def dentry(tm, nbytes, nsite, k):
+        # tm = (region average, per-launch median, per-launch min); rates from the average
+        t, tmed, tmin = tm
+        return {"us_avg": round(t * 1e6, 2), "us_median": round(tmed * 1e6, 2), "us_min": round(tmin * 1e6, 2),
                 "GBps": round(nbytes / t / 1e9, 1), "hbm_frac": round(nbytes / t / 1e9 / HBM_PEAK_GBPS, 4),
                 "gflops": round(FLOPS_PER_SITE * nsite * k / t / 1e9, 1)}
 
@@ -508,12 +521,14 @@ def main():
     var64 = rhmc.rhmc_dslash_variant(g, rhmc.RHMC_PREC_FP64, nrhs)
     log(f"hopping launch variants: fp32 x{nrhs} {var32}, fp64 x{nrhs} {var64}")
     byts = dslash_bytes_per_site("fp32", nrhs) * Vh
-    avg, avg_min = time_dslash("fp32", nrhs, args.dslash_reps)
+    t32_4 = time_dslash("fp32", nrhs, args.dslash_reps)
+    avg, avg_med, avg_min = t32_4
     achieved = byts / avg / 1e9
     byts64_4 = dslash_bytes_per_site("fp64c", nrhs) * Vh
-    t64_4, t64_4_min = time_dslash("fp64", nrhs, args.dslash_reps)
-    log(f"hopping fp32-12 x{nrhs}: {avg * 1e6:.1f} us ({achieved:.0f} GB/s); "
-        f"fp64-12 x{nrhs}: {t64_4 * 1e6:.1f} us ({byts64_4 / t64_4 / 1e9:.0f} GB/s)")
+    t64_4 = time_dslash("fp64", nrhs, args.dslash_reps)
+    log(f"hopping fp32-12 x{nrhs}: {avg * 1e6:.1f} us ({achieved:.0f} GB/s; per-launch events: "
+        f"median {avg_med * 1e6:.1f} us); fp64-12 x{nrhs}: {t64_4[0] * 1e6:.1f} us "
+        f"({byts64_4 / t64_4[0] / 1e9:.0f} GB/s)")
     if args.only_dslash:
         time_dslash("fp32", 8, args.dslash_reps)
         log("hopping fp32-12 x8 timed")
@@ -526,22 +541,22 @@ def main():
         return
 
     dslash = {
-        f"fp32_12_{nrhs}rhs": dentry(avg, avg_min, byts, Vh, nrhs),
-        f"fp64_12_{nrhs}rhs": dentry(t64_4, t64_4_min, byts64_4, Vh, nrhs),
+        f"fp32_12_{nrhs}rhs": dentry(t32_4, byts, Vh, nrhs),
+        f"fp64_12_{nrhs}rhs": dentry(t64_4, byts64_4, Vh, nrhs),
     }
-    t8, t8_min = time_dslash("fp32", 8, args.dslash_reps)
-    dslash["fp32_12_8rhs"] = dentry(t8, t8_min, dslash_bytes_per_site("fp32", 8) * Vh, Vh, 8)
-    t1, t1_min = time_dslash("fp32", 1, args.dslash_reps)
-    dslash["fp32_12_1rhs"] = dentry(t1, t1_min, dslash_bytes_per_site("fp32", 1) * Vh, Vh, 1)
-    t641, t641_min = time_dslash("fp64", 1, args.dslash_reps)
-    dslash["fp64_12_1rhs"] = dentry(t641, t641_min, dslash_bytes_per_site("fp64c", 1) * Vh, Vh, 1)
+    t8 = time_dslash("fp32", 8, args.dslash_reps)
+    dslash["fp32_12_8rhs"] = dentry(t8, dslash_bytes_per_site("fp32", 8) * Vh, Vh, 8)
+    t1 = time_dslash("fp32", 1, args.dslash_reps)
+    dslash["fp32_12_1rhs"] = dentry(t1, dslash_bytes_per_site("fp32", 1) * Vh, Vh, 1)
+    t641 = time_dslash("fp64", 1, args.dslash_reps)
+    dslash["fp64_12_1rhs"] = dentry(t641, dslash_bytes_per_site("fp64c", 1) * Vh, Vh, 1)
     # the four-rhs launch with a 1 GiB buffer read between launches: no link
     # or vector can be served from the 256 MB Infinity Cache
     junk = torch.ones(1 << 28, dtype=torch.float32, device=dev)
-    avg_cold, avg_cold_min = time_dslash("fp32", nrhs, args.dslash_reps, flush=junk)
+    _, avg_cold, avg_cold_min = time_dslash("fp32", nrhs, args.dslash_reps, flush=junk)
     del junk
-    log(f"fp32-12 x8 {t8 * 1e6:.1f} us, x1 {t1 * 1e6:.1f} us; fp64-12 x1 {t641 * 1e6:.1f} us; "
-        f"fp32-12 x{nrhs} cold cache {avg_cold * 1e6:.1f} us")
+    log(f"fp32-12 x8 {t8[0] * 1e6:.1f} us, x1 {t1[0] * 1e6:.1f} us; fp64-12 x1 {t641[0] * 1e6:.1f} us; "
+        f"fp32-12 x{nrhs} cold cache {avg_cold * 1e6:.1f} us (per-launch median; warm: {avg_med * 1e6:.1f} us)")
 
     # ---------------------------------------------------------------- headline solves
     prm_mixed = rhmc.solver_params(tol=c["tol"], mode=rhmc.RHMC_MODE_MIXED, tune=1, block=args.block)
@@ -690,17 +705,17 @@ def main():
     # link storages other than the defaults, same lattice
     if not args.no_extras:
         ghl = rhmc.rhmc_gauge_create(lat, U, flags=rhmc.RHMC_LINKS_HILO_12)
-        thl, thl_min = time_dslash("fp64", 1, args.dslash_reps, gauge=ghl)
+        thl = time_dslash("fp64", 1, args.dslash_reps, gauge=ghl)
         ghl.close()
-        dslash["fp64_hilo12_1rhs"] = dentry(thl, thl_min, dslash_bytes_per_site("fp64hl", 1) * Vh, Vh, 1)
+        dslash["fp64_hilo12_1rhs"] = dentry(thl, dslash_bytes_per_site("fp64hl", 1) * Vh, Vh, 1)
         g18 = rhmc.rhmc_gauge_create(lat, U, flags=rhmc.RHMC_LINKS_FP64_18)
-        t18, t18_min = time_dslash("fp64", 1, args.dslash_reps, gauge=g18)
+        t18 = time_dslash("fp64", 1, args.dslash_reps, gauge=g18)
         g18.close()
-        dslash["fp64_18_1rhs"] = dentry(t18, t18_min, dslash_bytes_per_site("fp64", 1) * Vh, Vh, 1)
+        dslash["fp64_18_1rhs"] = dentry(t18, dslash_bytes_per_site("fp64", 1) * Vh, Vh, 1)
         gf = rhmc.rhmc_gauge_create(lat, U, flags=rhmc.RHMC_LINKS_FP32_18 | rhmc.RHMC_LINKS_FP64_12)
-        tf4, tf4_min = time_dslash("fp32", nrhs, args.dslash_reps, gauge=gf)
+        tf4 = time_dslash("fp32", nrhs, args.dslash_reps, gauge=gf)
         gf.close()
-        dslash[f"fp32_18_{nrhs}rhs"] = dentry(tf4, tf4_min, dslash_bytes_per_site("fp32f", nrhs) * Vh, Vh, nrhs)
+        dslash[f"fp32_18_{nrhs}rhs"] = dentry(tf4, dslash_bytes_per_site("fp32f", nrhs) * Vh, Vh, nrhs)
     traffic = traffic_from_profile(f"dslash_fp32_{nrhs}rhs_{'x'.join(str(v) for v in L)}", var32)
     g.close()
     np.save(os.path.join(workdir, "c5_links.npy"), U)
@@ -832,11 +847,15 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBPS, 4),
             "traffic": traffic,
             "kernel": f"hopping FP32 12-real, {nrhs} rhs, launch variant {var32}, {avg * 1e6:.2f} us per "
-                      f"launch (median of {args.dslash_reps}; min {avg_min * 1e6:.2f}), "
+                      f"launch (average of {args.dslash_reps} back-to-back launches between one pair of HIP "
+                      f"events on the launching stream; with per-launch events: median "
+                      f"{avg_med * 1e6:.2f}, min {avg_min * 1e6:.2f}), "
                       f"{byts / 1e6:.1f} MB algorithmic per launch",
             "cold_cache": {"us_median": round(avg_cold * 1e6, 2), "us_min": round(avg_cold_min * 1e6, 2),
                            "GBps": round(byts / avg_cold / 1e9, 1),
-                           "note": "a 1 GiB buffer read between launches (outside the events)"},
+                           "warm_us_median": round(avg_med * 1e6, 2),
+                           "note": "per-launch events with a 1 GiB buffer read between launches (outside "
+                                   "the events); compare with the warm per-launch median"},
             "gflops": round(FLOPS_PER_SITE * Vh * nrhs / avg / 1e9, 1),
         },
         "dslash": dslash,

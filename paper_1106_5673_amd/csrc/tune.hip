@@ -38,11 +38,22 @@ rhmc_status tune_hop(rhmc_gauge* g, rhmc_prec prec, int nrhs, const void* in, vo
                      hipStream_t s) {
     const int cls = nr_class(nrhs);
     const size_t n = (size_t)3 * g->lat.Vh;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    RHMC_HIP_TRY(hipEventCreate(&e0));
-    RHMC_HIP_TRY(hipEventCreate(&e1));
+    // each timed launch between its own pair of events: in a solve every
+    // hopping launch sits between other kernels, and back-to-back launches of
+    // one variant (each starting while the previous one's output stores
+    // drain) rank the variants differently
+    constexpr int kMaxReps = 10;
+    hipEvent_t ev[2 * kMaxReps] = {};
+    for (int i = 0; i < 2 * kMaxReps; ++i) {
+        const hipError_t ce = hipEventCreate(&ev[i]);
+        if (ce != hipSuccess) {
+            for (int k = 0; k < i; ++k) hipEventDestroy(ev[k]);
+            RHMC_HIP_TRY(ce);
+        }
+    }
     std::vector<std::pair<float, int>> pass1;
-    // time `reps` launches of variant v after `warm` untimed ones (ms per launch)
+    // median time of `reps` (<= kMaxReps) launches of variant v after `warm`
+    // untimed ones (ms per launch)
     auto time_variant = [&](int v, int warm, int reps, float* ms_out) -> hipError_t {
         hipError_t err = hipSuccess;
         auto launch = [&]() {
@@ -72,13 +83,18 @@ rhmc_status tune_hop(rhmc_gauge* g, rhmc_prec prec, int nrhs, const void* in, vo
             }
         };
         for (int w = 0; w < warm && err == hipSuccess; ++w) launch();
-        if (err == hipSuccess) err = hipEventRecord(e0, s);
-        for (int w = 0; w < reps && err == hipSuccess; ++w) launch();
-        if (err == hipSuccess) err = hipEventRecord(e1, s);
-        if (err == hipSuccess) err = hipEventSynchronize(e1);
-        float ms = 0.f;
-        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
-        *ms_out = ms / reps;
+        for (int w = 0; w < reps && err == hipSuccess; ++w) {
+            err = hipEventRecord(ev[2 * w], s);
+            if (err == hipSuccess) launch();
+            if (err == hipSuccess) err = hipEventRecord(ev[2 * w + 1], s);
+        }
+        if (err == hipSuccess) err = hipEventSynchronize(ev[2 * reps - 1]);
+        float t[kMaxReps];
+        for (int w = 0; w < reps && err == hipSuccess; ++w) err = hipEventElapsedTime(&t[w], ev[2 * w], ev[2 * w + 1]);
+        if (err == hipSuccess) {
+            std::sort(t, t + reps);
+            *ms_out = t[reps / 2];
+        }
         return err;
     };
     hipError_t err = hipSuccess;
@@ -92,8 +108,8 @@ rhmc_status tune_hop(rhmc_gauge* g, rhmc_prec prec, int nrhs, const void* in, vo
     if (err == hipSuccess) {
         std::sort(pass1.begin(), pass1.end());
         // the fastest eight of the first pass, and the current variant (the
-        // measured default unless a caller pinned another): five back-to-back
-        // launches can misorder variants a few per cent apart
+        // measured default unless a caller pinned another): five launches can
+        // misorder variants a few per cent apart
         std::vector<int> cand;
         for (int c = 0; c < std::min<int>(8, (int)pass1.size()); ++c) cand.push_back(pass1[c].second);
         if (std::find(cand.begin(), cand.end(), cur_v) == cand.end()) cand.push_back(cur_v);
@@ -118,8 +134,7 @@ rhmc_status tune_hop(rhmc_gauge* g, rhmc_prec prec, int nrhs, const void* in, vo
         // a variant replaces the current one only if it is more than 1% faster
         if (err == hipSuccess && cur <= 1.01f * best) best_v = cur_v;
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    for (int i = 0; i < 2 * kMaxReps; ++i) hipEventDestroy(ev[i]);
     RHMC_HIP_TRY(err);
     g->hop_variant[prec][cls] = best_v;
     g->hop_tuned[prec][cls] = 1;
