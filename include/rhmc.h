@@ -298,7 +298,7 @@ rhmc_status rhmc_pf_force(const rhmc_gauge* g, double m, const rhmc_rational* ra
  * every launch variant (site processing order, hops per load batch, rows staged
  * in LDS per block) of one application D_oe on the given vectors
  * and keeps the fastest for this precision and rhs count in the gauge object
- * (the current variant stays unless another is more than 1% faster in the
+ * (the current variant stays unless another is more than 3% faster in the
  * final interleaved rounds); later calls of every entry point use it.  in: device vector set of nrhs
  * even-site vectors (layout above); out: the same, overwritten.  Blocks until
  * timed.

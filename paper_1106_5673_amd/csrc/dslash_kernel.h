@@ -462,12 +462,14 @@ __global__ __launch_bounds__(STG ? 512 : kBlock) void k_dslash(const LT* __restr
                 for (int c = 0; c < 3; ++c)
                     stnt(out + c * Vh + eo, make_float4(ar[r0][c], ai[r0][c], ar[r1][c], ai[r1][c]));
             } else {
+                // the site's own p is read once here: non-temporal, so that it
+                // does not take L2 room from the neighbour reads
                 const float4* self = reinterpret_cast<const float4*>(a.self[r0]);
                 const RT c0 = (RT)a.c[r0], c1 = (RT)a.c[r1];
                 double d0 = 0.0, d1 = 0.0;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    const float4 pv = self[c * Vh + eo];
+                    const float4 pv = ldg<true>((gp<float4>)(self + c * Vh + eo));
                     float4 o;
                     o.x = c0 * pv.x - ar[r0][c];
                     o.y = c0 * pv.y - ai[r0][c];
@@ -500,7 +502,7 @@ __global__ __launch_bounds__(STG ? 512 : kBlock) void k_dslash(const LT* __restr
             double d = 0.0;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const VT pv = a.self[r][c * Vh + eo];
+                const VT pv = ldg<true>((gp<VT>)(a.self[r] + c * Vh + eo));
                 VT o;
                 o.x = cr * pv.x - ar[r][c];
                 o.y = cr * pv.y - ai[r][c];

@@ -131,8 +131,9 @@ rhmc_status tune_hop(rhmc_gauge* g, rhmc_prec prec, int nrhs, const void* in, vo
                 best_v = cand[c];
             }
         }
-        // a variant replaces the current one only if it is more than 1% faster
-        if (err == hipSuccess && cur <= 1.01f * best) best_v = cur_v;
+        // a variant replaces the current one only if it is more than 3% faster:
+        // tuned inside a solve, variants 1-2% apart swap places from run to run
+        if (err == hipSuccess && cur <= 1.03f * best) best_v = cur_v;
     }
     for (int i = 0; i < 2 * kMaxReps; ++i) hipEventDestroy(ev[i]);
     RHMC_HIP_TRY(err);
