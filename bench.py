@@ -562,8 +562,8 @@ def main():
     # The 48^3x12 solves use the library's default launch variants (tune = 0,
     # the library default), which come from timing every variant on this
     # lattice: tuning again inside a solve picks among variants a few per
-    # cent apart and moved the MIXED apply between 1.924 and 1.949 s from run
-    # to run.  The 32^3x8 workloads below tune (tune = 1).
+    # cent apart, differently from run to run.  The 32^3x8 workloads below
+    # tune (tune = 1).
     prm_mixed = rhmc.solver_params(tol=c["tol"], mode=rhmc.RHMC_MODE_MIXED, tune=0, block=args.block)
     prm_fp64 = rhmc.solver_params(tol=c["tol"], mode=rhmc.RHMC_MODE_FP64, tune=0)
 
